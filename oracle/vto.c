@@ -1,0 +1,571 @@
+/*
+ * vto.c -- CPU oracle for digital Voronoi, Laguerre and Johnson-Mehl
+ * diagrams, following Moulinec, arXiv 2201.13234.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg to check the device library.  No product
+ * code path may call it.  It shares nothing with the device library.
+ *
+ * Build: gcc -std=c99 -O2 -fopenmp -ffp-contract=off -fno-fast-math
+ *        (no -march flag, so no fused multiply-add can be emitted).
+ *
+ * Contents
+ *   - keys of Sec. 2 with the distances of App. A (eq. de, eq. dL);
+ *   - brute force (Alg. "simple Voronoi algorithm", Sec. 3.1);
+ *   - the two-step ball algorithm (Alg. faster_voronoi_algo, Sec. 3.2;
+ *     Alg. faster_jmak_algo, Sec. 3.3; the Laguerre variant, Sec. 3.4);
+ *   - the cost models that fix the ball size (eq. nstep12_3d, eq. v0_3d,
+ *     eq. nstep12_jmak with eq. v').
+ */
+#include "vto.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Geometry shared by every routine of this file                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int ndim, kind, periodic;
+    int64_t n[3];
+    double L[3];
+    double h[3];  /* voxel size L_a / n_a */
+    double H[3];  /* half period L_a / 2 */
+    double G;     /* Johnson-Mehl growth rate */
+    int64_t nvox;
+} geo_t;
+
+static void geo_init(geo_t* g, const vto_problem* p)
+{
+    int a;
+    memset(g, 0, sizeof *g);
+    g->ndim = p->ndim;
+    g->kind = p->kind;
+    g->periodic = p->periodic ? 1 : 0;
+    g->G = p->growth;
+    g->nvox = 1;
+    for (a = 0; a < 3; ++a) {
+        if (a < p->ndim) {
+            g->n[a] = p->n[a];
+            g->L[a] = p->L[a];
+            g->h[a] = p->L[a] / (double)p->n[a];
+            g->H[a] = 0.5 * p->L[a];
+        } else {
+            g->n[a] = 1;
+            g->L[a] = 1.0;
+            g->h[a] = 1.0;
+            g->H[a] = 0.5;
+        }
+        g->nvox *= g->n[a];
+    }
+}
+
+/* Centre of voxel i along an axis: the paper's x(k) (Sec. 3.1) read as the
+ * centre of the cell [i*h, (i+1)*h). */
+static double voxel_centre(const geo_t* g, int a, int64_t i)
+{
+    return ((double)i + 0.5) * g->h[a];
+}
+
+/* Signed coordinate difference s - x along axis a.  With periodic
+ * boundaries this is the minimum-image difference of App. A:
+ * y - x - N((y - x)/L) L with N(y) = floor(y + 1/2), the quotient taken
+ * exactly.  Because s and x lie in [0, L), |s - x| < L and the correction
+ * is a single subtraction or addition of L, which is exact (Sterbenz). */
+static double axis_delta(const geo_t* g, int a, double s, double x)
+{
+    double d = s - x;
+    if (g->periodic) {
+        if (d >= g->H[a])
+            d = d - g->L[a];
+        else if (d < -g->H[a])
+            d = d + g->L[a];
+    }
+    return d;
+}
+
+/* The key the diagram minimises at point x for site s (Sec. 2):
+ *   squared distance q = d0^2 + (d1^2 + d2^2)    (eq. de / eq. dL, squared)
+ *   Voronoi:      q                              (eq. Voronoi_Cell; the
+ *                                                 squared distance is allowed
+ *                                                 by the remark of Sec. 3.1)
+ *   Laguerre:     q - w_s                        (power distance, Sec. 2.3)
+ *   Johnson-Mehl: t_s + sqrt(q) / G              (eq. JMAK2)              */
+static double site_key(const geo_t* g, const double* s, double prm, const double* x)
+{
+    double q;
+    double d0 = axis_delta(g, 0, s[0], x[0]);
+    double d1 = axis_delta(g, 1, s[1], x[1]);
+    if (g->ndim == 3) {
+        double d2 = axis_delta(g, 2, s[2], x[2]);
+        q = d0 * d0 + (d1 * d1 + d2 * d2);
+    } else {
+        q = d0 * d0 + d1 * d1;
+    }
+    if (g->kind == VTO_LAGUERRE)
+        return q - prm;
+    if (g->kind == VTO_JOHNSON_MEHL)
+        return prm + sqrt(q) / g->G;
+    return q;
+}
+
+static int resolve_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+    return nthreads < 1 ? 1 : nthreads;
+}
+
+int vto_max_threads(void) { return resolve_threads(0); }
+
+/* ------------------------------------------------------------------------ */
+/* Validation                                                                */
+/* ------------------------------------------------------------------------ */
+
+int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
+                 const double* param)
+{
+    int a;
+    int64_t s;
+    if (!p || (p->ndim != 2 && p->ndim != 3))
+        return VTO_ERR_INVALID;
+    if (p->kind < VTO_VORONOI || p->kind > VTO_JOHNSON_MEHL)
+        return VTO_ERR_INVALID;
+    if (nsites < 1 || nsites > 2147483647LL || !coords)
+        return VTO_ERR_INVALID;
+    if (p->kind != VTO_VORONOI && !param)
+        return VTO_ERR_INVALID;
+    if (p->kind == VTO_JOHNSON_MEHL && !(isfinite(p->growth) && p->growth > 0.0))
+        return VTO_ERR_INVALID;
+    for (a = 0; a < p->ndim; ++a) {
+        if (p->n[a] < 1 || p->n[a] > 2147483647LL)
+            return VTO_ERR_INVALID;
+        if (!(isfinite(p->L[a]) && p->L[a] > 0.0))
+            return VTO_ERR_INVALID;
+    }
+    for (s = 0; s < nsites; ++s) {
+        for (a = 0; a < p->ndim; ++a) {
+            double c = coords[s * p->ndim + a];
+            if (!(c >= 0.0 && c < p->L[a]))
+                return VTO_ERR_INPUT;
+        }
+        if (p->kind != VTO_VORONOI && !isfinite(param[s]))
+            return VTO_ERR_INPUT;
+    }
+    return VTO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cost models (Sec. 3.2.3, 3.3.2, 3.4)                                      */
+/* ------------------------------------------------------------------------ */
+
+static double unit_ball_volume(int d)
+{
+    /* omega_d = pi^(d/2) / Gamma(d/2 + 1) */
+    const double pi = 3.14159265358979323846;
+    return pow(pi, 0.5 * d) / tgamma(0.5 * d + 1.0);
+}
+
+static double domain_volume(const vto_problem* p)
+{
+    double V = 1.0;
+    int a;
+    for (a = 0; a < p->ndim; ++a)
+        V *= p->L[a];
+    return V;
+}
+
+static double sum_sq_lengths(const vto_problem* p)
+{
+    double S = 0.0;
+    int a;
+    for (a = 0; a < p->ndim; ++a)
+        S += p->L[a] * p->L[a];
+    return S;
+}
+
+double vto_v0_fraction(int64_t nsites)
+{
+    /* eq. v0_3d: v0 / V = 1 - (1/N_s)^(1/(N_s - 1)) */
+    double N = (double)nsites;
+    if (nsites <= 1)
+        return 1.0;
+    return 1.0 - pow(1.0 / N, 1.0 / (N - 1.0));
+}
+
+/* Volume of the ball of site s at level tau (the "investigation ball"):
+ *   Voronoi      radius r0 = sqrt(tau)
+ *   Johnson-Mehl radius r_s = G (t0 - t_s)^+          (eq. rs JM, tau = t0)
+ *   Laguerre     radius r_s = sqrt(G (t0 - t_s)^+)    (eq. rs Laguerre),
+ *                written with w_s = -G t_s and tau = G t0 as
+ *                r_s^2 = (tau + w_s)^+                                    */
+static double ball_radius(const vto_problem* p, double prm, double tau)
+{
+    if (p->kind == VTO_VORONOI)
+        return tau > 0.0 ? sqrt(tau) : 0.0;
+    if (p->kind == VTO_LAGUERRE) {
+        double r2 = tau + prm;
+        return r2 > 0.0 ? sqrt(r2) : 0.0;
+    }
+    {
+        double dt = tau - prm;
+        return dt > 0.0 ? p->growth * dt : 0.0;
+    }
+}
+
+double vto_cost_model(const vto_problem* p, int64_t nsites, const double* param,
+                      double tau)
+{
+    double V = domain_volume(p);
+    double Nv = 1.0, Ns = (double)nsites;
+    double wd = unit_ball_volume(p->ndim);
+    int a;
+    for (a = 0; a < p->ndim; ++a)
+        Nv *= (double)p->n[a];
+    if (p->kind == VTO_VORONOI) {
+        /* eq. nstep12_3d with v'_s = v0 (eq. nstep1b):
+         * E = N_s N_v (v0/V + (1 - v0/V)^N_s) */
+        double r = tau > 0.0 ? sqrt(tau) : 0.0;
+        double f = wd * pow(r, p->ndim) / V;
+        if (f > 1.0)
+            f = 1.0;
+        return Ns * Nv * (f + pow(1.0 - f, Ns));
+    } else {
+        /* eq. nstep12_jmak: E = N_v sum_s v'_s/V + N_s N_v prod_s (1 - v'_s/V)
+         * with v'_s = min(V, v_s) (eq. v'); the product is taken as the
+         * exponential of a sum of logarithms so that it does not underflow. */
+        double step1 = 0.0, logp = 0.0;
+        int64_t s;
+        for (s = 0; s < nsites; ++s) {
+            double r = ball_radius(p, param[s], tau);
+            double f = wd * pow(r, p->ndim) / V;
+            if (f > 1.0)
+                f = 1.0;
+            step1 += f;
+            logp += (f >= 1.0) ? -INFINITY : log1p(-f);
+        }
+        return Nv * step1 + Ns * Nv * exp(logp);
+    }
+}
+
+double vto_choose_tau(const vto_problem* p, int64_t nsites, const double* param)
+{
+    double lo, hi, span;
+    int it;
+    if (nsites <= 1)
+        return INFINITY; /* eq. v0_3d divides by N_s - 1 = 0: one ball covers everything */
+    if (p->kind == VTO_VORONOI) {
+        /* eq. v0_3d, then v0 = omega_d r0^d */
+        double v0 = vto_v0_fraction(nsites) * domain_volume(p);
+        double r0 = pow(v0 / unit_ball_volume(p->ndim), 1.0 / p->ndim);
+        return r0 * r0;
+    }
+    if (p->kind == VTO_JOHNSON_MEHL) {
+        /* Sec. 3.3.2: t0 lies in [min t, min t + sqrt(sum L^2)/(2G)]
+         * (periodic) or [min t, min t + sqrt(sum L^2)/G] (non-periodic). */
+        double tmin = param[0];
+        int64_t s;
+        for (s = 1; s < nsites; ++s)
+            if (param[s] < tmin)
+                tmin = param[s];
+        span = sqrt(sum_sq_lengths(p)) / p->growth;
+        if (p->periodic)
+            span *= 0.5;
+        lo = tmin;
+        hi = tmin + span;
+    } else {
+        /* Sec. 3.4: t0 in [min t, min t + sum L^2/(4G)] (periodic) or
+         * [min t, min t + sum L^2/G] (non-periodic); with G t_s = -w_s and
+         * tau = G t0 this is tau in [-max w, -max w + sum L^2 / 4] or
+         * [-max w, -max w + sum L^2]. */
+        double wmax = param[0];
+        int64_t s;
+        for (s = 1; s < nsites; ++s)
+            if (param[s] > wmax)
+                wmax = param[s];
+        span = sum_sq_lengths(p);
+        if (p->periodic)
+            span *= 0.25;
+        lo = -wmax;
+        hi = -wmax + span;
+    }
+    /* Dichotomy on the slope of the cost model (Sec. 3.3.2 asks for "a
+     * dichotomy method"): compare the model just left and right of the
+     * midpoint and keep the half that holds the smaller value. */
+    for (it = 0; it < 80; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double eps = (hi - lo) * 1e-4;
+        double fl = vto_cost_model(p, nsites, param, mid - eps);
+        double fr = vto_cost_model(p, nsites, param, mid + eps);
+        if (fl <= fr)
+            hi = mid + eps;
+        else
+            lo = mid - eps;
+        if (!(hi - lo > 1e-12 * (fabs(lo) + fabs(hi) + 1e-300)))
+            break;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brute force (Alg. simple Voronoi algorithm, Sec. 3.1)                     */
+/* ------------------------------------------------------------------------ */
+
+/* Brute force at one voxel: every site in ascending order, strict "<". */
+static void brute_voxel(const geo_t* g, int64_t nsites, const double* coords,
+                        const double* param, const double* x, int32_t* lab,
+                        double* key)
+{
+    double D = INFINITY;
+    int32_t I = -1;
+    int64_t s;
+    for (s = 0; s < nsites; ++s) {
+        double k = site_key(g, coords + s * g->ndim, param ? param[s] : 0.0, x);
+        if (k < D) {
+            D = k;
+            I = (int32_t)s;
+        }
+    }
+    *lab = I;
+    *key = D;
+}
+
+static void voxel_point(const geo_t* g, int64_t lin, double* x)
+{
+    int64_t i0 = lin % g->n[0];
+    int64_t r = lin / g->n[0];
+    int64_t i1 = r % g->n[1];
+    int64_t i2 = r / g->n[1];
+    x[0] = voxel_centre(g, 0, i0);
+    x[1] = voxel_centre(g, 1, i1);
+    x[2] = (g->ndim == 3) ? voxel_centre(g, 2, i2) : 0.0;
+}
+
+int vto_brute(const vto_problem* p, int64_t nsites, const double* coords,
+              const double* param, int nthreads, int32_t* labels, double* keys_out)
+{
+    geo_t g;
+    int64_t v;
+    int rc = vto_validate(p, nsites, coords, param);
+    if (rc != VTO_OK)
+        return rc;
+    if (!labels)
+        return VTO_ERR_INVALID;
+    geo_init(&g, p);
+    nthreads = resolve_threads(nthreads);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (v = 0; v < g.nvox; ++v) {
+        double x[3], k;
+        int32_t l;
+        voxel_point(&g, v, x);
+        brute_voxel(&g, nsites, coords, param, x, &l, &k);
+        labels[v] = l;
+        if (keys_out)
+            keys_out[v] = k;
+    }
+    return VTO_OK;
+}
+
+int vto_label_points(const vto_problem* p, int64_t nsites, const double* coords,
+                     const double* param, int64_t npts, const int64_t* vox,
+                     int nthreads, int32_t* labels, double* keys_out)
+{
+    geo_t g;
+    int64_t i;
+    int rc = vto_validate(p, nsites, coords, param);
+    if (rc != VTO_OK)
+        return rc;
+    if (npts < 0 || (npts > 0 && (!vox || !labels)))
+        return VTO_ERR_INVALID;
+    geo_init(&g, p);
+    for (i = 0; i < npts; ++i) {
+        int a;
+        for (a = 0; a < p->ndim; ++a)
+            if (vox[3 * i + a] < 0 || vox[3 * i + a] >= g.n[a])
+                return VTO_ERR_INVALID;
+    }
+    nthreads = resolve_threads(nthreads);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (i = 0; i < npts; ++i) {
+        double x[3], k;
+        int32_t l;
+        x[0] = voxel_centre(&g, 0, vox[3 * i + 0]);
+        x[1] = voxel_centre(&g, 1, vox[3 * i + 1]);
+        x[2] = (g.ndim == 3) ? voxel_centre(&g, 2, vox[3 * i + 2]) : 0.0;
+        brute_voxel(&g, nsites, coords, param, x, &l, &k);
+        labels[i] = l;
+        if (keys_out)
+            keys_out[i] = k;
+    }
+    return VTO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Two-step ball algorithm (Sec. 3.2.2, 3.3.1, 3.4)                          */
+/* ------------------------------------------------------------------------ */
+
+/* Voxel indices along axis a whose centres may lie within distance R of
+ * coordinate s: a conservative index box, one voxel wider on each side than
+ * the ball so that rounding of the key cannot leave a member outside.
+ * Writes the (wrapped, in periodic mode) indices to out and returns their
+ * count.  Ball membership itself is decided later by the key. */
+static int64_t axis_box(const geo_t* g, int a, double s, double R, int64_t* out)
+{
+    int64_t n = g->n[a], lo, hi, i, cnt = 0;
+    if (a >= g->ndim) {
+        out[0] = 0;
+        return 1;
+    }
+    if (!(R < 2.0 * g->L[a])) {
+        for (i = 0; i < n; ++i)
+            out[i] = i;
+        return n;
+    }
+    lo = (int64_t)floor((s - R) / g->h[a] - 0.5) - 1;
+    hi = (int64_t)ceil((s + R) / g->h[a] - 0.5) + 1;
+    if (g->periodic) {
+        if (hi - lo + 1 >= n) {
+            for (i = 0; i < n; ++i)
+                out[i] = i;
+            return n;
+        }
+        for (i = lo; i <= hi; ++i)
+            out[cnt++] = ((i % n) + n) % n;
+        return cnt;
+    }
+    if (lo < 0)
+        lo = 0;
+    if (hi > n - 1)
+        hi = n - 1;
+    for (i = lo; i <= hi; ++i)
+        out[cnt++] = i;
+    return cnt;
+}
+
+int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
+                   const double* param, double tau, int nthreads,
+                   int32_t* labels, double* keys_out, vto_stats* stats)
+{
+    geo_t g;
+    double* D;
+    int64_t n_step1 = 0, n_box = 0, n_out = 0;
+    int outer, rc, failed = 0;
+    rc = vto_validate(p, nsites, coords, param);
+    if (rc != VTO_OK)
+        return rc;
+    if (!labels)
+        return VTO_ERR_INVALID;
+    geo_init(&g, p);
+    outer = g.ndim - 1; /* threads own slabs along the slowest axis */
+    nthreads = resolve_threads(nthreads);
+
+    /* Initialisation: the level tau (eq. v0_3d or the t0 search), D = inf. */
+    if (isnan(tau))
+        tau = vto_choose_tau(p, nsites, param);
+    D = keys_out ? keys_out : (double*)malloc((size_t)g.nvox * sizeof(double));
+    if (!D)
+        return VTO_ERR_NOMEM;
+
+#pragma omp parallel num_threads(nthreads) reduction(+ : n_step1, n_box, n_out)
+    {
+        int T = 1, t = 0;
+        int64_t o0, o1, v, s;
+        int64_t *ix, *iy, *iz;
+#ifdef _OPENMP
+        T = omp_get_num_threads();
+        t = omp_get_thread_num();
+#endif
+        o0 = g.n[outer] * t / T;
+        o1 = g.n[outer] * (t + 1) / T;
+        ix = (int64_t*)malloc((size_t)(g.n[0] + g.n[1] + g.n[2]) * sizeof(int64_t));
+        if (!ix) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+            int64_t plane = g.n[0] * (outer == 2 ? g.n[1] : 1);
+            iy = ix + g.n[0];
+            iz = iy + g.n[1];
+            for (v = o0 * plane; v < o1 * plane; ++v) {
+                D[v] = INFINITY;
+                labels[v] = -1;
+            }
+
+            /* Step 1: for s = 1..N_s, every voxel of the ball of s takes s if
+             * its key is strictly below D. */
+            for (s = 0; s < nsites; ++s) {
+                const double* sp = coords + s * g.ndim;
+                double prm = param ? param[s] : 0.0;
+                double R = ball_radius(p, prm, tau);
+                int64_t nx, ny, nz, a, b, c;
+                if (tau == -INFINITY)
+                    break;
+                if (p->kind == VTO_VORONOI && !(tau >= 0.0))
+                    break;
+                if (p->kind == VTO_LAGUERRE && !(tau + prm >= 0.0))
+                    continue;
+                if (p->kind == VTO_JOHNSON_MEHL && !(tau >= prm))
+                    continue;
+                nx = axis_box(&g, 0, sp[0], R, ix);
+                ny = axis_box(&g, 1, sp[1], R, iy);
+                nz = axis_box(&g, 2, g.ndim == 3 ? sp[2] : 0.0, R, iz);
+                for (c = 0; c < nz; ++c) {
+                    for (b = 0; b < ny; ++b) {
+                        int64_t jo = (outer == 2) ? iz[c] : iy[b];
+                        double x[3];
+                        if (jo < o0 || jo >= o1)
+                            continue;
+                        x[1] = voxel_centre(&g, 1, iy[b]);
+                        x[2] = (g.ndim == 3) ? voxel_centre(&g, 2, iz[c]) : 0.0;
+                        for (a = 0; a < nx; ++a) {
+                            int64_t lin = ix[a] + g.n[0] * (iy[b] + g.n[1] * iz[c]);
+                            double k;
+                            x[0] = voxel_centre(&g, 0, ix[a]);
+                            k = site_key(&g, sp, prm, x);
+                            ++n_box;
+                            if (k <= tau) { /* the voxel is inside the ball */
+                                ++n_step1;
+                                if (k < D[lin]) {
+                                    D[lin] = k;
+                                    labels[lin] = (int32_t)s;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+
+            /* Step 2: voxels outside every ball go through the brute-force
+             * loop. */
+            for (v = o0 * plane; v < o1 * plane; ++v) {
+                if (labels[v] == -1) {
+                    double x[3];
+                    ++n_out;
+                    voxel_point(&g, v, x);
+                    brute_voxel(&g, nsites, coords, param, x, &labels[v], &D[v]);
+                }
+            }
+            free(ix);
+        }
+    }
+    if (!keys_out)
+        free(D);
+    if (failed)
+        return VTO_ERR_NOMEM;
+    if (stats) {
+        stats->tau = tau;
+        stats->n_step1 = n_step1;
+        stats->n_box = n_box;
+        stats->n_out = n_out;
+        stats->n_step2 = n_out * nsites;
+    }
+    return VTO_OK;
+}
