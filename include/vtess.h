@@ -1,0 +1,148 @@
+/*
+ * vtess.h -- C ABI of the MI355X library that computes digital images of
+ * Voronoi, Laguerre and Johnson-Mehl diagrams (Moulinec, arXiv 2201.13234).
+ *
+ * Problem (Sec. 3, list at the top of the section): a regular grid of
+ * n_0 x n_1 [x n_2] voxels covers the box Omega = [0,L_0) x [0,L_1) [x [0,L_2)].
+ * Every voxel gets the 0-based index of the site that minimises, at the
+ * voxel centre x_a = (i_a + 1/2) * L_a / n_a,
+ *   Voronoi       q                 (squared distance; cells of eq. Voronoi_Cell)
+ *   Laguerre      q - w_s           (power distance of Sec. 2.3, w_s = r_s^2)
+ *   Johnson-Mehl  t_s + sqrt(q) / v (arrival time of eq. JMAK2, growth rate v)
+ * where q is the squared Euclidean distance (App. A, eq. de) or, with periodic
+ * boundaries, the squared L-periodic distance (App. A, eq. dL).  The result is
+ * bit-identical to brute force in IEEE binary64 with
+ *   d_a = s_a - x_a, minimum image d_a -= L_a if d_a >= L_a/2,
+ *   d_a += L_a if d_a < -L_a/2, q = d0*d0 + (d1*d1 + d2*d2) (3D) or
+ *   d0*d0 + d1*d1 (2D), every operation rounded once (no fused multiply-add),
+ * and ties go to the lowest site index (the paper's strict '<' over sites in
+ * ascending order, Alg. "simple Voronoi algorithm").
+ *
+ * Conventions
+ *  - All device work is asynchronous on the caller's HIP stream (passed as
+ *    void*, a hipStream_t; NULL is the default stream).
+ *  - Device pointers: coords, param, labels and status arrays are device
+ *    memory owned by the caller, who keeps them alive until the stream has
+ *    completed the call.  The library owns its scratch and vt_bins objects.
+ *  - Errors are return codes; nothing is thrown across the ABI.  Errors in
+ *    scalars are reported before any launch.  Bad coordinates or parameters
+ *    are found on the device: that job's labels become -1 and its status word
+ *    (if given) becomes VT_ERR_INPUT once the stream has run the call.
+ *  - Threading: a vt_ctx is used by one host thread at a time.
+ */
+#ifndef VTESS_H
+#define VTESS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { VT_VORONOI = 0, VT_LAGUERRE = 1, VT_JOHNSON_MEHL = 2 } vt_kind;
+typedef enum { VT_NONPERIODIC = 0, VT_PERIODIC = 1 } vt_bc;
+typedef enum {
+    VT_OK = 0,
+    VT_ERR_INVALID = 1, /* bad scalar argument (dims, lengths, growth, null pointer) */
+    VT_ERR_NOMEM = 2,   /* device or host allocation failed */
+    VT_ERR_HIP = 3,     /* a HIP runtime call failed (see vt_last_error) */
+    VT_ERR_BUSY = 4,    /* resource limit of the call exceeded (e.g. batch too large) */
+    VT_ERR_INPUT = 5    /* bad site coordinates or parameters, found on the device */
+} vt_status;
+
+typedef struct vt_ctx vt_ctx;   /* device, scratch pool, tuning table */
+typedef struct vt_bins vt_bins; /* one job's sites binned on the device */
+
+/* One diagram to label (problem statement of Sec. 3). */
+typedef struct {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t kind;        /* vt_kind */
+    int32_t bc;          /* vt_bc */
+    int32_t reserved;    /* must be 0 */
+    int64_t n[3];        /* voxels per axis, axis 0 fastest in memory; n[2] ignored in 2D */
+    double  L[3];        /* domain lengths > 0; L[2] ignored in 2D */
+    double  growth;      /* Johnson-Mehl growth rate v > 0 (G of eq. JMAK2); ignored otherwise */
+    int64_t nsites;      /* 1 .. 2^31 - 1 */
+    const double* coords;/* device, [nsites][ndim] binary64, each in [0, L_a) */
+    const double* param; /* device, [nsites]: Laguerre w_s, Johnson-Mehl t_s; NULL for Voronoi */
+    int32_t* labels;     /* device, prod(n) int32 written by the call (x fastest) */
+} vt_job;
+
+/* Creates a context on HIP device `device`.  Reads a tuning cache from the
+ * file named by the environment variable VT_TUNE_CACHE if it is set. */
+vt_status vt_create(int device, vt_ctx** out);
+void vt_destroy(vt_ctx* ctx);
+
+/* Plain single-diagram path: bins the sites (counting sort into a uniform
+ * bin grid) and labels every voxel.  status_dev (nullable): one device int32,
+ * set to VT_OK or VT_ERR_INPUT by the kernels.  May grow the context's
+ * scratch, which synchronises the device. */
+vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
+
+/* Many diagrams, of any sizes, kinds and boundaries: one segmented binning
+ * pass and one persistent labelling launch over all of them.  status_dev
+ * (nullable): njobs device int32, one per job.  A job with bad sites gets -1
+ * labels and VT_ERR_INPUT without affecting the others. */
+vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs,
+                              int32_t* status_dev, void* stream);
+
+/* Bins one job's sites into device memory owned by the returned object,
+ * which stays resident until vt_bins_free.  The job's coords/param buffers
+ * are read only by this call; labels is kept as the output buffer of later
+ * vt_label_batch calls.  status_dev (nullable) as for vt_tessellate. */
+vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out,
+                        int32_t* status_dev, void* stream);
+
+/* Labels the jobs behind n resident bin objects in one persistent launch,
+ * writing each into the labels buffer given at vt_bins_build.  status_dev
+ * (nullable): n device int32 (VT_ERR_INPUT for jobs whose binning flagged bad
+ * input, else VT_OK). */
+vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n,
+                         int32_t* status_dev, void* stream);
+
+/* Releases a bin object after the work queued on `stream` that uses it. */
+vt_status vt_bins_free(vt_ctx* ctx, vt_bins* bins, void* stream);
+
+/* Times the candidate tile shapes and bin sizes on the sample jobs (their
+ * label buffers are overwritten), keeps the fastest per job class in the
+ * context and, if cache_path is not NULL, writes them there as JSON.
+ * Synchronous. */
+vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char* cache_path);
+
+/* Loads a tuning cache written by vt_autotune. */
+vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path);
+
+/* Forces the tile configuration and bin-size factor of later calls
+ * (tile_cfg < 0 and bin_factor <= 0 restore the tuned/default choice).
+ * Tile configurations: 3D 0 = 8x8x8, 1 = 16x8x4, 2 = 32x4x4;
+ * 2D 0 = 32x16, 1 = 16x32, 2 = 64x8 (voxels, x first). */
+vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor);
+
+/* Bins per axis and tile configuration the next call would use for job. */
+vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3,
+                  int32_t* tile_cfg, double* bin_factor);
+
+/* Device-numerics probe: sqrt_out[i] = sqrt(x[i]) and div_out[i] = x[i] / den[i]
+ * computed by the same binary64 operations the labelling kernels use, so that
+ * a test can check them against correctly rounded host results (the keys of
+ * eq. JMAK2 need an IEEE square root and division).  All four arrays are
+ * device memory of n doubles. */
+vt_status vt_numerics_probe(vt_ctx* ctx, const double* x, const double* den, double* sqrt_out,
+                            double* div_out, int64_t n, void* stream);
+
+/* Phase timing of the plain path, for benchmarks.  While enabled, every
+ * vt_tessellate call records three HIP events on its own stream: before the
+ * binning kernels, before the labelling kernel and after it.  vt_profile_read
+ * waits for the recorded events, returns the summed milliseconds of the two
+ * phases and the number of calls recorded, and clears the record. */
+vt_status vt_profile_enable(vt_ctx* ctx, int32_t enable);
+vt_status vt_profile_read(vt_ctx* ctx, double* bin_ms, double* label_ms, int64_t* calls);
+
+const char* vt_status_string(vt_status s);
+/* Detail text of the last error of the calling thread. */
+const char* vt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VTESS_H */

@@ -1,0 +1,825 @@
+// api.hip -- host side of the C ABI declared in include/vtess.h: argument
+// checks, planning (bin grid, tile grid), scratch ownership, launch
+// sequencing, the resident-bins objects used by the serving loop, and the
+// autotuner with its JSON cache.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vt_internal.h"
+#include "vtess.h"
+
+using vt::JobDev;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+vt_status fail(vt_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+vt_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(VT_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define VT_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess)                          \
+            return hip_fail(e_, #call);                \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves sub-arrays out of one allocation.
+struct Carver {
+    size_t off = 0;
+    template <class T>
+    size_t take(int64_t count, size_t align = 256)
+    {
+        off = align_up(off, align);
+        size_t at = off;
+        off += (size_t)std::max<int64_t>(count, 0) * sizeof(T);
+        return at;
+    }
+};
+
+struct TuneEntry {
+    int ndim, kind, bc, size_cls, dens_cls;
+    int cfg;
+    double bin_factor;
+    double ms;
+};
+
+int size_class(int64_t nvox) { return (int)std::floor(std::log2((double)std::max<int64_t>(nvox, 1)) / 2.0); }
+int dens_class(int64_t nvox, int64_t ns)
+{
+    return (int)std::floor(std::log2((double)std::max<int64_t>(nvox, 1) / (double)std::max<int64_t>(ns, 1)));
+}
+
+}  // namespace
+
+struct vt_ctx {
+    int device = 0;
+    // scratch of the plain path and of batch binning
+    void* scratch = nullptr;
+    size_t scratch_cap = 0;
+    // pinned staging for job tables; the event marks the last copy out of it
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t staging_evt = nullptr;
+    bool staging_used = false;
+    int force_cfg = -1;
+    double force_bin = 0.0;
+    std::vector<TuneEntry> tune;
+    int batch_grid = 0;
+    // phase timing: three events per recorded call
+    bool profile = false;
+    std::vector<hipEvent_t> prof_events;
+    size_t prof_used = 0;
+};
+
+struct vt_bins {
+    JobDev job;
+    void* mem = nullptr;
+};
+
+namespace {
+
+bool is_pow2_scale(double v)
+{
+    int e = 0;
+    double m = std::frexp(v, &e);
+    return m == 0.5 && e >= -60 && e <= 60;
+}
+
+const TuneEntry* find_tune(const vt_ctx* ctx, const vt_job* j, int64_t nvox)
+{
+    const int sc = size_class(nvox), dc = dens_class(nvox, j->nsites);
+    for (const TuneEntry& t : ctx->tune)
+        if (t.ndim == j->ndim && t.kind == j->kind && t.bc == (j->bc ? 1 : 0) && t.size_cls == sc &&
+            t.dens_cls == dc)
+            return &t;
+    return nullptr;
+}
+
+// Checks the scalars of a job and fills the geometry of its device record.
+vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d, bool batch)
+{
+    if (!j)
+        return fail(VT_ERR_INVALID, "job is NULL");
+    if (j->ndim != 2 && j->ndim != 3)
+        return fail(VT_ERR_INVALID, "ndim must be 2 or 3");
+    if (j->kind < VT_VORONOI || j->kind > VT_JOHNSON_MEHL)
+        return fail(VT_ERR_INVALID, "unknown diagram kind");
+    if (j->bc != VT_NONPERIODIC && j->bc != VT_PERIODIC)
+        return fail(VT_ERR_INVALID, "unknown boundary mode");
+    if (j->nsites < 1 || j->nsites > 0x7fffffffLL)
+        return fail(VT_ERR_INVALID, "nsites must be in [1, 2^31-1]");
+    if (!j->coords || !j->labels)
+        return fail(VT_ERR_INVALID, "coords and labels must be device pointers");
+    if (j->kind != VT_VORONOI && !j->param)
+        return fail(VT_ERR_INVALID, "param is required for Laguerre and Johnson-Mehl");
+    if (j->kind == VT_JOHNSON_MEHL && !(std::isfinite(j->growth) && j->growth > 0.0))
+        return fail(VT_ERR_INVALID, "growth rate must be finite and > 0");
+    std::memset(d, 0, sizeof *d);
+    d->ndim = j->ndim;
+    d->kind = j->kind;
+    d->bc = j->bc ? 1 : 0;
+    int64_t nvox = 1;
+    double V = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        if (a < j->ndim) {
+            if (j->n[a] < 1 || j->n[a] > (1 << 30))
+                return fail(VT_ERR_INVALID, "n[a] must be in [1, 2^30]");
+            if (!(std::isfinite(j->L[a]) && j->L[a] > 0.0))
+                return fail(VT_ERR_INVALID, "L[a] must be finite and > 0");
+            d->n[a] = (int32_t)j->n[a];
+            d->L[a] = j->L[a];
+            d->h[a] = j->L[a] / (double)j->n[a];
+            d->H[a] = 0.5 * j->L[a];
+        } else {
+            d->n[a] = 1;
+            d->L[a] = 1.0;
+            d->h[a] = 1.0;
+            d->H[a] = 0.5;
+        }
+        nvox *= d->n[a];
+        V *= d->L[a];
+    }
+    if (nvox > (int64_t)1 << 40)
+        return fail(VT_ERR_INVALID, "more than 2^40 voxels");
+    d->nvox = nvox;
+    d->nsites = (int32_t)j->nsites;
+    d->growth = j->kind == VT_JOHNSON_MEHL ? j->growth : 1.0;
+    d->rgrowth = 1.0 / d->growth;
+    d->jm_div = (j->kind == VT_JOHNSON_MEHL && !is_pow2_scale(d->growth)) ? 1 : 0;
+
+    // Tile configuration and bin size: forced, tuned, or default.
+    int cfg = 0;
+    double bf = 1.0;
+    if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
+        cfg = t->cfg;
+        bf = t->bin_factor;
+    }
+    if (ctx->force_cfg >= 0)
+        cfg = ctx->force_cfg;
+    if (ctx->force_bin > 0.0)
+        bf = ctx->force_bin;
+    if (batch)
+        cfg = 0;
+    if (cfg < 0 || cfg > 2)
+        cfg = 0;
+    d->cfg = cfg;
+
+    // Bins: side ~ bf times the mean site spacing (V / N)^(1/d), at most
+    // 2^20 per axis and about 4 N + 64 in total.
+    const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim) * bf;
+    int64_t nbins = 1;
+    for (int a = 0; a < 3; ++a) {
+        int nb = 1;
+        if (a < j->ndim) {
+            double f = std::floor(j->L[a] / spacing + 0.5);
+            nb = (int)std::min(std::max(f, 1.0), (double)(1 << 20));
+        }
+        d->nb[a] = nb;
+        nbins *= nb;
+    }
+    while (nbins > 4 * (int64_t)j->nsites + 64) {
+        nbins = 1;
+        for (int a = 0; a < j->ndim; ++a) {
+            d->nb[a] = std::max(1, d->nb[a] * 3 / 4);
+            nbins *= d->nb[a];
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        d->bs[a] = d->L[a] / (double)d->nb[a];
+        d->inv_bs[a] = (double)d->nb[a] / d->L[a];
+    }
+    d->nbins = (int32_t)nbins;
+
+    const vt::TileShape sh = vt::shape_of(j->ndim, cfg);
+    const int T[3] = {sh.run * sh.lx, sh.ly, j->ndim == 3 ? sh.lz : 1};
+    int64_t ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        d->nt[a] = (d->n[a] + T[a] - 1) / T[a];
+        ntiles *= d->nt[a];
+    }
+    d->ntiles = ntiles;
+    d->coords = j->coords;
+    d->param = j->param;
+    d->labels = j->labels;
+    return VT_OK;
+}
+
+vt_status ensure_scratch(vt_ctx* ctx, size_t bytes)
+{
+    if (bytes <= ctx->scratch_cap)
+        return VT_OK;
+    // Growing replaces memory that queued work may still use.
+    VT_HIP(hipDeviceSynchronize());
+    if (ctx->scratch)
+        VT_HIP(hipFree(ctx->scratch));
+    ctx->scratch = nullptr;
+    ctx->scratch_cap = 0;
+    size_t cap = align_up(bytes + bytes / 4, 1 << 20);
+    if (hipMalloc(&ctx->scratch, cap) != hipSuccess) {
+        ctx->scratch = nullptr;
+        return fail(VT_ERR_NOMEM, "scratch allocation failed");
+    }
+    ctx->scratch_cap = cap;
+    return VT_OK;
+}
+
+vt_status ensure_pinned(vt_ctx* ctx, size_t bytes)
+{
+    if (ctx->staging_used)
+        VT_HIP(hipEventSynchronize(ctx->staging_evt));
+    ctx->staging_used = false;
+    if (bytes <= ctx->pinned_cap)
+        return VT_OK;
+    if (ctx->pinned)
+        VT_HIP(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_cap = 0;
+    size_t cap = align_up(bytes + bytes / 4, 1 << 16);
+    if (hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault) != hipSuccess) {
+        ctx->pinned = nullptr;
+        return fail(VT_ERR_NOMEM, "pinned staging allocation failed");
+    }
+    ctx->pinned_cap = cap;
+    return VT_OK;
+}
+
+// Binning arrays of one job carved from `base` (device memory).
+struct SingleLayout {
+    size_t pbound, status, bin_count, bin_start, site_bin, site_rank, sites, sidx, partial, total;
+    int64_t partial_cap;
+};
+
+SingleLayout single_layout(const JobDev& d)
+{
+    SingleLayout L;
+    Carver c;
+    L.pbound = c.take<unsigned long long>(2);
+    L.status = c.take<int32_t>(1, 8);
+    L.bin_count = c.take<int32_t>(d.nbins, 8);
+    L.bin_start = c.take<int32_t>((int64_t)d.nbins + 1);
+    L.site_bin = c.take<int32_t>(d.nsites);
+    L.site_rank = c.take<int32_t>(d.nsites);
+    L.sites = c.take<double4>(d.nsites);
+    L.sidx = c.take<int32_t>(d.nsites);
+    L.partial_cap = vt::scan_partials_needed((int64_t)d.nbins);
+    L.partial = c.take<int32_t>(L.partial_cap);
+    L.total = align_up(c.off, 256);
+    return L;
+}
+
+void bind_single(JobDev& d, char* base, const SingleLayout& L, int32_t* status_dev)
+{
+    d.pbound = (unsigned long long*)(base + L.pbound);
+    d.status = status_dev ? status_dev : (int32_t*)(base + L.status);
+    d.bin_count = (int32_t*)(base + L.bin_count);
+    d.bin_start = (int32_t*)(base + L.bin_start);
+    d.site_bin = (int32_t*)(base + L.site_bin);
+    d.site_rank = (int32_t*)(base + L.site_rank);
+    d.sites = (double4*)(base + L.sites);
+    d.sidx = (int32_t*)(base + L.sidx);
+}
+
+__global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < nwords; k += stride)
+        zero_begin[k] = 0;
+    if (i == 0 && extra)
+        *extra = 0;
+}
+
+hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, hipStream_t s)
+{
+    int64_t g = (nwords + 255) / 256;
+    g = std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
+    k_prepare<<<(unsigned)g, 256, 0, s>>>(zero_begin, nwords, extra);
+    return hipGetLastError();
+}
+
+// Count, scan and scatter the sites of one job (its arrays already bound).
+vt_status bin_single(const JobDev& d, char* base, const SingleLayout& L, hipStream_t s)
+{
+    // pbound, internal status and bin counts are contiguous from L.pbound.
+    const int64_t words = (int64_t)((L.bin_count - L.pbound) / 4) + d.nbins;
+    int32_t* extra = (d.status != (int32_t*)(base + L.status)) ? d.status : nullptr;
+    VT_HIP(launch_prepare((int32_t*)(base + L.pbound), words, extra, s));
+    VT_HIP(vt::launch_bin_count(d, nullptr, 1, nullptr, d.nsites, s));
+    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (int32_t*)(base + L.partial), L.partial_cap, s));
+    VT_HIP(vt::launch_bin_scatter(d, nullptr, 1, nullptr, d.nsites, s));
+    return VT_OK;
+}
+
+__global__ void k_probe(const double* x, const double* den, double* so, double* dq, int64_t n)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        so[i] = sqrt(x[i]);
+        dq[i] = x[i] / den[i];
+    }
+}
+
+__global__ void k_copy_status(const JobDev* jobs, int n, int32_t* out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = *jobs[i].status;
+}
+
+// Uploads a job table through the pinned staging buffer into a stream-ordered
+// device allocation (freed by the caller after the launches that read it).
+vt_status upload_table(vt_ctx* ctx, const std::vector<JobDev>& host, const std::vector<int64_t>* prefix,
+                       void** dev_out, size_t* prefix_off, hipStream_t s)
+{
+    size_t jb = align_up(host.size() * sizeof(JobDev), 256);
+    size_t pb = prefix ? prefix->size() * sizeof(int64_t) : 0;
+    size_t bytes = jb + pb;
+    vt_status st = ensure_pinned(ctx, bytes);
+    if (st != VT_OK)
+        return st;
+    std::memcpy(ctx->pinned, host.data(), host.size() * sizeof(JobDev));
+    if (prefix)
+        std::memcpy((char*)ctx->pinned + jb, prefix->data(), pb);
+    void* dev = nullptr;
+    if (hipMallocAsync(&dev, bytes, s) != hipSuccess)
+        return fail(VT_ERR_NOMEM, "job table allocation failed");
+    VT_HIP(hipMemcpyAsync(dev, ctx->pinned, bytes, hipMemcpyHostToDevice, s));
+    VT_HIP(hipEventRecord(ctx->staging_evt, s));
+    ctx->staging_used = true;
+    *dev_out = dev;
+    if (prefix_off)
+        *prefix_off = jb;
+    return VT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vt_status_string(vt_status s)
+{
+    switch (s) {
+    case VT_OK: return "ok";
+    case VT_ERR_INVALID: return "invalid argument";
+    case VT_ERR_NOMEM: return "out of memory";
+    case VT_ERR_HIP: return "HIP runtime error";
+    case VT_ERR_BUSY: return "resource limit exceeded";
+    case VT_ERR_INPUT: return "bad site data";
+    }
+    return "unknown status";
+}
+
+const char* vt_last_error(void) { return g_last_error.c_str(); }
+
+vt_status vt_create(int device, vt_ctx** out)
+{
+    if (!out)
+        return fail(VT_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    VT_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count)
+        return fail(VT_ERR_INVALID, "no such device");
+    VT_HIP(hipSetDevice(device));
+    vt_ctx* c = new vt_ctx();
+    c->device = device;
+    if (hipEventCreateWithFlags(&c->staging_evt, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return fail(VT_ERR_HIP, "event creation failed");
+    }
+    c->batch_grid = vt::label_batch_grid(device);
+    if (const char* path = std::getenv("VT_TUNE_CACHE"))
+        vt_load_tuning(c, path);  // a missing cache is not an error
+    *out = c;
+    return VT_OK;
+}
+
+void vt_destroy(vt_ctx* ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->scratch)
+        (void)hipFree(ctx->scratch);
+    if (ctx->pinned)
+        (void)hipHostFree(ctx->pinned);
+    if (ctx->staging_evt)
+        (void)hipEventDestroy(ctx->staging_evt);
+    for (hipEvent_t e : ctx->prof_events)
+        (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    if (tile_cfg > 2)
+        return fail(VT_ERR_INVALID, "tile_cfg must be 0, 1 or 2 (or < 0)");
+    if (!(bin_factor <= 0.0 || (bin_factor >= 0.125 && bin_factor <= 16.0)))
+        return fail(VT_ERR_INVALID, "bin_factor out of range");
+    ctx->force_cfg = tile_cfg;
+    ctx->force_bin = bin_factor > 0.0 ? bin_factor : 0.0;
+    return VT_OK;
+}
+
+vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3, int32_t* tile_cfg, double* bin_factor)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    JobDev d;
+    vt_status st = plan_job(ctx, job, &d, false);
+    if (st != VT_OK)
+        return st;
+    if (bins_per_axis3)
+        for (int a = 0; a < 3; ++a)
+            bins_per_axis3[a] = d.nb[a];
+    if (tile_cfg)
+        *tile_cfg = d.cfg;
+    if (bin_factor) {
+        double bf = 1.0;
+        if (const TuneEntry* t = find_tune(ctx, job, d.nvox))
+            bf = t->bin_factor;
+        if (ctx->force_bin > 0.0)
+            bf = ctx->force_bin;
+        *bin_factor = bf;
+    }
+    return VT_OK;
+}
+
+vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    JobDev d;
+    vt_status st = plan_job(ctx, job, &d, false);
+    if (st != VT_OK)
+        return st;
+    VT_HIP(hipSetDevice(ctx->device));
+    const SingleLayout L = single_layout(d);
+    if ((st = ensure_scratch(ctx, L.total)) != VT_OK)
+        return st;
+    char* base = (char*)ctx->scratch;
+    bind_single(d, base, L, status_dev);
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (ctx->profile) {
+        while (ctx->prof_events.size() < ctx->prof_used + 3) {
+            hipEvent_t e;
+            VT_HIP(hipEventCreate(&e));
+            ctx->prof_events.push_back(e);
+        }
+        for (int k = 0; k < 3; ++k)
+            ev[k] = ctx->prof_events[ctx->prof_used + k];
+        ctx->prof_used += 3;
+        VT_HIP(hipEventRecord(ev[0], s));
+    }
+    if ((st = bin_single(d, base, L, s)) != VT_OK)
+        return st;
+    if (ev[1])
+        VT_HIP(hipEventRecord(ev[1], s));
+    VT_HIP(vt::launch_label_single(d, s));
+    if (ev[2])
+        VT_HIP(hipEventRecord(ev[2], s));
+    return VT_OK;
+}
+
+vt_status vt_profile_enable(vt_ctx* ctx, int32_t enable)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    ctx->profile = enable != 0;
+    return VT_OK;
+}
+
+vt_status vt_profile_read(vt_ctx* ctx, double* bin_ms, double* label_ms, int64_t* calls)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    double b = 0.0, l = 0.0;
+    for (size_t k = 0; k + 2 < ctx->prof_used; k += 3) {
+        float t1 = 0.0f, t2 = 0.0f;
+        VT_HIP(hipEventSynchronize(ctx->prof_events[k + 2]));
+        VT_HIP(hipEventElapsedTime(&t1, ctx->prof_events[k], ctx->prof_events[k + 1]));
+        VT_HIP(hipEventElapsedTime(&t2, ctx->prof_events[k + 1], ctx->prof_events[k + 2]));
+        b += t1;
+        l += t2;
+    }
+    if (bin_ms)
+        *bin_ms = b;
+    if (label_ms)
+        *label_ms = l;
+    if (calls)
+        *calls = (int64_t)(ctx->prof_used / 3);
+    ctx->prof_used = 0;
+    return VT_OK;
+}
+
+vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, int32_t* status_dev, void* stream)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    if (njobs < 1 || !jobs)
+        return fail(VT_ERR_INVALID, "need at least one job");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<JobDev> host((size_t)njobs);
+    std::vector<int64_t> prefix((size_t)njobs + 1, 0);
+    int64_t total_bins = 0, total_tiles = 0;
+    for (int i = 0; i < njobs; ++i) {
+        vt_status st = plan_job(ctx, &jobs[i], &host[i], true);
+        if (st != VT_OK)
+            return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
+        prefix[i + 1] = prefix[i] + host[i].nsites;
+        host[i].tile_begin = total_tiles;
+        total_tiles += host[i].ntiles;
+        total_bins += host[i].nbins;
+    }
+    const int64_t total_sites = prefix[njobs];
+    if (total_sites > 0x7fffffffLL || total_bins > 0x7ffffffeLL)
+        return fail(VT_ERR_BUSY, "batch too large: more than 2^31 sites or bins");
+    VT_HIP(hipSetDevice(ctx->device));
+    // Layout: [pbound 2/job][status 1/job][bin_count][counters 8] zeroed together,
+    // then bin_start, site arrays, scan partials.
+    Carver c;
+    const size_t o_pb = c.take<unsigned long long>(2 * (int64_t)njobs);
+    const size_t o_st = c.take<int32_t>(njobs, 8);
+    const size_t o_cnt = c.take<int32_t>(total_bins, 4);
+    const size_t o_ctr = c.take<int32_t>(8, 4);
+    const size_t zero_end = c.off;
+    const size_t o_start = c.take<int32_t>(total_bins + 1);
+    const size_t o_sbin = c.take<int32_t>(total_sites);
+    const size_t o_srank = c.take<int32_t>(total_sites);
+    const size_t o_sites = c.take<double4>(total_sites);
+    const size_t o_sidx = c.take<int32_t>(total_sites);
+    const int64_t pcap = vt::scan_partials_needed(total_bins);
+    const size_t o_part = c.take<int32_t>(pcap);
+    vt_status st = ensure_scratch(ctx, align_up(c.off, 256));
+    if (st != VT_OK)
+        return st;
+    char* base = (char*)ctx->scratch;
+    int64_t bin_off = 0;
+    for (int i = 0; i < njobs; ++i) {
+        JobDev& d = host[i];
+        d.pbound = (unsigned long long*)(base + o_pb) + 2 * i;
+        d.status = status_dev ? status_dev + i : (int32_t*)(base + o_st) + i;
+        d.bin_count = (int32_t*)(base + o_cnt) + bin_off;
+        d.bin_start = (int32_t*)(base + o_start) + bin_off;  // values index the batch-wide site arrays
+        d.site_bin = (int32_t*)(base + o_sbin) + prefix[i];
+        d.site_rank = (int32_t*)(base + o_srank) + prefix[i];
+        d.sites = (double4*)(base + o_sites);
+        d.sidx = (int32_t*)(base + o_sidx);
+        bin_off += d.nbins;
+    }
+    void* table = nullptr;
+    size_t poff = 0;
+    if ((st = upload_table(ctx, host, &prefix, &table, &poff, s)) != VT_OK)
+        return st;
+    const JobDev* djobs = (const JobDev*)table;
+    const int64_t* dprefix = (const int64_t*)((char*)table + poff);
+    VT_HIP(launch_prepare((int32_t*)(base + o_pb), (int64_t)((zero_end - o_pb) / 4), nullptr, s));
+    if (status_dev)
+        VT_HIP(vt::launch_fill_i32(status_dev, njobs, 0, s));
+    JobDev dummy;
+    std::memset(&dummy, 0, sizeof dummy);
+    VT_HIP(vt::launch_bin_count(dummy, djobs, njobs, dprefix, total_sites, s));
+    VT_HIP(vt::launch_scan((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins,
+                           (int32_t*)(base + o_part), pcap, s));
+    VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
+    VT_HIP(vt::launch_label_batch(djobs, njobs, 0, total_tiles, (int32_t*)(base + o_ctr), ctx->batch_grid, s));
+    VT_HIP(hipFreeAsync(table, s));
+    return VT_OK;
+}
+
+vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out, int32_t* status_dev, void* stream)
+{
+    if (!ctx || !out)
+        return fail(VT_ERR_INVALID, "ctx and out must not be NULL");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    JobDev d;
+    vt_status st = plan_job(ctx, job, &d, true);
+    if (st != VT_OK)
+        return st;
+    VT_HIP(hipSetDevice(ctx->device));
+    const SingleLayout L = single_layout(d);
+    void* mem = nullptr;
+    if (hipMallocAsync(&mem, L.total, s) != hipSuccess)
+        return fail(VT_ERR_NOMEM, "bins allocation failed");
+    char* base = (char*)mem;
+    bind_single(d, base, L, nullptr);
+    if ((st = bin_single(d, base, L, s)) != VT_OK) {
+        (void)hipFreeAsync(mem, s);
+        return st;
+    }
+    if (status_dev)
+        VT_HIP(hipMemcpyAsync(status_dev, d.status, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    vt_bins* b = new vt_bins();
+    b->job = d;
+    b->mem = mem;
+    *out = b;
+    return VT_OK;
+}
+
+vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n, int32_t* status_dev, void* stream)
+{
+    if (!ctx || !bins || n < 1)
+        return fail(VT_ERR_INVALID, "need a context and at least one bins object");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<JobDev> host((size_t)n);
+    int64_t total_tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!bins[i])
+            return fail(VT_ERR_INVALID, "bins[" + std::to_string(i) + "] is NULL");
+        host[i] = bins[i]->job;
+        host[i].tile_begin = total_tiles;
+        total_tiles += host[i].ntiles;
+    }
+    VT_HIP(hipSetDevice(ctx->device));
+    // Table followed by the eight tile counters, zeroed on the device.
+    host.push_back(JobDev());
+    std::memset(&host.back(), 0, sizeof(JobDev));
+    void* table = nullptr;
+    vt_status st = upload_table(ctx, host, nullptr, &table, nullptr, s);
+    if (st != VT_OK)
+        return st;
+    int32_t* counters = (int32_t*)((char*)table + (size_t)n * sizeof(JobDev));
+    VT_HIP(vt::launch_fill_i32(counters, 8, 0, s));
+    VT_HIP(vt::launch_label_batch((const JobDev*)table, n, 0, total_tiles, counters, ctx->batch_grid, s));
+    if (status_dev)
+        k_copy_status<<<(n + 255) / 256, 256, 0, s>>>((const JobDev*)table, n, status_dev);
+    VT_HIP(hipGetLastError());
+    VT_HIP(hipFreeAsync(table, s));
+    return VT_OK;
+}
+
+vt_status vt_bins_free(vt_ctx* ctx, vt_bins* bins, void* stream)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    if (!bins)
+        return VT_OK;
+    VT_HIP(hipSetDevice(ctx->device));
+    hipError_t e = hipFreeAsync(bins->mem, (hipStream_t)stream);
+    delete bins;
+    if (e != hipSuccess)
+        return hip_fail(e, "hipFreeAsync");
+    return VT_OK;
+}
+
+vt_status vt_numerics_probe(vt_ctx* ctx, const double* x, const double* den, double* sqrt_out, double* div_out,
+                            int64_t n, void* stream)
+{
+    if (!ctx || n < 0 || (n > 0 && (!x || !den || !sqrt_out || !div_out)))
+        return fail(VT_ERR_INVALID, "bad probe arguments");
+    if (n == 0)
+        return VT_OK;
+    VT_HIP(hipSetDevice(ctx->device));
+    const int64_t g = (n + 255) / 256;
+    if (g > 0x7fffffffLL)
+        return fail(VT_ERR_INVALID, "probe too large");
+    k_probe<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(x, den, sqrt_out, div_out, n);
+    VT_HIP(hipGetLastError());
+    return VT_OK;
+}
+
+vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path)
+{
+    if (!ctx || !cache_path)
+        return fail(VT_ERR_INVALID, "ctx and cache_path must not be NULL");
+    FILE* f = std::fopen(cache_path, "r");
+    if (!f)
+        return fail(VT_ERR_INVALID, std::string("cannot open ") + cache_path);
+    char line[512];
+    std::vector<TuneEntry> got;
+    while (std::fgets(line, sizeof line, f)) {
+        TuneEntry t;
+        if (std::sscanf(line,
+                        " {\"ndim\": %d, \"kind\": %d, \"bc\": %d, \"size_class\": %d, \"density_class\": %d, "
+                        "\"tile_cfg\": %d, \"bin_factor\": %lf, \"ms\": %lf",
+                        &t.ndim, &t.kind, &t.bc, &t.size_cls, &t.dens_cls, &t.cfg, &t.bin_factor, &t.ms) == 8)
+            got.push_back(t);
+    }
+    std::fclose(f);
+    for (const TuneEntry& t : got) {
+        bool replaced = false;
+        for (TuneEntry& o : ctx->tune)
+            if (o.ndim == t.ndim && o.kind == t.kind && o.bc == t.bc && o.size_cls == t.size_cls &&
+                o.dens_cls == t.dens_cls) {
+                o = t;
+                replaced = true;
+            }
+        if (!replaced)
+            ctx->tune.push_back(t);
+    }
+    return VT_OK;
+}
+
+vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char* cache_path)
+{
+    if (!ctx || !samples || n < 1)
+        return fail(VT_ERR_INVALID, "need a context and at least one sample job");
+    VT_HIP(hipSetDevice(ctx->device));
+    const int saved_cfg = ctx->force_cfg;
+    const double saved_bin = ctx->force_bin;
+    const double factors[] = {0.7, 1.0, 1.4, 2.0};
+    hipEvent_t e0, e1;
+    VT_HIP(hipEventCreate(&e0));
+    VT_HIP(hipEventCreate(&e1));
+    vt_status result = VT_OK;
+    for (int i = 0; i < n && result == VT_OK; ++i) {
+        const vt_job* j = &samples[i];
+        JobDev d;
+        if ((result = plan_job(ctx, j, &d, false)) != VT_OK)
+            break;
+        TuneEntry best{};
+        best.ms = 1e300;
+        for (int cfg = 0; cfg < 3 && result == VT_OK; ++cfg) {
+            for (double bf : factors) {
+                ctx->force_cfg = cfg;
+                ctx->force_bin = bf;
+                // one warm-up, then the best of three
+                if ((result = vt_tessellate(ctx, j, nullptr, nullptr)) != VT_OK)
+                    break;
+                float tbest = 1e30f;
+                for (int r = 0; r < 3 && result == VT_OK; ++r) {
+                    float ms = 0;
+                    if (hipEventRecord(e0, nullptr) != hipSuccess ||
+                        (result = vt_tessellate(ctx, j, nullptr, nullptr)) != VT_OK ||
+                        hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        if (result == VT_OK)
+                            result = fail(VT_ERR_HIP, "autotune timing failed");
+                        break;
+                    }
+                    tbest = std::min(tbest, ms);
+                }
+                if (result != VT_OK)
+                    break;
+                if (tbest < best.ms) {
+                    best.ms = tbest;
+                    best.cfg = cfg;
+                    best.bin_factor = bf;
+                }
+            }
+        }
+        if (result != VT_OK)
+            break;
+        best.ndim = j->ndim;
+        best.kind = j->kind;
+        best.bc = j->bc ? 1 : 0;
+        best.size_cls = size_class(d.nvox);
+        best.dens_cls = dens_class(d.nvox, j->nsites);
+        bool replaced = false;
+        for (TuneEntry& o : ctx->tune)
+            if (o.ndim == best.ndim && o.kind == best.kind && o.bc == best.bc && o.size_cls == best.size_cls &&
+                o.dens_cls == best.dens_cls) {
+                o = best;
+                replaced = true;
+            }
+        if (!replaced)
+            ctx->tune.push_back(best);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->force_cfg = saved_cfg;
+    ctx->force_bin = saved_bin;
+    if (result != VT_OK)
+        return result;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "w");
+        if (!f)
+            return fail(VT_ERR_INVALID, std::string("cannot write ") + cache_path);
+        std::fprintf(f, "[\n");
+        for (size_t k = 0; k < ctx->tune.size(); ++k) {
+            const TuneEntry& t = ctx->tune[k];
+            std::fprintf(f,
+                         " {\"ndim\": %d, \"kind\": %d, \"bc\": %d, \"size_class\": %d, \"density_class\": %d, "
+                         "\"tile_cfg\": %d, \"bin_factor\": %.3f, \"ms\": %.6f}%s\n",
+                         t.ndim, t.kind, t.bc, t.size_cls, t.dens_cls, t.cfg, t.bin_factor, t.ms,
+                         k + 1 < ctx->tune.size() ? "," : "");
+        }
+        std::fprintf(f, "]\n");
+        std::fclose(f);
+    }
+    return VT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,289 @@
+// bin_kernels.hip -- site binning on the device: a counting sort of the
+// sites into a uniform grid of bins (count with atomics, exclusive prefix
+// scan of the counts, scatter).  The labelling kernel then finds the sites
+// near a voxel tile by walking bins outward from it.
+//
+// One thread per site.  In a batch, a thread finds its job by binary search
+// over the per-job site offsets.  The count pass also checks every site
+// (finite coordinates inside [0, L_a), finite parameter; problem statement of
+// Sec. 3) and records max(param) and max(-param) for the labelling kernel's
+// lower bounds.
+#include "vt_internal.h"
+
+namespace vt {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline unsigned long long ordered_bits(double v)
+{
+    // Monotone map from binary64 to uint64 (larger double -> larger integer).
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ inline int find_segment(const int64_t* prefix, int n, int64_t g)
+{
+    // Largest j in [0, n) with prefix[j] <= g.
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDev* __restrict__ jobs,
+                                                      int njobs, const int64_t* __restrict__ prefix,
+                                                      int64_t total)
+{
+    int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (g >= total)
+        return;
+    int j = 0;
+    int64_t i = g;
+    if (jobs) {
+        j = find_segment(prefix, njobs, g);
+        i = g - prefix[j];
+    }
+    const JobDev& J = jobs ? jobs[j] : single;
+    const int nd = J.ndim;
+    bool ok = true;
+    int b[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        if (a < nd) {
+            double c = J.coords[i * nd + a];
+            if (!(c >= 0.0 && c < J.L[a])) {
+                ok = false;
+            } else {
+                int v = (int)(c * J.inv_bs[a]);  // c >= 0: truncation is floor
+                b[a] = v < 0 ? 0 : (v >= J.nb[a] ? J.nb[a] - 1 : v);
+            }
+        }
+    }
+    double p = 0.0;
+    if (J.kind != KIND_VORONOI) {
+        p = J.param[i];
+        if (!isfinite(p))
+            ok = false;
+    }
+    if (!ok) {
+        b[0] = b[1] = b[2] = 0;
+        atomicOr(J.status, ST_INPUT);
+    }
+    int lin = b[0] + J.nb[0] * (b[1] + J.nb[1] * b[2]);
+    int rank = atomicAdd(&J.bin_count[lin], 1);
+    J.site_bin[i] = lin;
+    J.site_rank[i] = rank;
+    if (ok && J.kind != KIND_VORONOI) {
+        unsigned long long hi = ordered_bits(p), lo = ordered_bits(-p);
+        // The racy pre-read only skips atomics that cannot change the value.
+        if (hi > J.pbound[0])
+            atomicMax(&J.pbound[0], hi);
+        if (lo > J.pbound[1])
+            atomicMax(&J.pbound[1], lo);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const JobDev* __restrict__ jobs,
+                                                        int njobs, const int64_t* __restrict__ prefix,
+                                                        int64_t total)
+{
+    int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (g >= total)
+        return;
+    int j = 0;
+    int64_t i = g;
+    if (jobs) {
+        j = find_segment(prefix, njobs, g);
+        i = g - prefix[j];
+    }
+    const JobDev& J = jobs ? jobs[j] : single;
+    const int nd = J.ndim;
+    int lin = J.site_bin[i];
+    int pos = J.bin_start[lin] + J.site_rank[i];
+    const double* c = J.coords + i * nd;
+    double4 rec;
+    rec.x = c[0];
+    rec.y = c[1];
+    rec.z = nd == 3 ? c[2] : 0.0;
+    rec.w = J.kind != KIND_VORONOI ? J.param[i] : 0.0;
+    J.sites[pos] = rec;
+    J.sidx[pos] = (int32_t)i;
+}
+
+// ---- exclusive prefix scan of int32 counts: reduce, scan partials, final ----
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ inline int wave_inclusive_add(int v, int lane)
+{
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int t = __shfl_up(v, o);
+        if (lane >= o)
+            v += t;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over the block; returns the
+// exclusive prefix and the block total.
+__device__ inline int block_exclusive_add(int v, int& total)
+{
+    __shared__ int wsum[kScanThreads / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    int inc = wave_inclusive_add(v, lane);
+    if (lane == WAVE - 1)
+        wsum[w] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int k = 0; k < kScanThreads / WAVE; ++k) {
+        int s = wsum[k];
+        if (k < w)
+            off += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                              int32_t* __restrict__ partial)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n)
+            s += in[base + k];
+    int total;
+    block_exclusive_add(s, total);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(int32_t* partial, int64_t nblk)
+{
+    int carry = 0;
+    for (int64_t base = 0; base < nblk; base += kScanThreads) {
+        int64_t i = base + threadIdx.x;
+        int v = i < nblk ? partial[i] : 0;
+        int total;
+        int ex = block_exclusive_add(v, total);
+        if (i < nblk)
+            partial[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_final(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                             int64_t n, const int32_t* __restrict__ partial)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int run = block_exclusive_add(s, total) + partial[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n)
+            out[base + k] = run;
+        if (base + k == n - 1)
+            out[n] = run + v[k];
+        run += v[k];
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block)
+{
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    unsigned g = grid_for(n, 256);
+    if (g > 4096)
+        g = 4096;
+    k_fill_i32<<<g, 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    unsigned g = grid_for(n, 256);
+    if (g > 4096)
+        g = 4096;
+    k_fill_u64<<<g, 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_count(const JobDev& single, const JobDev* jobs_dev, int njobs,
+                            const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s)
+{
+    if (total_sites <= 0)
+        return hipSuccess;
+    k_bin_count<<<grid_for(total_sites, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs,
+                                                                site_prefix_dev, total_sites);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int njobs,
+                              const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s)
+{
+    if (total_sites <= 0)
+        return hipSuccess;
+    k_bin_scatter<<<grid_for(total_sites, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs,
+                                                                  site_prefix_dev, total_sites);
+    return hipGetLastError();
+}
+
+int64_t scan_partials_needed(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* partial,
+                       int64_t partial_cap, hipStream_t s)
+{
+    int64_t nblk = (n + kScanTile - 1) / kScanTile;
+    if (n <= 0 || nblk > partial_cap || nblk > 0x7fffffff)
+        return hipErrorInvalidValue;
+    k_scan_reduce<<<(unsigned)nblk, kScanThreads, 0, s>>>(in, n, partial);
+    k_scan_partials<<<1, kScanThreads, 0, s>>>(partial, nblk);
+    k_scan_final<<<(unsigned)nblk, kScanThreads, 0, s>>>(in, out, n, partial);
+    return hipGetLastError();
+}
+
+}  // namespace vt

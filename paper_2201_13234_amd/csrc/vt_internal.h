@@ -1,0 +1,71 @@
+// vt_internal.h -- types and launchers shared by the host code and the
+// kernels of the device library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vt {
+
+enum { KIND_VORONOI = 0, KIND_LAGUERRE = 1, KIND_JM = 2 };
+enum { ST_OK = 0, ST_INPUT = 5 };
+
+// Largest number of candidate sites one wave holds in LDS at a time.
+constexpr int CAP = 128;
+constexpr int WAVE = 64;
+
+// Device-side description of one diagram.  Plain old data: copied to the
+// device as a kernel argument (single job) or as a table (batches).
+struct JobDev {
+    int32_t ndim, kind, bc, cfg;   // cfg: tile configuration id
+    int32_t jm_div;                // Johnson-Mehl: 1 = divide by v, 0 = multiply by exact 1/v
+    int32_t nsites, nbins, pad0;
+    int32_t n[3];                  // voxels per axis (n[2] = 1 in 2D)
+    int32_t nb[3];                 // bins per axis (nb[2] = 1 in 2D)
+    int32_t nt[3];                 // tiles per axis
+    int32_t pad1;
+    double L[3], h[3], H[3];       // lengths, voxel size, half lengths
+    double bs[3], inv_bs[3];       // bin side and its reciprocal
+    double growth, rgrowth;        // v and 1/v
+    int64_t nvox, ntiles;
+    int64_t tile_begin;            // first tile of this job in a batch enumeration
+    const double* coords;          // [nsites][ndim], caller input
+    const double* param;           // [nsites] or null
+    int32_t* labels;               // caller output
+    int32_t* status;               // one word, written by the kernels
+    int32_t* bin_count;            // [nbins]
+    int32_t* bin_start;            // [nbins + 1], indexes `sites`
+    int32_t* site_bin;             // [nsites]
+    int32_t* site_rank;            // [nsites]
+    double4* sites;                // sorted sites {x, y, z, param}
+    int32_t* sidx;                 // sorted -> input index (0-based)
+    unsigned long long* pbound;    // [2]: ordered bits of max(param), max(-param)
+};
+
+// Tile configurations: lane run length along x, lanes along x, y, z.
+struct TileShape { int run, lx, ly, lz; };
+constexpr TileShape kShape3[3] = {{8, 1, 8, 8}, {8, 2, 8, 4}, {8, 4, 4, 4}};
+constexpr TileShape kShape2[3] = {{8, 4, 16, 1}, {8, 2, 32, 1}, {8, 8, 8, 1}};
+
+inline TileShape shape_of(int ndim, int cfg) { return ndim == 3 ? kShape3[cfg] : kShape2[cfg]; }
+
+// ---- launchers (defined in the .hip files) ----
+// Binning over one job (jobs_dev == nullptr, `single` used) or over njobs jobs
+// whose sites are enumerated by site_prefix_dev ([njobs + 1], device).
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_bin_count(const JobDev& single, const JobDev* jobs_dev, int njobs,
+                            const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* partial,
+                       int64_t partial_cap, hipStream_t s);
+int64_t scan_partials_needed(int64_t n);
+hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int njobs,
+                              const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s);
+
+// Labelling: single job (all its tiles) or a persistent batch launch.
+hipError_t launch_label_single(const JobDev& job, hipStream_t s);
+hipError_t launch_label_batch(const JobDev* jobs_dev, int njobs, int ndim_mask,
+                              int64_t total_tiles, int32_t* counters, int grid, hipStream_t s);
+int label_batch_grid(int device);
+
+}  // namespace vt

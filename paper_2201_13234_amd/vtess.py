@@ -1,0 +1,241 @@
+"""Thin ctypes binding of the device library (include/vtess.h).
+
+Only argument marshalling happens here: every step of the labelling runs in
+the HIP kernels of ``libvtess.so``.  PyTorch supplies device memory and the
+current stream; no torch type crosses the C ABI.  If the library has not been
+built, every entry point raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvtess.so")
+
+VORONOI, LAGUERRE, JOHNSON_MEHL = 0, 1, 2
+NONPERIODIC, PERIODIC = 0, 1
+OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BUSY, ERR_INPUT = range(6)
+
+# Symbols declared in include/vtess.h.
+EXPORTS = ["vt_create", "vt_destroy", "vt_tessellate", "vt_tessellate_batch", "vt_bins_build",
+           "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_load_tuning", "vt_set_params",
+           "vt_plan", "vt_numerics_probe", "vt_profile_enable", "vt_profile_read",
+           "vt_status_string", "vt_last_error"]
+
+
+class VtJob(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("kind", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("L", ctypes.c_double * 3),
+                ("growth", ctypes.c_double), ("nsites", ctypes.c_int64),
+                ("coords", ctypes.c_void_p), ("param", ctypes.c_void_p), ("labels", ctypes.c_void_p)]
+
+
+class VtError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: status {code} ({status_string(code)}): {last_error()}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Loads libvtess.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"device library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P = ctypes.POINTER
+        L.vt_create.argtypes = [ctypes.c_int, P(vp)]
+        L.vt_destroy.argtypes = [vp]
+        L.vt_destroy.restype = None
+        L.vt_tessellate.argtypes = [vp, P(VtJob), vp, vp]
+        L.vt_tessellate_batch.argtypes = [vp, P(VtJob), i32, vp, vp]
+        L.vt_bins_build.argtypes = [vp, P(VtJob), P(vp), vp, vp]
+        L.vt_label_batch.argtypes = [vp, P(vp), i32, vp, vp]
+        L.vt_bins_free.argtypes = [vp, vp, vp]
+        L.vt_autotune.argtypes = [vp, P(VtJob), i32, ctypes.c_char_p]
+        L.vt_load_tuning.argtypes = [vp, ctypes.c_char_p]
+        L.vt_set_params.argtypes = [vp, i32, dbl]
+        L.vt_plan.argtypes = [vp, P(VtJob), P(i32), P(i32), P(dbl)]
+        L.vt_numerics_probe.argtypes = [vp, vp, vp, vp, vp, i64, vp]
+        L.vt_profile_enable.argtypes = [vp, i32]
+        L.vt_profile_read.argtypes = [vp, P(dbl), P(dbl), P(i64)]
+        L.vt_status_string.argtypes = [ctypes.c_int]
+        L.vt_status_string.restype = ctypes.c_char_p
+        L.vt_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("vt_destroy", "vt_status_string", "vt_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code):
+    return lib().vt_status_string(int(code)).decode()
+
+
+def last_error():
+    return lib().vt_last_error().decode()
+
+
+def _check(code, what):
+    if code != OK:
+        raise VtError(code, what)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+@dataclass
+class Job:
+    """One diagram: device tensors for sites, parameters and labels."""
+    n: tuple
+    L: tuple
+    kind: int
+    periodic: bool
+    coords: object            # torch float64 [nsites, ndim] on the device
+    param: object = None      # torch float64 [nsites] or None
+    growth: float = 1.0
+    labels: object = None     # torch int32 with prod(n) elements, allocated if None
+
+    def to_c(self):
+        import torch
+        d = len(self.n)
+        if self.labels is None:
+            self.labels = torch.empty(tuple(reversed(self.n)), dtype=torch.int32,
+                                      device=self.coords.device)
+        for name, t, dt in (("coords", self.coords, torch.float64), ("param", self.param, torch.float64),
+                            ("labels", self.labels, torch.int32)):
+            if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor")
+        if self.coords.dim() != 2 or self.coords.shape[1] != d:
+            raise ValueError("coords must be [nsites, ndim]")
+        if self.labels.numel() != int(_prod(self.n)):
+            raise ValueError("labels must hold prod(n) elements")
+        j = VtJob()
+        j.ndim = d
+        j.kind = int(self.kind)
+        j.bc = PERIODIC if self.periodic else NONPERIODIC
+        j.reserved = 0
+        for a in range(3):
+            j.n[a] = int(self.n[a]) if a < d else 1
+            j.L[a] = float(self.L[a]) if a < d else 1.0
+        j.growth = float(self.growth)
+        j.nsites = int(self.coords.shape[0])
+        j.coords = self.coords.data_ptr()
+        j.param = self.param.data_ptr() if self.param is not None else None
+        j.labels = self.labels.data_ptr()
+        return j
+
+
+def _prod(v):
+    p = 1
+    for x in v:
+        p *= int(x)
+    return p
+
+
+class Bins:
+    """Sites of one job binned on the device; kept until free()."""
+
+    def __init__(self, ctx, handle, job):
+        self.ctx, self.handle, self.job = ctx, handle, job
+
+    def free(self, stream=None):
+        if self.handle:
+            _check(lib().vt_bins_free(self.ctx.handle, self.handle, _stream(stream)), "vt_bins_free")
+            self.handle = None
+
+
+class Context:
+    """A vt_ctx on one device."""
+
+    def __init__(self, device=0):
+        self.handle = ctypes.c_void_p()
+        _check(lib().vt_create(int(device), ctypes.byref(self.handle)), "vt_create")
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().vt_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tessellate(self, job, status=None, stream=None):
+        cj = job.to_c()
+        _check(lib().vt_tessellate(self.handle, ctypes.byref(cj), _ptr(status), _stream(stream)),
+               "vt_tessellate")
+        return job.labels
+
+    def tessellate_batch(self, jobs, status=None, stream=None):
+        arr = (VtJob * len(jobs))(*[j.to_c() for j in jobs])
+        _check(lib().vt_tessellate_batch(self.handle, arr, len(jobs), _ptr(status), _stream(stream)),
+               "vt_tessellate_batch")
+        return [j.labels for j in jobs]
+
+    def bins_build(self, job, status=None, stream=None):
+        cj = job.to_c()
+        h = ctypes.c_void_p()
+        _check(lib().vt_bins_build(self.handle, ctypes.byref(cj), ctypes.byref(h), _ptr(status),
+                                   _stream(stream)), "vt_bins_build")
+        return Bins(self, h, job)
+
+    def label_batch(self, bins, status=None, stream=None):
+        arr = (ctypes.c_void_p * len(bins))(*[b.handle for b in bins])
+        _check(lib().vt_label_batch(self.handle, arr, len(bins), _ptr(status), _stream(stream)),
+               "vt_label_batch")
+
+    def autotune(self, samples, cache_path=None):
+        arr = (VtJob * len(samples))(*[j.to_c() for j in samples])
+        _check(lib().vt_autotune(self.handle, arr, len(samples),
+                                 cache_path.encode() if cache_path else None), "vt_autotune")
+
+    def load_tuning(self, path):
+        _check(lib().vt_load_tuning(self.handle, path.encode()), "vt_load_tuning")
+
+    def set_params(self, tile_cfg=-1, bin_factor=0.0):
+        _check(lib().vt_set_params(self.handle, int(tile_cfg), float(bin_factor)), "vt_set_params")
+
+    def plan(self, job):
+        cj = job.to_c()
+        nb = (ctypes.c_int32 * 3)()
+        cfg = ctypes.c_int32()
+        bf = ctypes.c_double()
+        _check(lib().vt_plan(self.handle, ctypes.byref(cj), nb, ctypes.byref(cfg), ctypes.byref(bf)),
+               "vt_plan")
+        return dict(bins=tuple(nb), tile_cfg=cfg.value, bin_factor=bf.value)
+
+    def profile_enable(self, enable=True):
+        _check(lib().vt_profile_enable(self.handle, 1 if enable else 0), "vt_profile_enable")
+
+    def profile_read(self):
+        """(binning ms, labelling ms, calls) summed over the recorded calls."""
+        b, l, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().vt_profile_read(self.handle, ctypes.byref(b), ctypes.byref(l), ctypes.byref(n)),
+               "vt_profile_read")
+        return b.value, l.value, n.value
+
+    def numerics_probe(self, x, den, stream=None):
+        """Device sqrt(x) and x / den (binary64), for checking IEEE rounding."""
+        import torch
+        s = torch.empty_like(x)
+        q = torch.empty_like(x)
+        _check(lib().vt_numerics_probe(self.handle, _ptr(x), _ptr(den), _ptr(s), _ptr(q), x.numel(),
+                                       _stream(stream)), "vt_numerics_probe")
+        return s, q

@@ -1,0 +1,77 @@
+"""CPU-side checks of the device library's boundary: it builds, loads and
+exports every entry point that include/vtess.h declares; the product code
+never reaches the oracle."""
+import ast
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2201_13234_amd")
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vtess.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vt_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("vt_create", "vt_destroy", "vt_tessellate", "vt_tessellate_batch", "vt_bins_build",
+              "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_status_string", "vt_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2201_13234_amd import vtess
+    L = vtess.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(vtess.EXPORTS) == declared_functions()
+
+
+def test_status_strings():
+    from paper_2201_13234_amd import vtess
+    assert vtess.status_string(vtess.OK) == "ok"
+    assert vtess.status_string(vtess.ERR_INPUT) == "bad site data"
+    assert vtess.status_string(99) == "unknown status"
+
+
+def test_job_struct_matches_header_layout():
+    import ctypes
+    from paper_2201_13234_amd import vtess
+    # 4 int32, 3 int64, 3 double, double, int64, 3 pointers
+    assert ctypes.sizeof(vtess.VtJob) == 16 + 24 + 24 + 8 + 8 + 24
+    assert vtess.VtJob.coords.offset == 80
+
+
+def test_product_code_never_imports_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            path = os.path.join(dirpath, f)
+            if f.endswith(".py"):
+                tree = ast.parse(open(path).read())
+                for node in ast.walk(tree):
+                    if isinstance(node, ast.Import):
+                        assert not any(a.name.split(".")[0] == "oracle" for a in node.names), path
+                    if isinstance(node, ast.ImportFrom):
+                        assert (node.module or "").split(".")[0] != "oracle", path
+            if f.endswith((".hip", ".h", ".cpp")):
+                src = open(path).read()
+                assert "vto.h" not in src and "vto_" not in src, path
+
+
+def test_inputs_are_deterministic():
+    from paper_2201_13234_amd import inputs as I
+    a, b = I.m1(), I.m1()
+    assert np.array_equal(a.coords, b.coords)
+    w = I.m3()
+    assert w.coords.shape == (20_000, 3) and w.param.shape == (20_000,)
+    assert np.all(w.coords >= 0) and np.all(w.coords < 512)
+    sp = (512 ** 3 / 20_000) ** (1 / 3)
+    # median radius half the spacing (w = r^2)
+    assert abs(np.median(np.sqrt(w.param)) / (0.5 * sp) - 1) < 0.02
+    j = I.stream_job(5)
+    assert j.ndim in (2, 3) and 10 <= j.nsites <= 20_000

@@ -1,0 +1,267 @@
+"""Parity of the device library with the oracle, voxel by voxel, bit for bit.
+
+Labels are integers, so the bar is exact equality.  Sizes go from single
+voxels to the full benchmark configurations, with ragged tile tails, every
+diagram kind and boundary mode, and the degenerate inputs of the problem
+(ties, duplicates, one site, clustered sites, empty cells, more sites than
+voxels).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13234_amd import inputs as I
+from gpu_util import describe_mismatch, run_device, run_oracle, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2201_13234_amd import vtess
+    assert torch.cuda.is_available()
+    c = vtess.Context(0)
+    yield c
+    c.close()
+
+
+def check(ctx, w, cfgs=(None,)):
+    ref = run_oracle(w)
+    for cfg in cfgs:
+        if cfg is not None:
+            ctx.set_params(*cfg)
+        try:
+            got, st = run_device(ctx, w, status=True)
+        finally:
+            if cfg is not None:
+                ctx.set_params(-1, 0.0)
+        assert st == 0
+        assert got.shape == ref.shape
+        assert np.array_equal(got, ref), f"{w.name} cfg={cfg}: " + describe_mismatch(got, ref)
+
+
+def random_workload(seed):
+    rng = np.random.default_rng(1000 + seed)
+    d = 2 + int(rng.integers(0, 2))
+    if d == 3:
+        n = tuple(int(v) for v in rng.integers(1, 41, 3))
+    else:
+        n = tuple(int(v) for v in rng.integers(1, 160, 2))
+    aniso = seed % 3 == 0
+    L = tuple(float(v) * (float(rng.uniform(0.4, 2.5)) if aniso else 1.0) for v in n)
+    ns = int(rng.integers(1, 400))
+    kind = int(rng.integers(0, 3))
+    periodic = bool(rng.integers(0, 2))
+    coords = I.uniform_sites(rng, ns, L)
+    sp = (np.prod(L) / ns) ** (1 / d)
+    growth = float(rng.choice([1.0, 0.5, 2.0, 0.7, 1.3, 4.0]))
+    param = None
+    if kind == I.LAGUERRE:
+        if seed % 2:
+            param = I.lognormal_weights(rng, ns, 0.5 * sp, 0.3)
+        else:
+            param = rng.uniform(-2.0, 3.0, ns) * sp * sp
+    elif kind == I.JOHNSON_MEHL:
+        param = rng.uniform(0.0, 2.0 * sp / growth, ns)
+    return workload(n, kind, periodic, coords, param, growth, L, name=f"random{seed}")
+
+
+@pytest.mark.parametrize("seed", range(48))
+def test_random_small_jobs(ctx, seed):
+    check(ctx, random_workload(seed))
+
+
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("bf", [0.7, 1.0, 2.0])
+def test_m1_all_tile_shapes_and_bin_sizes(ctx, cfg, bf):
+    check(ctx, I.m1(), cfgs=[(cfg, bf)])
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("d", [2, 3])
+def test_every_variant_and_tile_shape(ctx, kind, periodic, d):
+    n = (37, 29, 23) if d == 3 else (131, 77)
+    w = I.make(n, kind, periodic, 300 if d == 3 else 250, 77 + kind + 3 * d, growth=0.75)
+    check(ctx, w, cfgs=[(0, 0.0), (1, 0.0), (2, 0.0)])
+
+
+# ---------------------------------------------------------------- adversarial
+
+def lattice(m, c, offset):
+    pts = [(a * c[0] + offset[0], b * c[1] + offset[1], e * c[2] + offset[2])
+           for e in range(m[2]) for b in range(m[1]) for a in range(m[0])]
+    return np.array(pts, dtype=np.float64)
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_lattice_exact_ties(ctx, periodic, reverse):
+    m, c = (6, 5, 4), (3, 3, 3)
+    n = tuple(m[a] * c[a] for a in range(3))
+    pts = lattice(m, c, (1.0, 1.0, 1.0))
+    if reverse:
+        pts = pts[::-1].copy()
+    for kind, param in ((0, None), (1, np.full(len(pts), 4.0)), (2, np.zeros(len(pts)))):
+        check(ctx, workload(n, kind, periodic, pts, param, name=f"lattice{kind}"))
+
+
+def test_duplicates_and_voxel_centres(ctx):
+    rng = np.random.default_rng(5)
+    n = (30, 26, 22)
+    pts = np.floor(I.uniform_sites(rng, 200, [float(v) for v in n])) + 0.5
+    pts[100:150] = pts[:50]
+    for kind in (0, 1, 2):
+        param = None if kind == 0 else rng.integers(0, 4, 200).astype(np.float64)
+        for periodic in (True, False):
+            check(ctx, workload(n, kind, periodic, pts, param, name=f"dup{kind}"))
+
+
+def test_sites_on_domain_faces(ctx):
+    n = (24, 20, 16)
+    L = np.array(n, dtype=np.float64)
+    pts = []
+    for x in (0.0, np.nextafter(L[0], 0), 12.0):
+        for y in (0.0, np.nextafter(L[1], 0), 10.0):
+            for z in (0.0, np.nextafter(L[2], 0), 8.0):
+                pts.append((x, y, z))
+    pts = np.array(pts)
+    for kind in (0, 1, 2):
+        param = None if kind == 0 else np.arange(len(pts), dtype=np.float64) % 5
+        for periodic in (True, False):
+            check(ctx, workload(n, kind, periodic, pts, param, name=f"faces{kind}"))
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_single_site_and_clusters(ctx, kind, periodic):
+    rng = np.random.default_rng(9)
+    n = (70, 45, 33)
+    one = workload(n, kind, periodic, [[3.3, 40.1, 20.7]], None if kind == 0 else [1.5], 0.6)
+    check(ctx, one)
+    pts = rng.uniform(0, 6.0, (40, 3))          # all sites in one corner: huge cells
+    param = None if kind == 0 else rng.uniform(0, 3, 40)
+    check(ctx, workload(n, kind, periodic, pts, param, 1.7))
+
+
+def test_more_sites_than_voxels(ctx):
+    rng = np.random.default_rng(11)
+    for d, n in ((3, (24, 24, 24)), (2, (90, 70))):
+        ns = 20_000
+        pts = I.uniform_sites(rng, ns, [float(v) for v in n])
+        for kind in (0, 1, 2):
+            param = None if kind == 0 else rng.uniform(0, 1, ns)
+            check(ctx, workload(n, kind, kind != 1, pts, param, 1.0, name=f"dense{d}{kind}"))
+
+
+def test_thin_grids(ctx):
+    rng = np.random.default_rng(12)
+    for n in ((1, 300), (300, 1), (1, 1, 500), (500, 1, 1), (1, 200, 3), (9, 1, 130)):
+        pts = I.uniform_sites(rng, 17, [float(v) for v in n])
+        for kind in (0, 1, 2):
+            param = None if kind == 0 else rng.uniform(0, 5, 17)
+            for periodic in (True, False):
+                check(ctx, workload(n, kind, periodic, pts, param, 1.0, name=f"thin{n}"))
+
+
+def test_dominant_weight_and_swallowed_sites(ctx):
+    rng = np.random.default_rng(13)
+    n = (48, 40, 36)
+    ns = 150
+    pts = I.uniform_sites(rng, ns, [float(v) for v in n])
+    w = rng.uniform(0, 20, ns)
+    w[7] = 3000.0                       # one huge power-distance bubble
+    w[8] = -500.0                       # and a negative weight
+    for periodic in (True, False):
+        check(ctx, workload(n, 1, periodic, pts, w, name="lag_dominant"))
+    t = rng.uniform(0, 3, ns)
+    t[::5] += 40.0                      # late sites, mostly swallowed
+    for g in (1.0, 3.7, 0.25):
+        for periodic in (True, False):
+            check(ctx, workload(n, 2, periodic, pts, t, g, name=f"jm_swallow{g}"))
+
+
+def test_periodic_half_period_boundary(ctx):
+    # |s - x| == L/2 exactly: both images are at the same distance.
+    n = (8, 8, 8)
+    pts = np.array([[0.5, 0.5, 0.5], [4.5, 0.5, 0.5], [0.5, 4.5, 4.5], [4.5, 4.5, 0.5]])
+    for kind in (0, 1, 2):
+        param = None if kind == 0 else np.zeros(4)
+        check(ctx, workload(n, kind, True, pts, param, name="halfL"))
+
+
+def test_invalid_sites_give_minus_one(ctx):
+    import torch
+    from gpu_util import to_dev
+    rng = np.random.default_rng(14)
+    n = (20, 20, 20)
+    for bad in (20.0, -0.5, float("nan"), float("inf")):
+        pts = I.uniform_sites(rng, 30, [20.0] * 3)
+        pts[11, 1] = bad
+        w = workload(n, 0, True, pts)
+        lab, st = run_device(ctx, w, status=True)
+        assert st == 5
+        assert np.all(lab == -1)
+    # a non-finite parameter
+    pts = I.uniform_sites(rng, 30, [20.0] * 3)
+    t = np.zeros(30)
+    t[3] = float("nan")
+    lab, st = run_device(ctx, workload(n, 2, False, pts, t), status=True)
+    assert st == 5 and np.all(lab == -1)
+    # the context keeps working afterwards
+    check(ctx, workload(n, 0, True, I.uniform_sites(rng, 30, [20.0] * 3)))
+
+
+def test_invalid_scalars_raise_before_launch(ctx):
+    import torch
+    from paper_2201_13234_amd import vtess
+    from gpu_util import to_dev
+    w = workload((8, 8, 8), 2, True, np.full((3, 3), 1.0), np.zeros(3), growth=0.0)
+    with pytest.raises(vtess.VtError) as e:
+        ctx.tessellate(to_dev(w))
+    assert e.value.code == vtess.ERR_INVALID
+    w = workload((8, 8, 8), 1, True, np.full((3, 3), 1.0), None)
+    with pytest.raises(vtess.VtError):
+        ctx.tessellate(to_dev(w))
+
+
+def test_deterministic(ctx):
+    w = I.make((100, 90, 80), 1, False, 3000, 15)
+    a = run_device(ctx, w)
+    b = run_device(ctx, w)
+    assert np.array_equal(a, b)
+
+
+def test_numerics_probe_is_ieee(ctx):
+    # eq. JMAK2 needs a correctly rounded sqrt and division: compare the device
+    # results with numpy's (IEEE binary64) bit for bit.
+    import torch
+    rng = np.random.default_rng(15)
+    x = np.concatenate([rng.uniform(0, 1e6, 400_000), rng.uniform(0, 4, 400_000),
+                        np.exp(rng.uniform(-700, 700, 200_000)),
+                        np.array([0.0, 1.0, 2.0, 4.0, 0.25, 5e-324, 2.2250738585072014e-308,
+                                  1.7976931348623157e308, 3.0, 1e-300])])
+    den = np.concatenate([rng.uniform(0.1, 10, x.size - 10), np.array([1.0, 3.0, 0.7, 1.3, 7.0, 1.0,
+                                                                      1.0, 2.0, 3.0, 0.3])])
+    dx = torch.from_numpy(x).cuda()
+    dd = torch.from_numpy(den).cuda()
+    s, q = ctx.numerics_probe(dx, dd)
+    torch.cuda.synchronize()
+    assert np.array_equal(s.cpu().numpy().view(np.uint64), np.sqrt(x).view(np.uint64))
+    assert np.array_equal(q.cpu().numpy().view(np.uint64), (x / den).view(np.uint64))
+
+
+# ------------------------------------------------------------ full-size configs
+
+@pytest.mark.parametrize("name", ["M2", "M3", "M4"])
+def test_full_size_config(ctx, name):
+    w = I.CONFIGS[name]()
+    print(f"[{name}] {w.name}: device run", flush=True)
+    got, st = run_device(ctx, w, status=True)
+    assert st == 0
+    print(f"[{name}] oracle run", flush=True)
+    ref = run_oracle(w)
+    assert np.array_equal(got, ref), describe_mismatch(got, ref)
