@@ -208,13 +208,13 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d, bool batch)
     d->nbins = (int32_t)nbins;
 
     const vt::TileShape sh = vt::shape_of(j->ndim, cfg);
-    const int T[3] = {sh.run * sh.lx, sh.ly, j->ndim == 3 ? sh.lz : 1};
-    int64_t ntiles = 1;
+    const int R[3] = {sh.run * sh.lx * sh.rx, sh.ly * sh.ry, j->ndim == 3 ? sh.lz * sh.rz : 1};
+    int64_t nregions = 1;
     for (int a = 0; a < 3; ++a) {
-        d->nt[a] = (d->n[a] + T[a] - 1) / T[a];
-        ntiles *= d->nt[a];
+        d->nr[a] = (d->n[a] + R[a] - 1) / R[a];
+        nregions *= d->nr[a];
     }
-    d->ntiles = ntiles;
+    d->nregions = nregions;
     d->coords = j->coords;
     d->param = j->param;
     d->labels = j->labels;
@@ -262,7 +262,8 @@ vt_status ensure_pinned(vt_ctx* ctx, size_t bytes)
 
 // Binning arrays of one job carved from `base` (device memory).
 struct SingleLayout {
-    size_t pbound, status, bin_count, bin_start, site_bin, site_rank, sites, sidx, partial, total;
+    size_t pbound, status, ovf_count, bin_count, bin_start, site_bin, site_rank, sites, sidx, partial, ovf_list,
+        total;
     int64_t partial_cap;
 };
 
@@ -270,9 +271,11 @@ SingleLayout single_layout(const JobDev& d)
 {
     SingleLayout L;
     Carver c;
+    // pbound, status, overflow count and bin counts are zeroed together
     L.pbound = c.take<unsigned long long>(2);
-    L.status = c.take<int32_t>(1, 8);
-    L.bin_count = c.take<int32_t>(d.nbins, 8);
+    L.status = c.take<int32_t>(1, 4);
+    L.ovf_count = c.take<int32_t>(1, 4);
+    L.bin_count = c.take<int32_t>(d.nbins, 4);
     L.bin_start = c.take<int32_t>((int64_t)d.nbins + 1);
     L.site_bin = c.take<int32_t>(d.nsites);
     L.site_rank = c.take<int32_t>(d.nsites);
@@ -280,6 +283,7 @@ SingleLayout single_layout(const JobDev& d)
     L.sidx = c.take<int32_t>(d.nsites);
     L.partial_cap = vt::scan_partials_needed((int64_t)d.nbins);
     L.partial = c.take<int32_t>(L.partial_cap);
+    L.ovf_list = c.take<int32_t>(d.nregions * 4);
     L.total = align_up(c.off, 256);
     return L;
 }
@@ -294,6 +298,8 @@ void bind_single(JobDev& d, char* base, const SingleLayout& L, int32_t* status_d
     d.site_rank = (int32_t*)(base + L.site_rank);
     d.sites = (double4*)(base + L.sites);
     d.sidx = (int32_t*)(base + L.sidx);
+    d.ovf_count = (int32_t*)(base + L.ovf_count);
+    d.ovf_list = (int32_t*)(base + L.ovf_list);
 }
 
 __global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra)
@@ -343,29 +349,28 @@ __global__ void k_copy_status(const JobDev* jobs, int n, int32_t* out)
         out[i] = *jobs[i].status;
 }
 
-// Uploads a job table through the pinned staging buffer into a stream-ordered
-// device allocation (freed by the caller after the launches that read it).
-vt_status upload_table(vt_ctx* ctx, const std::vector<JobDev>& host, const std::vector<int64_t>* prefix,
-                       void** dev_out, size_t* prefix_off, hipStream_t s)
+// Stream-ordered device allocation for per-call tables (freed by the caller
+// with hipFreeAsync after the launches that read it).
+vt_status alloc_table(size_t bytes, hipStream_t s, void** dev)
 {
-    size_t jb = align_up(host.size() * sizeof(JobDev), 256);
-    size_t pb = prefix ? prefix->size() * sizeof(int64_t) : 0;
-    size_t bytes = jb + pb;
+    *dev = nullptr;
+    if (hipMallocAsync(dev, bytes, s) != hipSuccess) {
+        *dev = nullptr;
+        return fail(VT_ERR_NOMEM, "table allocation failed");
+    }
+    return VT_OK;
+}
+
+// Copies `bytes` of host data to the device through the pinned staging buffer.
+vt_status stage_copy(vt_ctx* ctx, void* dev, const void* host, size_t bytes, hipStream_t s)
+{
     vt_status st = ensure_pinned(ctx, bytes);
     if (st != VT_OK)
         return st;
-    std::memcpy(ctx->pinned, host.data(), host.size() * sizeof(JobDev));
-    if (prefix)
-        std::memcpy((char*)ctx->pinned + jb, prefix->data(), pb);
-    void* dev = nullptr;
-    if (hipMallocAsync(&dev, bytes, s) != hipSuccess)
-        return fail(VT_ERR_NOMEM, "job table allocation failed");
+    std::memcpy(ctx->pinned, host, bytes);
     VT_HIP(hipMemcpyAsync(dev, ctx->pinned, bytes, hipMemcpyHostToDevice, s));
     VT_HIP(hipEventRecord(ctx->staging_evt, s));
     ctx->staging_used = true;
-    *dev_out = dev;
-    if (prefix_off)
-        *prefix_off = jb;
     return VT_OK;
 }
 
@@ -497,6 +502,7 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     if (ev[1])
         VT_HIP(hipEventRecord(ev[1], s));
     VT_HIP(vt::launch_label_single(d, s));
+    VT_HIP(vt::launch_label_fallback(d, s));
     if (ev[2])
         VT_HIP(hipEventRecord(ev[2], s));
     return VT_OK;
@@ -548,8 +554,8 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
         if (st != VT_OK)
             return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
         prefix[i + 1] = prefix[i] + host[i].nsites;
-        host[i].tile_begin = total_tiles;
-        total_tiles += host[i].ntiles;
+        host[i].region_begin = total_tiles;
+        total_tiles += host[i].nregions;
         total_bins += host[i].nbins;
     }
     const int64_t total_sites = prefix[njobs];
@@ -563,6 +569,7 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     const size_t o_st = c.take<int32_t>(njobs, 8);
     const size_t o_cnt = c.take<int32_t>(total_bins, 4);
     const size_t o_ctr = c.take<int32_t>(8, 4);
+    const size_t o_ovfc = c.take<int32_t>(1, 4);
     const size_t zero_end = c.off;
     const size_t o_start = c.take<int32_t>(total_bins + 1);
     const size_t o_sbin = c.take<int32_t>(total_sites);
@@ -571,6 +578,7 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     const size_t o_sidx = c.take<int32_t>(total_sites);
     const int64_t pcap = vt::scan_partials_needed(total_bins);
     const size_t o_part = c.take<int32_t>(pcap);
+    const size_t o_ovf = c.take<int32_t>(total_tiles * 4);
     vt_status st = ensure_scratch(ctx, align_up(c.off, 256));
     if (st != VT_OK)
         return st;
@@ -586,14 +594,22 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
         d.site_rank = (int32_t*)(base + o_srank) + prefix[i];
         d.sites = (double4*)(base + o_sites);
         d.sidx = (int32_t*)(base + o_sidx);
+        d.ovf_count = (int32_t*)(base + o_ovfc);
+        d.ovf_list = (int32_t*)(base + o_ovf);
         bin_off += d.nbins;
     }
+    // job table and site prefix in one stream-ordered allocation
+    const size_t jb = align_up(host.size() * sizeof(JobDev), 256);
+    std::vector<char> blob(jb + prefix.size() * sizeof(int64_t));
+    std::memcpy(blob.data(), host.data(), host.size() * sizeof(JobDev));
+    std::memcpy(blob.data() + jb, prefix.data(), prefix.size() * sizeof(int64_t));
     void* table = nullptr;
-    size_t poff = 0;
-    if ((st = upload_table(ctx, host, &prefix, &table, &poff, s)) != VT_OK)
+    if ((st = alloc_table(blob.size(), s, &table)) != VT_OK)
+        return st;
+    if ((st = stage_copy(ctx, table, blob.data(), blob.size(), s)) != VT_OK)
         return st;
     const JobDev* djobs = (const JobDev*)table;
-    const int64_t* dprefix = (const int64_t*)((char*)table + poff);
+    const int64_t* dprefix = (const int64_t*)((char*)table + jb);
     VT_HIP(launch_prepare((int32_t*)(base + o_pb), (int64_t)((zero_end - o_pb) / 4), nullptr, s));
     if (status_dev)
         VT_HIP(vt::launch_fill_i32(status_dev, njobs, 0, s));
@@ -603,7 +619,8 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     VT_HIP(vt::launch_scan((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins,
                            (int32_t*)(base + o_part), pcap, s));
     VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
-    VT_HIP(vt::launch_label_batch(djobs, njobs, 0, total_tiles, (int32_t*)(base + o_ctr), ctx->batch_grid, s));
+    VT_HIP(vt::launch_label_batch(djobs, njobs, total_tiles, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovf),
+                                  (int32_t*)(base + o_ovfc), ctx->batch_grid, s));
     VT_HIP(hipFreeAsync(table, s));
     return VT_OK;
 }
@@ -649,20 +666,30 @@ vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n, int32_t* 
         if (!bins[i])
             return fail(VT_ERR_INVALID, "bins[" + std::to_string(i) + "] is NULL");
         host[i] = bins[i]->job;
-        host[i].tile_begin = total_tiles;
-        total_tiles += host[i].ntiles;
+        host[i].region_begin = total_tiles;
+        total_tiles += host[i].nregions;
     }
     VT_HIP(hipSetDevice(ctx->device));
-    // Table followed by the eight tile counters, zeroed on the device.
-    host.push_back(JobDev());
-    std::memset(&host.back(), 0, sizeof(JobDev));
+    // One stream-ordered allocation: job table, then eight region counters and
+    // the overflow count (zeroed on the device), then the overflow list.
+    const size_t jb = align_up((size_t)n * sizeof(JobDev), 256);
+    const size_t bytes = jb + 16 * sizeof(int32_t) + (size_t)total_tiles * 4 * sizeof(int32_t);
     void* table = nullptr;
-    vt_status st = upload_table(ctx, host, nullptr, &table, nullptr, s);
+    vt_status st = alloc_table(bytes, s, &table);
     if (st != VT_OK)
         return st;
-    int32_t* counters = (int32_t*)((char*)table + (size_t)n * sizeof(JobDev));
-    VT_HIP(vt::launch_fill_i32(counters, 8, 0, s));
-    VT_HIP(vt::launch_label_batch((const JobDev*)table, n, 0, total_tiles, counters, ctx->batch_grid, s));
+    int32_t* counters = (int32_t*)((char*)table + jb);
+    int32_t* ovf_count = counters + 8;
+    int32_t* ovf_list = counters + 16;
+    for (JobDev& d : host) {
+        d.ovf_count = ovf_count;
+        d.ovf_list = ovf_list;
+    }
+    if ((st = stage_copy(ctx, table, host.data(), (size_t)n * sizeof(JobDev), s)) != VT_OK)
+        return st;
+    VT_HIP(vt::launch_fill_i32(counters, 9, 0, s));
+    VT_HIP(vt::launch_label_batch((const JobDev*)table, n, total_tiles, counters, ovf_list, ovf_count,
+                                  ctx->batch_grid, s));
     if (status_dev)
         k_copy_status<<<(n + 255) / 256, 256, 0, s>>>((const JobDev*)table, n, status_dev);
     VT_HIP(hipGetLastError());

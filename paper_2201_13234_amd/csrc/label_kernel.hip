@@ -1,54 +1,102 @@
-// label_kernel.hip -- per-voxel argmin of the diagram's key over the sites,
-// one wavefront (64 lanes) per voxel tile.
+// label_kernel.hip -- per-voxel argmin of the diagram's key over the sites.
 //
 // What is computed (Sec. 2, Sec. 3 problem statement, App. A): for every voxel
 // centre x, the lowest index s minimising
 //     Voronoi q,  Laguerre q - w_s,  Johnson-Mehl t_s + sqrt(q) / v,
 // q = d0*d0 + (d1*d1 + d2*d2) with minimum-image differences for periodic
-// boundaries, each operation rounded once in binary64 (build flags keep the
+// boundaries, each operation rounded once in binary64 (the build keeps the
 // compiler from contracting into fused multiply-add).
 //
 // How (our GPU design, not the paper's CPU ball scheme):
-//   1. Gather.  Walk the uniform bin grid outward from the tile, one shell of
-//      bins at a time.  Each gathered site gets a lower and an upper bound of
-//      its key over the tile's box of voxel centres; UB = min over gathered
-//      sites of their upper bound bounds every voxel's winning key.  Sites
-//      whose lower bound exceeds UB are dropped at once.  The walk stops when
-//      a lower bound of the key of every site outside the visited bins
-//      (gap^2, gap^2 - max w, min t + gap / v) exceeds UB, or when every bin has
-//      been visited.
-//   2. Prune.  A site is dropped if another site beats it on the whole tile:
-//      for Voronoi and Laguerre the key difference of two sites is linear in x,
-//      so its minimum over the box is at a corner; for Johnson-Mehl a bound of
-//      the difference of distances is used.
-//   3. Sort the survivors by site index and evaluate them for every voxel of
-//      the lane's run with the exact key and a strict '<' -- the paper's
-//      brute-force loop restricted to the survivors, which gives the lowest
-//      index on ties.
+//   A workgroup of four wavefronts owns a region of four voxel tiles.
+//   1. Region gather (whole workgroup).  The bins around the region are loaded
+//      into LDS, many per round.  Every site gets an upper bound of its key
+//      over the region's box of voxel centres; UB = the smallest of them bounds
+//      the winning key of every voxel of the region.  A face of the visited
+//      bin box is moved outward until the sites beyond it provably lose:
+//      gap^2 > UB (Voronoi), gap^2 - max w > UB (Laguerre),
+//      min t + gap / v > UB (Johnson-Mehl).
+//   2. Tile pruning (one wavefront per tile).  Sites whose lower bound over the
+//      tile exceeds the tile's own UB are dropped, then every site that another
+//      site beats on the whole tile: the key difference of two sites is linear
+//      in x for Voronoi and Laguerre, so its minimum over the box is at a
+//      corner; for Johnson-Mehl a bound of the difference of distances is used.
+//   3. Exact evaluation.  The survivors, sorted by site index, are evaluated
+//      at every voxel of the lane's run with the exact key and a strict '<':
+//      the paper's brute-force loop restricted to the survivors, which keeps
+//      the lowest index on ties.
 // Every bound test keeps a margin of 2^-36 times the problem's key scale, far
 // above the rounding error of any computed key, so a dropped site's computed
-// key is strictly larger than the winner's at every voxel of the tile: the
-// labels equal brute force bit for bit.
+// key is strictly larger than the winner's at every voxel: the labels equal
+// brute force bit for bit.  A region whose sites do not fit in LDS falls back
+// to a per-tile walk that evaluates its candidates in batches.
 #include "vt_internal.h"
 
 namespace vt {
 
 namespace {
 
-struct WaveLds {
-    double4 cs[CAP];   // candidate site {x, y, z, param}
-    double2 cb[CAP];   // {lower, upper} bound of the key over the tile box
-    double2 cq[CAP];   // {min, max} distance to the tile box
-    int2 cm[CAP];      // {site index, flags}
-    int bcnt[WAVE];    // inclusive prefix of site counts of the current bin chunk
-    int bsrc[WAVE];    // first sorted-site position of each bin of the chunk
-};
+constexpr int NW = 4;          // wavefronts per workgroup = tiles per region
+constexpr int NT = NW * WAVE;  // threads per workgroup
+constexpr int CAP_R = 384;     // region candidate capacity (LDS)
+constexpr int CAP_S = 64;      // tile candidate capacity (LDS, per wavefront)
+constexpr int CAP_F = 64;      // fallback per-tile capacity (LDS, per wavefront)
 
 // flags: wrap code per axis in bits 2a..2a+1 (0 none, 1 subtract L, 2 add L),
 // bit 6 = some axis needs a per-voxel minimum-image test.
 constexpr int FL_GENERIC = 64;
 
 enum { KV = 0, KL = 1, KJM = 2, KJD = 3 };  // Johnson-Mehl: multiply by exact 1/v, or divide
+
+struct TileLds {
+    double4 cs[CAP_S];  // site {x, y, z, param}
+    double2 cq[CAP_S];  // {min, max} distance to the tile box
+    int2 cm[CAP_S];     // {site index, flags}
+};
+
+struct RegionLds {
+    double4 rs[CAP_R];
+    int ri[CAP_R];
+    int wsum[NW];
+    double wred[NW];
+    int flag;
+};
+
+struct FallbackLds {
+    double4 cs[CAP_F];
+    double2 cb[CAP_F];  // {lower, upper} bound of the key over the tile box
+    double2 cq[CAP_F];
+    int2 cm[CAP_F];
+    int bcnt[WAVE];
+    int bsrc[WAVE];
+};
+
+struct Smem {
+    struct {
+        RegionLds reg;
+        TileLds tile[NW];
+    } r;
+};
+
+struct TileBox {
+    double lo[3], hi[3];  // box of voxel centres
+};
+
+struct JobConst {
+    double M;        // pruning margin
+    double pmax, pmin;
+    double v, rv;    // growth rate and its reciprocal
+    double sqrtL2;   // sqrt(sum L_a^2)
+};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ inline int wrap_code(double d, double H) { return d >= H ? 1 : (d < -H ? 2 : 0); }
 __device__ inline double code_off(int c, double L) { return c == 1 ? -L : (c == 2 ? L : 0.0); }
@@ -85,6 +133,39 @@ __device__ inline unsigned long long lanes_below(int lane)
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+__device__ inline int block_excl_scan(int v, int& total, int* wsum, int tid)
+{
+    const int lane = tid & (WAVE - 1), w = tid / WAVE;
+    const int inc = wave_inclusive_add(v, lane);
+    if (lane == WAVE - 1)
+        wsum[w] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int s = wsum[k];
+        off += k < w ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+__device__ inline double block_min(double v, double* wred, int tid)
+{
+    v = wave_min(v);
+    if ((tid & (WAVE - 1)) == 0)
+        wred[tid / WAVE] = v;
+    __syncthreads();
+    double r = wred[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k)
+        r = fmin(r, wred[k]);
+    __syncthreads();
+    return r;
+}
+
 template <int KIND>
 __device__ inline double dist_key(double q, double p, double v, double rv)
 {
@@ -97,138 +178,31 @@ __device__ inline double dist_key(double q, double p, double v, double rv)
     return p + sqrt(q) / v;
 }
 
-struct TileBox {
-    double lo[3], hi[3];  // box of voxel centres
-};
-
-// Keeps the entries of the wave's list whose predicate holds, in order.
-// keep0/keep1 refer to entries lane and lane + 64.
-__device__ inline int compact(WaveLds& S, int nc, bool keep0, bool keep1, int lane)
+template <int KIND>
+__device__ inline JobConst job_const(const JobDev& J, int dim)
 {
-    double4 s0, s1;
-    double2 b0, b1, q0, q1;
-    int2 m0, m1;
-    const bool v0 = lane < nc, v1 = lane + WAVE < nc;
-    keep0 = keep0 && v0;
-    keep1 = keep1 && v1;
-    if (v0) {
-        s0 = S.cs[lane];
-        b0 = S.cb[lane];
-        q0 = S.cq[lane];
-        m0 = S.cm[lane];
+    JobConst C;
+    double sumL2 = 0.0;
+    for (int a = 0; a < dim; ++a)
+        sumL2 += J.L[a] * J.L[a];
+    C.sqrtL2 = sqrt(sumL2);
+    C.v = J.growth;
+    C.rv = J.rgrowth;
+    C.pmax = C.pmin = 0.0;
+    if (KIND != KV) {
+        C.pmax = from_ordered(J.pbound[0]);
+        C.pmin = -from_ordered(J.pbound[1]);
     }
-    if (v1) {
-        s1 = S.cs[lane + WAVE];
-        b1 = S.cb[lane + WAVE];
-        q1 = S.cq[lane + WAVE];
-        m1 = S.cm[lane + WAVE];
-    }
-    __syncthreads();
-    const unsigned long long k0 = __ballot(keep0), k1 = __ballot(keep1);
-    const int n0 = __popcll(k0);
-    if (keep0) {
-        int d = __popcll(k0 & lanes_below(lane));
-        S.cs[d] = s0;
-        S.cb[d] = b0;
-        S.cq[d] = q0;
-        S.cm[d] = m0;
-    }
-    if (keep1) {
-        int d = n0 + __popcll(k1 & lanes_below(lane));
-        S.cs[d] = s1;
-        S.cb[d] = b1;
-        S.cq[d] = q1;
-        S.cm[d] = m1;
-    }
-    __syncthreads();
-    return n0 + __popcll(k1);
+    const double pabs = fmax(fabs(C.pmax), fabs(C.pmin));
+    const double scale = (KIND == KV) ? sumL2 : (KIND == KL) ? sumL2 + 2.0 * pabs : C.sqrtL2 * C.rv + 2.0 * pabs;
+    C.M = scale * 0x1p-36;
+    return C;
 }
 
-// True if site c (entry e) loses to some other listed site on the whole box.
-template <int KIND, int DIM>
-__device__ inline bool dominated(const WaveLds& S, int nc, int e, const JobDev& J, const TileBox& B,
-                                 double M, double sumL2_sqrt, double rv)
+// Voxel-centre box of voxels [v0, ve] (ve clipped to the grid).
+template <int DIM>
+__device__ inline TileBox make_box(const JobDev& J, const int* v0, const int* ve)
 {
-    const double4 c = S.cs[e];
-    const int2 cm = S.cm[e];
-    const double2 cq = S.cq[e];
-    const double2 cb = S.cb[e];
-    const bool cgen = (cm.y & FL_GENERIC) != 0;
-    double sc[3] = {c.x, c.y, c.z};
-    if (!cgen)
-        for (int a = 0; a < DIM; ++a)
-            sc[a] += code_off((cm.y >> (2 * a)) & 3, J.L[a]);
-    bool dom = false;
-    for (int t = 0; t < nc; ++t) {
-        if (t == e)
-            continue;
-        const double4 o = S.cs[t];
-        const int2 om = S.cm[t];
-        if (KIND == KV || KIND == KL) {
-            if (cgen || (om.y & FL_GENERIC))
-                continue;
-            // key_c - key_t = sum_a (sc - so)(sc + so - 2 x_a) - w_c + w_t, linear in x
-            double so[3] = {o.x, o.y, o.z};
-            double D = 0.0;
-            for (int a = 0; a < DIM; ++a) {
-                so[a] += code_off((om.y >> (2 * a)) & 3, J.L[a]);
-                double al = sc[a] - so[a];
-                double xs = al > 0.0 ? B.hi[a] : B.lo[a];
-                D += al * ((sc[a] + so[a]) - 2.0 * xs);
-            }
-            if (KIND == KL)
-                D = D - c.w + o.w;
-            if (D > M)
-                dom = true;
-        } else {
-            // t_c + d_c/v - (t_t + d_t/v) >= (t_c - t_t) + lbd / v, lbd a lower
-            // bound of d_c - d_t over the box.
-            const double2 oq = S.cq[t];
-            double lbd = cq.x - oq.y;
-            if (!cgen && !(om.y & FL_GENERIC)) {
-                double Dq = 0.0;
-                for (int a = 0; a < DIM; ++a) {
-                    double so = (a == 0 ? o.x : (a == 1 ? o.y : o.z)) +
-                                code_off((om.y >> (2 * a)) & 3, J.L[a]);
-                    double al = sc[a] - so;
-                    double xs = al > 0.0 ? B.hi[a] : B.lo[a];
-                    Dq += al * ((sc[a] + so) - 2.0 * xs);
-                }
-                const double floor_den = sumL2_sqrt * 0x1p-10;
-                if (Dq > 0.0) {
-                    double den = cq.y + oq.y;
-                    if (den >= floor_den)
-                        lbd = fmax(lbd, Dq / den);
-                } else {
-                    double den = cq.x + oq.x;
-                    if (den >= floor_den)
-                        lbd = fmax(lbd, Dq / den);
-                }
-            }
-            double f = (c.w - o.w) + lbd * rv;
-            if (f > M)
-                dom = true;
-        }
-        (void)cb;
-    }
-    return dom;
-}
-
-template <int KIND, int DIM, int RUN, int LX, int LY, int LZ>
-__device__ void label_tile(const JobDev& J, int64_t tile, WaveLds& S, const int lane)
-{
-    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
-    static_assert(LX * LY * LZ == WAVE, "64 lanes per tile");
-    const bool periodic = J.bc != 0;
-
-    // ---- tile and lane geometry
-    const int tx = (int)(tile % J.nt[0]);
-    const int64_t rr = tile / J.nt[0];
-    const int ty = (int)(rr % J.nt[1]);
-    const int tz = (int)(rr / J.nt[1]);
-    const int v0[3] = {tx * TX, ty * TY, tz * TZ};
-    const int ve[3] = {min(v0[0] + TX, J.n[0]) - 1, min(v0[1] + TY, J.n[1]) - 1,
-                       min(v0[2] + TZ, J.n[2]) - 1};
     TileBox B;
     for (int a = 0; a < 3; ++a) {
         if (a < DIM) {
@@ -238,14 +212,547 @@ __device__ void label_tile(const JobDev& J, int64_t tile, WaveLds& S, const int 
             B.lo[a] = B.hi[a] = 0.0;
         }
     }
+    return B;
+}
+
+// Bounds of site s over box B: wrap flags, lower/upper bound of the key and
+// min/max distance.
+template <int KIND, int DIM>
+__device__ inline void box_bounds(const JobDev& J, const JobConst& C, const TileBox& B, bool periodic,
+                                  const double4& s, int& flags, double& lb, double& ub, double& dmn,
+                                  double& dmx)
+{
+    const double sc[3] = {s.x, s.y, s.z};
+    double qmin = 0.0, qmax = 0.0;
+    flags = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double sg = sc[a], dmin, dmax;
+        bool gen = false;
+        if (periodic) {
+            const int c1 = wrap_code(sc[a] - B.lo[a], J.H[a]);
+            const int c2 = wrap_code(sc[a] - B.hi[a], J.H[a]);
+            if (c1 == c2) {
+                flags |= c1 << (2 * a);
+                sg = sc[a] + code_off(c1, J.L[a]);
+            } else {
+                gen = true;
+            }
+        }
+        if (gen) {
+            flags |= FL_GENERIC;
+            dmin = 0.0;
+            dmax = J.H[a];
+        } else {
+            dmin = fmax(0.0, fmax(B.lo[a] - sg, sg - B.hi[a]));
+            dmax = fmax(fabs(sg - B.lo[a]), fabs(sg - B.hi[a]));
+        }
+        qmin += dmin * dmin;
+        qmax += dmax * dmax;
+    }
+    dmn = sqrt(qmin);
+    dmx = sqrt(qmax);
+    if (KIND == KV) {
+        lb = qmin;
+        ub = qmax;
+    } else if (KIND == KL) {
+        lb = qmin - s.w;
+        ub = qmax - s.w;
+    } else {
+        lb = s.w + dmn * C.rv;
+        ub = s.w + dmx * C.rv;
+    }
+}
+
+// Upper bound only (cheaper: no flags, no lower bound).
+template <int KIND, int DIM>
+__device__ inline double box_upper(const JobDev& J, const JobConst& C, const TileBox& B, bool periodic,
+                                   const double4& s)
+{
+    const double sc[3] = {s.x, s.y, s.z};
+    double qmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double dmax;
+        if (periodic) {
+            const int c1 = wrap_code(sc[a] - B.lo[a], J.H[a]);
+            const int c2 = wrap_code(sc[a] - B.hi[a], J.H[a]);
+            const double sg = sc[a] + code_off(c1, J.L[a]);
+            dmax = c1 == c2 ? fmax(fabs(sg - B.lo[a]), fabs(sg - B.hi[a])) : J.H[a];
+        } else {
+            dmax = fmax(fabs(sc[a] - B.lo[a]), fabs(sc[a] - B.hi[a]));
+        }
+        qmax += dmax * dmax;
+    }
+    if (KIND == KV)
+        return qmax;
+    if (KIND == KL)
+        return qmax - s.w;
+    return s.w + sqrt(qmax) * C.rv;
+}
+
+// Distance a face of the visited bin box must keep from the box of voxel
+// centres so that every site beyond it provably loses (key > UB + margin).
+template <int KIND>
+__device__ inline double needed_reach(const JobConst& C, double UB)
+{
+    const double t = UB + C.M;
+    if (KIND == KV)
+        return sqrt(fmax(t, 0.0));
+    if (KIND == KL)
+        return sqrt(fmax(t + C.pmax, 0.0));
+    return fmax(t - C.pmin, 0.0) * C.v;
+}
+
+template <int KIND>
+__device__ inline double outside_lower_bound(const JobConst& C, double G)
+{
+    if (KIND == KV)
+        return G * G;
+    if (KIND == KL)
+        return G * G - C.pmax;
+    return C.pmin + G * C.rv;
+}
+
+// Gap between the box of voxel centres and the low / high face of the bin
+// box [blo, bhi] along axis a (+inf where no site can lie beyond the face).
+__device__ inline double gap_low(const JobDev& J, const TileBox& B, int a, int blo, bool periodic)
+{
+    if (!periodic && blo <= 0)
+        return __builtin_inf();
+    return B.lo[a] - ((double)blo * J.bs[a] + J.L[a] * 0x1p-30);
+}
+
+__device__ inline double gap_high(const JobDev& J, const TileBox& B, int a, int bhi, bool periodic)
+{
+    if (!periodic && bhi >= J.nb[a] - 1)
+        return __builtin_inf();
+    return ((double)(bhi + 1) * J.bs[a] - J.L[a] * 0x1p-30) - B.hi[a];
+}
+
+// True if the listed site e loses to some other listed site on the whole box.
+template <int KIND, int DIM>
+__device__ inline bool dominated(const double4* cs, const int2* cm, const double2* cq, int nc, int e,
+                                 const JobDev& J, const JobConst& C, const TileBox& B)
+{
+    const double4 c = cs[e];
+    const int2 me = cm[e];
+    const double2 mq = cq[e];
+    const bool cgen = (me.y & FL_GENERIC) != 0;
+    double sc[3] = {c.x, c.y, c.z};
+    if (!cgen)
+        for (int a = 0; a < DIM; ++a)
+            sc[a] += code_off((me.y >> (2 * a)) & 3, J.L[a]);
+    bool dom = false;
+    for (int t = 0; t < nc; ++t) {
+        const double4 o = cs[t];
+        const int2 om = cm[t];
+        if (t == e)
+            continue;
+        if (KIND == KV || KIND == KL) {
+            if (cgen || (om.y & FL_GENERIC))
+                continue;
+            // key_c - key_t = sum_a (sc - so)(sc + so - 2 x_a) - w_c + w_t, linear in x
+            const double oc[3] = {o.x, o.y, o.z};
+            double D = 0.0;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                const double so = oc[a] + code_off((om.y >> (2 * a)) & 3, J.L[a]);
+                const double al = sc[a] - so;
+                const double xs = al > 0.0 ? B.hi[a] : B.lo[a];
+                D += al * ((sc[a] + so) - 2.0 * xs);
+            }
+            if (KIND == KL)
+                D = D - c.w + o.w;
+            dom = dom || D > C.M;
+        } else {
+            // t_c + d_c/v - (t_t + d_t/v) >= (t_c - t_t) + lbd / v, lbd a lower
+            // bound of d_c - d_t over the box.
+            const double2 oq = cq[t];
+            double lbd = mq.x - oq.y;
+            if (!cgen && !(om.y & FL_GENERIC)) {
+                const double oc[3] = {o.x, o.y, o.z};
+                double Dq = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const double so = oc[a] + code_off((om.y >> (2 * a)) & 3, J.L[a]);
+                    const double al = sc[a] - so;
+                    const double xs = al > 0.0 ? B.hi[a] : B.lo[a];
+                    Dq += al * ((sc[a] + so) - 2.0 * xs);
+                }
+                const double floor_den = C.sqrtL2 * 0x1p-10;
+                const double den = Dq > 0.0 ? mq.y + oq.y : mq.x + oq.x;
+                if (den >= floor_den)
+                    lbd = fmax(lbd, Dq / den);
+            }
+            dom = dom || ((c.w - o.w) + lbd * C.rv) > C.M;
+        }
+    }
+    return dom;
+}
+
+// Drops dominated entries of a wavefront's list (one entry per lane, nc <= 64),
+// then sorts the rest by site index.  Returns the new count.
+template <int KIND, int DIM>
+__device__ inline int prune_and_sort(double4* cs, int2* cm, double2* cq, int nc, int lane, const JobDev& J,
+                                     const JobConst& C, const TileBox& B)
+{
+    const bool mine = lane < nc;
+    bool keep = mine;
+    if (nc > 1 && mine)
+        keep = !dominated<KIND, DIM>(cs, cm, cq, nc, lane, J, C, B);
+    double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+    int2 m = make_int2(0, 0);
+    if (mine) {
+        s = cs[lane];
+        m = cm[lane];
+    }
+    const unsigned long long km = __ballot(keep);
+    const int n = __popcll(km);
+    wave_sync();
+    // rank among the kept entries by site index (indices are distinct)
+    int rank = 0;
+    for (int t = 0; t < nc; ++t) {
+        const int it = cm[t].x;
+        rank += (((km >> t) & 1ull) != 0 && it < m.x) ? 1 : 0;
+    }
+    wave_sync();
+    if (keep) {
+        cs[rank] = s;
+        cm[rank] = m;
+    }
+    wave_sync();
+    return n;
+}
+
+// Exact keys of the listed sites (ascending index) at the lane's run.
+template <int KIND, int DIM, int RUN>
+__device__ inline void evaluate(const double4* cs, const int2* cm, int nc, bool lex, const JobDev& J,
+                                const JobConst& C, bool periodic, const double* xr, double yv, double zv,
+                                double* best, int* lab)
+{
+    for (int k = 0; k < nc; ++k) {
+        const double4 s = cs[k];
+        const int2 m = cm[k];
+        const int idx = m.x, fl = m.y;
+        double c;
+        double dxv[RUN];
+        if (fl == 0) {
+            const double dy = s.y - yv;
+            if (DIM == 3) {
+                const double dz = s.z - zv;
+                c = dy * dy + dz * dz;
+            } else {
+                c = dy * dy;
+            }
+#pragma unroll
+            for (int q = 0; q < RUN; ++q)
+                dxv[q] = s.x - xr[q];
+        } else if (!(fl & FL_GENERIC)) {
+            const double dy = (s.y - yv) + code_off((fl >> 2) & 3, J.L[1]);
+            if (DIM == 3) {
+                const double dz = (s.z - zv) + code_off((fl >> 4) & 3, J.L[2]);
+                c = dy * dy + dz * dz;
+            } else {
+                c = dy * dy;
+            }
+            const double ox = code_off(fl & 3, J.L[0]);
+#pragma unroll
+            for (int q = 0; q < RUN; ++q)
+                dxv[q] = (s.x - xr[q]) + ox;
+        } else {
+            const double dy = periodic ? min_image(s.y - yv, J.H[1], J.L[1]) : s.y - yv;
+            if (DIM == 3) {
+                const double dz = periodic ? min_image(s.z - zv, J.H[2], J.L[2]) : s.z - zv;
+                c = dy * dy + dz * dz;
+            } else {
+                c = dy * dy;
+            }
+#pragma unroll
+            for (int q = 0; q < RUN; ++q)
+                dxv[q] = periodic ? min_image(s.x - xr[q], J.H[0], J.L[0]) : s.x - xr[q];
+        }
+        if (!lex) {
+#pragma unroll
+            for (int q = 0; q < RUN; ++q) {
+                const double key = dist_key<KIND>(dxv[q] * dxv[q] + c, s.w, C.v, C.rv);
+                lab[q] = key < best[q] ? idx : lab[q];
+                best[q] = fmin(best[q], key);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < RUN; ++q) {
+                const double key = dist_key<KIND>(dxv[q] * dxv[q] + c, s.w, C.v, C.rv);
+                const bool lt = key < best[q] || (key == best[q] && idx < lab[q]);
+                lab[q] = lt ? idx : lab[q];
+                best[q] = fmin(best[q], key);
+            }
+        }
+    }
+}
+
+template <int RUN>
+__device__ inline void store_run(const JobDev& J, int mi, int mj, int mk, bool bad, int* lab)
+{
+    if (mj >= J.n[1] || mk >= J.n[2] || mi >= J.n[0])
+        return;
+    int32_t* out = J.labels + (int64_t)mi + (int64_t)J.n[0] * ((int64_t)mj + (int64_t)J.n[1] * mk);
+    if (bad) {
+#pragma unroll
+        for (int q = 0; q < RUN; ++q)
+            lab[q] = -1;
+    }
+    if (mi + RUN <= J.n[0] && ((uintptr_t)out & 15) == 0 && RUN % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < RUN; q += 4)
+            *(int4*)(out + q) = make_int4(lab[q], lab[q + 1], lab[q + 2], lab[q + 3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < RUN; ++q)
+            if (mi + q < J.n[0])
+                out[q] = lab[q];
+    }
+}
+
+// ------------------------------------------------ fallback: one tile alone
+
+// Walks the bins around one tile shell by shell, keeps the sites that can
+// win somewhere in the tile and evaluates them in batches of at most CAP_F
+// (the first batch with a strict '<' in index order, later ones with the
+// lexicographic (key, index) order).  Used when a region's sites overflow LDS.
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ>
+__device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0, FallbackLds& S, int lane,
+                              double* xr, double yv, double zv, double* best, int* lab)
+{
+    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
+    const bool periodic = J.bc != 0;
+    const int ve[3] = {min(v0[0] + TX, J.n[0]) - 1, min(v0[1] + TY, J.n[1]) - 1, min(v0[2] + TZ, J.n[2]) - 1};
+    const TileBox B = make_box<DIM>(J, v0, ve);
+    int blo[3], bhi[3], olo[3], ohi[3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < DIM) {
+            const int l = (int)(B.lo[a] * J.inv_bs[a]), h = (int)(B.hi[a] * J.inv_bs[a]);
+            blo[a] = max(0, min(l, J.nb[a] - 1));
+            bhi[a] = max(blo[a], min(h, J.nb[a] - 1));
+        } else {
+            blo[a] = bhi[a] = 0;
+        }
+        olo[a] = 1;
+        ohi[a] = 0;
+    }
+    int nbx = bhi[0] - blo[0] + 1, nby = bhi[1] - blo[1] + 1, nbz = bhi[2] - blo[2] + 1;
+    int64_t sh_total = (int64_t)nbx * nby * nbz, sh_pos = 0;
+    int ch_T = 0, ch_off = 0;
+    bool ch_live = false;
+    double UB = __builtin_inf();
+    int nc = 0;
+    bool lex = false, done = false;
+    for (;;) {
+        bool flush = false;
+        while (!done && !flush) {
+            if (!ch_live) {
+                if (sh_pos >= sh_total) {
+                    bool complete = true;
+                    double G = __builtin_inf();
+                    for (int a = 0; a < DIM; ++a) {
+                        const bool full = periodic ? (bhi[a] - blo[a] + 1 >= J.nb[a])
+                                                   : (blo[a] == 0 && bhi[a] == J.nb[a] - 1);
+                        if (full)
+                            continue;
+                        complete = false;
+                        G = fmin(G, fmin(gap_low(J, B, a, blo[a], periodic), gap_high(J, B, a, bhi[a], periodic)));
+                    }
+                    if (complete || outside_lower_bound<KIND>(C, fmax(G, 0.0)) > UB + C.M) {
+                        done = true;
+                        break;
+                    }
+                    for (int a = 0; a < DIM; ++a) {
+                        olo[a] = blo[a];
+                        ohi[a] = bhi[a];
+                        if (periodic) {
+                            if (bhi[a] - blo[a] + 1 < J.nb[a]) {
+                                blo[a] -= 1;
+                                bhi[a] += 1;
+                                if (bhi[a] - blo[a] + 1 > J.nb[a])
+                                    bhi[a] = blo[a] + J.nb[a] - 1;
+                            }
+                        } else {
+                            blo[a] = max(blo[a] - 1, 0);
+                            bhi[a] = min(bhi[a] + 1, J.nb[a] - 1);
+                        }
+                    }
+                    if (DIM == 2)
+                        olo[2] = ohi[2] = 0;
+                    nbx = bhi[0] - blo[0] + 1;
+                    nby = bhi[1] - blo[1] + 1;
+                    nbz = bhi[2] - blo[2] + 1;
+                    sh_total = (int64_t)nbx * nby * nbz;
+                    sh_pos = 0;
+                    continue;
+                }
+                const int64_t e = sh_pos + lane;
+                int cnt = 0, src = 0;
+                if (e < sh_total) {
+                    const int ex = (int)(e % nbx);
+                    const int64_t e2 = e / nbx;
+                    const int ey = (int)(e2 % nby), ez = (int)(e2 / nby);
+                    const int bx = blo[0] + ex, by = blo[1] + ey, bz = blo[2] + ez;
+                    const bool old = bx >= olo[0] && bx <= ohi[0] && by >= olo[1] && by <= ohi[1] && bz >= olo[2] &&
+                                     bz <= ohi[2];
+                    if (!old) {
+                        int wx = bx, wy = by, wz = bz;
+                        if (periodic) {
+                            wx = ((wx % J.nb[0]) + J.nb[0]) % J.nb[0];
+                            wy = ((wy % J.nb[1]) + J.nb[1]) % J.nb[1];
+                            wz = ((wz % J.nb[2]) + J.nb[2]) % J.nb[2];
+                        }
+                        const int lin = wx + J.nb[0] * (wy + J.nb[1] * wz);
+                        src = J.bin_start[lin];
+                        cnt = J.bin_start[lin + 1] - src;
+                    }
+                }
+                const int inc = wave_inclusive_add(cnt, lane);
+                S.bcnt[lane] = inc;
+                S.bsrc[lane] = src;
+                ch_T = __shfl(inc, WAVE - 1);
+                ch_off = 0;
+                ch_live = ch_T > 0;
+                sh_pos += WAVE;
+                wave_sync();
+                continue;
+            }
+            const int p = ch_off + lane;
+            const bool valid = p < ch_T;
+            double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+            int sid = 0, flags = 0;
+            double lb = __builtin_inf(), ub = __builtin_inf(), dmn = 0.0, dmx = 0.0;
+            if (valid) {
+                int lo = 0, hi = WAVE - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (S.bcnt[mid] > p)
+                        hi = mid;
+                    else
+                        lo = mid + 1;
+                }
+                const int excl = lo == 0 ? 0 : S.bcnt[lo - 1];
+                const int pos = S.bsrc[lo] + (p - excl);
+                s = J.sites[pos];
+                sid = J.sidx[pos];
+                box_bounds<KIND, DIM>(J, C, B, periodic, s, flags, lb, ub, dmn, dmx);
+            }
+            UB = fmin(UB, wave_min(ub));
+            const bool keep = valid && lb <= UB + C.M;
+            const unsigned long long km = __ballot(keep);
+            if (keep) {
+                const int slot = nc + __popcll(km & lanes_below(lane));
+                S.cs[slot] = s;
+                S.cb[slot] = make_double2(lb, ub);
+                S.cq[slot] = make_double2(dmn, dmx);
+                S.cm[slot] = make_int2(sid, flags);
+            }
+            nc += __popcll(km);
+            ch_off += WAVE;
+            if (ch_off >= ch_T)
+                ch_live = false;
+            wave_sync();
+            if (nc > CAP_F - WAVE)
+                flush = true;
+        }
+        if (nc > 0) {
+            // keep the entries under the current UB, then prune, sort, evaluate
+            const double thr = UB + C.M;
+            double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+            double2 q = make_double2(0.0, 0.0);
+            int2 m = make_int2(0, 0);
+            bool keep = false;
+            if (lane < nc) {
+                s = S.cs[lane];
+                q = S.cq[lane];
+                m = S.cm[lane];
+                keep = S.cb[lane].x <= thr;
+            }
+            const unsigned long long km = __ballot(keep);
+            wave_sync();
+            if (keep) {
+                const int d = __popcll(km & lanes_below(lane));
+                S.cs[d] = s;
+                S.cq[d] = q;
+                S.cm[d] = m;
+            }
+            nc = __popcll(km);
+            wave_sync();
+            nc = prune_and_sort<KIND, DIM>(S.cs, S.cm, S.cq, nc, lane, J, C, B);
+            evaluate<KIND, DIM, RUN>(S.cs, S.cm, nc, lex, J, C, periodic, xr, yv, zv, best, lab);
+            lex = true;
+            nc = 0;
+            wave_sync();
+        }
+        if (done)
+            break;
+    }
+}
+
+// ------------------------------------------------------------ one region
+
+struct LaneGeo {
+    int t0[3];      // first voxel of the tile
+    bool live;      // tile inside the grid
+    int mi, mj, mk; // first voxel of the lane's run
+};
+
+template <int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
+__device__ inline LaneGeo lane_geometry(const JobDev& J, int64_t r, int w, int lane)
+{
+    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
+    const int rx = (int)(r % J.nr[0]);
+    const int64_t rr = r / J.nr[0];
+    const int ry = (int)(rr % J.nr[1]);
+    const int rz = (int)(rr / J.nr[1]);
+    LaneGeo G;
+    G.t0[0] = rx * TX * RX + (w % RX) * TX;
+    G.t0[1] = ry * TY * RY + ((w / RX) % RY) * TY;
+    G.t0[2] = rz * TZ * RZ + (w / (RX * RY)) * TZ;
+    G.live = G.t0[0] < J.n[0] && G.t0[1] < J.n[1] && G.t0[2] < J.n[2];
     const int lx = lane % LX, ly = (lane / LX) % LY, lz = lane / (LX * LY);
-    const int mi = v0[0] + lx * RUN, mj = v0[1] + ly, mk = (DIM == 3) ? v0[2] + lz : 0;
+    G.mi = G.t0[0] + lx * RUN;
+    G.mj = G.t0[1] + ly;
+    G.mk = (DIM == 3) ? G.t0[2] + lz : 0;
+    return G;
+}
+
+// Region `r` of job J: NW tiles of shape T (tile w of the region is processed
+// by wavefront w), RX x RY x RZ tiles.  `unit` numbers the region in the
+// launch (job-local, or batch-wide) for the overflow list.
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
+__device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm, const int tid)
+{
+    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
+    static_assert(LX * LY * LZ == WAVE, "64 lanes per tile");
+    static_assert(RX * RY * RZ == NW, "one tile per wavefront");
+    const bool periodic = J.bc != 0;
+    const int lane = tid & (WAVE - 1), w = tid / WAVE;
+
+    // ---- region and tile geometry
+    const int rx = (int)(r % J.nr[0]);
+    const int64_t rr = r / J.nr[0];
+    const int ry = (int)(rr % J.nr[1]);
+    const int rz = (int)(rr / J.nr[1]);
+    const int r0[3] = {rx * TX * RX, ry * TY * RY, rz * TZ * RZ};
+    const int re[3] = {min(r0[0] + TX * RX, J.n[0]) - 1, min(r0[1] + TY * RY, J.n[1]) - 1,
+                       min(r0[2] + TZ * RZ, J.n[2]) - 1};
+    const TileBox BR = make_box<DIM>(J, r0, re);
+    const LaneGeo G = lane_geometry<DIM, RUN, LX, LY, LZ, RX, RY, RZ>(J, r, w, lane);
+    const int te[3] = {min(G.t0[0] + TX, J.n[0]) - 1, min(G.t0[1] + TY, J.n[1]) - 1,
+                       min(G.t0[2] + TZ, J.n[2]) - 1};
+    const TileBox BT = make_box<DIM>(J, G.t0, te);
+
     double xr[RUN];
 #pragma unroll
     for (int q = 0; q < RUN; ++q)
-        xr[q] = ((double)(mi + q) + 0.5) * J.h[0];
-    const double yv = ((double)mj + 0.5) * J.h[1];
-    const double zv = (DIM == 3) ? ((double)mk + 0.5) * J.h[2] : 0.0;
+        xr[q] = ((double)(G.mi + q) + 0.5) * J.h[0];
+    const double yv = ((double)G.mj + 0.5) * J.h[1];
+    const double zv = (DIM == 3) ? ((double)G.mk + 0.5) * J.h[2] : 0.0;
     double best[RUN];
     int lab[RUN];
 #pragma unroll
@@ -255,421 +762,322 @@ __device__ void label_tile(const JobDev& J, int64_t tile, WaveLds& S, const int 
     }
 
     const bool bad = *(volatile int32_t*)J.status != 0;
+    bool tile_ovf = false;
     if (!bad) {
-        // ---- per-job constants: key scale, margin, bounds of the parameters
-        double sumL2 = 0.0;
-        for (int a = 0; a < DIM; ++a)
-            sumL2 += J.L[a] * J.L[a];
-        const double sumL2_sqrt = sqrt(sumL2);
-        const double v = J.growth, rv = J.rgrowth;
-        double pmax = 0.0, pmin = 0.0;
-        if (KIND != KV) {
-            pmax = from_ordered(J.pbound[0]);
-            pmin = -from_ordered(J.pbound[1]);
-        }
-        const double pabs = fmax(fabs(pmax), fabs(pmin));
-        const double scale = (KIND == KV) ? sumL2
-                             : (KIND == KL) ? sumL2 + 2.0 * pabs
-                                            : sumL2_sqrt * rv + 2.0 * pabs;
-        const double M = scale * 0x1p-36;
+        const JobConst C = job_const<KIND>(J, DIM);
+        RegionLds& R = sm.r.reg;
 
-        // ---- visited bin box (unwrapped bin coordinates) and previous box
+        // ======== 1. region gather (whole workgroup)
         int blo[3], bhi[3], olo[3], ohi[3];
         for (int a = 0; a < 3; ++a) {
             if (a < DIM) {
-                int l = (int)(B.lo[a] * J.inv_bs[a]), h = (int)(B.hi[a] * J.inv_bs[a]);
-                blo[a] = max(0, min(l, J.nb[a] - 1));
-                bhi[a] = max(blo[a], min(h, J.nb[a] - 1));
+                const int nb = J.nb[a];
+                int l = (int)(BR.lo[a] * J.inv_bs[a]), h = (int)(BR.hi[a] * J.inv_bs[a]);
+                l = max(0, min(l, nb - 1));
+                h = max(l, min(h, nb - 1));
+                if (periodic) {
+                    blo[a] = l - 1;
+                    bhi[a] = h + 1;
+                    if (bhi[a] - blo[a] + 1 >= nb) {
+                        blo[a] = l;
+                        bhi[a] = l + nb - 1;
+                    }
+                } else {
+                    blo[a] = max(l - 1, 0);
+                    bhi[a] = min(h + 1, nb - 1);
+                }
             } else {
                 blo[a] = bhi[a] = 0;
             }
             olo[a] = 1;
             ohi[a] = 0;
         }
-        int nbx = bhi[0] - blo[0] + 1, nby = bhi[1] - blo[1] + 1, nbz = bhi[2] - blo[2] + 1;
-        int64_t sh_total = (int64_t)nbx * nby * nbz, sh_pos = 0;
-        int ch_T = 0, ch_off = 0;
-        bool ch_live = false;
-        double UB = __builtin_inf();
-        int nc = 0;
-        bool lex = false, done = false;
-
-        for (;;) {
-            bool flush = false;
-            // ======== gather ========
-            while (!done && !flush) {
-                if (!ch_live) {
-                    if (sh_pos >= sh_total) {
-                        // Shell finished: lower bound of every unvisited site.
-                        bool complete = true;
-                        double G = __builtin_inf();
-                        for (int a = 0; a < DIM; ++a) {
-                            const bool full = periodic ? (bhi[a] - blo[a] + 1 >= J.nb[a])
-                                                       : (blo[a] == 0 && bhi[a] == J.nb[a] - 1);
-                            if (full)
-                                continue;
-                            complete = false;
-                            const double slack = J.L[a] * 0x1p-30;
-                            if (periodic || blo[a] > 0)
-                                G = fmin(G, B.lo[a] - ((double)blo[a] * J.bs[a] + slack));
-                            if (periodic || bhi[a] < J.nb[a] - 1)
-                                G = fmin(G, ((double)(bhi[a] + 1) * J.bs[a] - slack) - B.hi[a]);
+        int nR = 0;
+        bool overflow = false;
+        for (int round = 0;; ++round) {
+            // load every bin of the box that is not in the previous box
+            const int nbx = bhi[0] - blo[0] + 1, nby = bhi[1] - blo[1] + 1, nbz = bhi[2] - blo[2] + 1;
+            const int64_t nbox = (int64_t)nbx * nby * nbz;
+            for (int64_t base = 0; base < nbox; base += NT) {
+                const int64_t e = base + tid;
+                int cnt = 0, src = 0;
+                if (e < nbox) {
+                    const int ex = (int)(e % nbx);
+                    const int64_t e2 = e / nbx;
+                    const int ey = (int)(e2 % nby), ez = (int)(e2 / nby);
+                    const int bx = blo[0] + ex, by = blo[1] + ey, bz = blo[2] + ez;
+                    const bool old = bx >= olo[0] && bx <= ohi[0] && by >= olo[1] && by <= ohi[1] && bz >= olo[2] &&
+                                     bz <= ohi[2];
+                    if (!old) {
+                        int wx = bx, wy = by, wz = bz;
+                        if (periodic) {
+                            wx = ((wx % J.nb[0]) + J.nb[0]) % J.nb[0];
+                            wy = ((wy % J.nb[1]) + J.nb[1]) % J.nb[1];
+                            wz = ((wz % J.nb[2]) + J.nb[2]) % J.nb[2];
                         }
-                        if (complete) {
-                            done = true;
-                            break;
-                        }
-                        G = fmax(G, 0.0);
-                        const double LB = (KIND == KV)   ? G * G
-                                          : (KIND == KL) ? G * G - pmax
-                                                         : pmin + G * rv;
-                        if (LB > UB + M) {
-                            done = true;
-                            break;
-                        }
-                        for (int a = 0; a < DIM; ++a) {
-                            olo[a] = blo[a];
-                            ohi[a] = bhi[a];
-                            if (periodic) {
-                                if (bhi[a] - blo[a] + 1 < J.nb[a]) {
-                                    blo[a] -= 1;
-                                    bhi[a] += 1;
-                                    if (bhi[a] - blo[a] + 1 > J.nb[a])
-                                        bhi[a] = blo[a] + J.nb[a] - 1;
-                                }
-                            } else {
-                                blo[a] = max(blo[a] - 1, 0);
-                                bhi[a] = min(bhi[a] + 1, J.nb[a] - 1);
-                            }
-                        }
-                        if (DIM == 2) {
-                            olo[2] = ohi[2] = 0;
-                        }
-                        nbx = bhi[0] - blo[0] + 1;
-                        nby = bhi[1] - blo[1] + 1;
-                        nbz = bhi[2] - blo[2] + 1;
-                        sh_total = (int64_t)nbx * nby * nbz;
-                        sh_pos = 0;
-                        continue;
+                        const int lin = wx + J.nb[0] * (wy + J.nb[1] * wz);
+                        src = J.bin_start[lin];
+                        cnt = J.bin_start[lin + 1] - src;
                     }
-                    // Next chunk of up to 64 bins of the box, skipping the old box.
-                    const int64_t e = sh_pos + lane;
-                    int cnt = 0, src = 0;
-                    if (e < sh_total) {
-                        const int ex = (int)(e % nbx);
-                        const int64_t e2 = e / nbx;
-                        const int ey = (int)(e2 % nby), ez = (int)(e2 / nby);
-                        const int bx = blo[0] + ex, by = blo[1] + ey, bz = blo[2] + ez;
-                        const bool old = bx >= olo[0] && bx <= ohi[0] && by >= olo[1] && by <= ohi[1] &&
-                                         bz >= olo[2] && bz <= ohi[2];
-                        if (!old) {
-                            int wx = bx, wy = by, wz = bz;
-                            if (periodic) {
-                                wx = ((wx % J.nb[0]) + J.nb[0]) % J.nb[0];
-                                wy = ((wy % J.nb[1]) + J.nb[1]) % J.nb[1];
-                                wz = ((wz % J.nb[2]) + J.nb[2]) % J.nb[2];
-                            }
-                            const int lin = wx + J.nb[0] * (wy + J.nb[1] * wz);
-                            src = J.bin_start[lin];
-                            cnt = J.bin_start[lin + 1] - src;
-                        }
-                    }
-                    const int inc = wave_inclusive_add(cnt, lane);
-                    S.bcnt[lane] = inc;
-                    S.bsrc[lane] = src;
-                    ch_T = __shfl(inc, WAVE - 1);
-                    ch_off = 0;
-                    ch_live = ch_T > 0;
-                    sh_pos += WAVE;
-                    __syncthreads();
+                }
+                int total;
+                const int off = block_excl_scan(cnt, total, R.wsum, tid);
+                if (nR + total > CAP_R) {
+                    overflow = true;
+                    break;
+                }
+                for (int k = 0; k < cnt; ++k) {
+                    R.rs[nR + off + k] = J.sites[src + k];
+                    R.ri[nR + off + k] = J.sidx[src + k];
+                }
+                nR += total;
+            }
+            if (overflow)
+                break;
+            __syncthreads();
+            // UB over the region from every listed site
+            double ubm = __builtin_inf();
+            for (int e = tid; e < nR; e += NT)
+                ubm = fmin(ubm, box_upper<KIND, DIM>(J, C, BR, periodic, R.rs[e]));
+            const double UB = block_min(ubm, R.wred, tid);
+            // move the faces that are too close
+            const double reach = needed_reach<KIND>(C, UB);
+            const double need = reach + reach * 0x1p-20 + 1e-300;
+            bool moved = false;
+            int nlo[3], nhi[3];
+            for (int a = 0; a < 3; ++a) {
+                nlo[a] = blo[a];
+                nhi[a] = bhi[a];
+            }
+            for (int a = 0; a < DIM; ++a) {
+                const int nb = J.nb[a];
+                if (periodic && bhi[a] - blo[a] + 1 >= nb)
+                    continue;
+                int lo = blo[a], hi = bhi[a];
+                if (periodic && need >= J.L[a]) {
+                    nlo[a] = blo[a];
+                    nhi[a] = blo[a] + nb - 1;
+                    moved = true;
                     continue;
                 }
-                // Up to 64 sites of the chunk, one per lane.
-                const int p = ch_off + lane;
-                const bool valid = p < ch_T;
-                double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
-                int sid = 0, flags = 0;
-                double lb = __builtin_inf(), ub = __builtin_inf(), dmn = 0.0, dmx = 0.0;
-                if (valid) {
-                    int lo = 0, hi = WAVE - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (S.bcnt[mid] > p)
-                            hi = mid;
-                        else
-                            lo = mid + 1;
-                    }
-                    const int excl = lo == 0 ? 0 : S.bcnt[lo - 1];
-                    const int pos = S.bsrc[lo] + (p - excl);
-                    s = J.sites[pos];
-                    sid = J.sidx[pos];
-                    const double sc[3] = {s.x, s.y, s.z};
-                    double qmin = 0.0, qmax = 0.0;
-                    for (int a = 0; a < DIM; ++a) {
-                        double sg = sc[a], dmin, dmax;
-                        bool gen = false;
-                        if (periodic) {
-                            const int c1 = wrap_code(sc[a] - B.lo[a], J.H[a]);
-                            const int c2 = wrap_code(sc[a] - B.hi[a], J.H[a]);
-                            if (c1 == c2) {
-                                flags |= c1 << (2 * a);
-                                sg = sc[a] + code_off(c1, J.L[a]);
-                            } else {
-                                gen = true;
-                            }
-                        }
-                        if (gen) {
-                            flags |= FL_GENERIC;
-                            dmin = 0.0;
-                            dmax = J.H[a];
-                        } else {
-                            dmin = fmax(0.0, fmax(B.lo[a] - sg, sg - B.hi[a]));
-                            dmax = fmax(fabs(sg - B.lo[a]), fabs(sg - B.hi[a]));
-                        }
-                        qmin += dmin * dmin;
-                        qmax += dmax * dmax;
-                    }
-                    dmn = sqrt(qmin);
-                    dmx = sqrt(qmax);
-                    if (KIND == KV) {
-                        lb = qmin;
-                        ub = qmax;
-                    } else if (KIND == KL) {
-                        lb = qmin - s.w;
-                        ub = qmax - s.w;
-                    } else {
-                        lb = s.w + dmn * rv;
-                        ub = s.w + dmx * rv;
-                    }
+                if (gap_low(J, BR, a, lo, periodic) <= need) {
+                    int t = (int)fmax(floor((BR.lo[a] - need) * J.inv_bs[a]), -2.0 * nb - 2.0);
+                    lo = min(lo - 1, t);
+                    if (!periodic)
+                        lo = max(lo, 0);
+                    while (gap_low(J, BR, a, lo, periodic) <= need && (periodic || lo > 0))
+                        --lo;
                 }
-                UB = fmin(UB, wave_min(ub));
-                const bool keep = valid && lb <= UB + M;
+                if (gap_high(J, BR, a, hi, periodic) <= need) {
+                    int t = (int)fmin(floor((BR.hi[a] + need) * J.inv_bs[a]), 3.0 * nb + 2.0);
+                    hi = max(hi + 1, t);
+                    if (!periodic)
+                        hi = min(hi, nb - 1);
+                    while (gap_high(J, BR, a, hi, periodic) <= need && (periodic || hi < nb - 1))
+                        ++hi;
+                }
+                if (periodic && hi - lo + 1 >= nb) {
+                    lo = blo[a];
+                    hi = blo[a] + nb - 1;
+                }
+                moved = moved || lo != blo[a] || hi != bhi[a];
+                nlo[a] = lo;
+                nhi[a] = hi;
+            }
+            if (!moved)
+                break;
+            for (int a = 0; a < 3; ++a) {
+                olo[a] = blo[a];
+                ohi[a] = bhi[a];
+                blo[a] = nlo[a];
+                bhi[a] = nhi[a];
+            }
+            if (round > 64) {  // every round grows the box; leave pathological cases to the fallback
+                overflow = true;
+                break;
+            }
+        }
+        __syncthreads();
+
+        // ======== 2-3. per tile: prune and evaluate (one wavefront)
+        tile_ovf = overflow;
+        if (!overflow && G.live) {
+            TileLds& S = sm.r.tile[w];
+            double ubm = __builtin_inf();
+            for (int e = lane; e < nR; e += WAVE)
+                ubm = fmin(ubm, box_upper<KIND, DIM>(J, C, BT, periodic, R.rs[e]));
+            const double thr = wave_min(ubm) + C.M;
+            int nc = 0;
+            for (int ebase = 0; ebase < nR; ebase += WAVE) {
+                const int e = ebase + lane;
+                int flags = 0;
+                double lb = __builtin_inf(), ub, dmn = 0.0, dmx = 0.0;
+                double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (e < nR) {
+                    s = R.rs[e];
+                    box_bounds<KIND, DIM>(J, C, BT, periodic, s, flags, lb, ub, dmn, dmx);
+                }
+                const bool keep = e < nR && lb <= thr;
                 const unsigned long long km = __ballot(keep);
+                if (nc + __popcll(km) > CAP_S) {
+                    tile_ovf = true;
+                    break;
+                }
                 if (keep) {
                     const int slot = nc + __popcll(km & lanes_below(lane));
                     S.cs[slot] = s;
-                    S.cb[slot] = make_double2(lb, ub);
                     S.cq[slot] = make_double2(dmn, dmx);
-                    S.cm[slot] = make_int2(sid, flags);
+                    S.cm[slot] = make_int2(R.ri[e], flags);
                 }
                 nc += __popcll(km);
-                ch_off += WAVE;
-                if (ch_off >= ch_T)
-                    ch_live = false;
-                __syncthreads();
-                if (nc > CAP - WAVE) {
-                    const double thr = UB + M;
-                    nc = compact(S, nc, S.cb[lane].x <= thr, S.cb[lane + WAVE].x <= thr, lane);
-                    if (nc > CAP - WAVE)
-                        flush = true;
-                }
             }
-
-            // ======== prune, sort by index, evaluate ========
-            if (nc > 0) {
-                const double thr = UB + M;
-                nc = compact(S, nc, S.cb[lane].x <= thr, S.cb[lane + WAVE].x <= thr, lane);
-                if (nc > 1) {
-                    const bool d0 = lane < nc && dominated<KIND, DIM>(S, nc, lane, J, B, M, sumL2_sqrt, rv);
-                    const bool d1 = lane + WAVE < nc &&
-                                    dominated<KIND, DIM>(S, nc, lane + WAVE, J, B, M, sumL2_sqrt, rv);
-                    nc = compact(S, nc, !d0, !d1, lane);
-                }
-                // Rank by site index (indices are distinct), then permute in place.
-                {
-                    int r0 = 0, r1 = 0;
-                    const int i0 = lane < nc ? S.cm[lane].x : 0;
-                    const int i1 = lane + WAVE < nc ? S.cm[lane + WAVE].x : 0;
-                    for (int t = 0; t < nc; ++t) {
-                        const int it = S.cm[t].x;
-                        r0 += it < i0;
-                        r1 += it < i1;
-                    }
-                    double4 s0, s1;
-                    int2 m0, m1;
-                    if (lane < nc) {
-                        s0 = S.cs[lane];
-                        m0 = S.cm[lane];
-                    }
-                    if (lane + WAVE < nc) {
-                        s1 = S.cs[lane + WAVE];
-                        m1 = S.cm[lane + WAVE];
-                    }
-                    __syncthreads();
-                    if (lane < nc) {
-                        S.cs[r0] = s0;
-                        S.cm[r0] = m0;
-                    }
-                    if (lane + WAVE < nc) {
-                        S.cs[r1] = s1;
-                        S.cm[r1] = m1;
-                    }
-                    __syncthreads();
-                }
-                // Exact keys, candidates in ascending index order.
-                for (int k = 0; k < nc; ++k) {
-                    const double4 s = S.cs[k];
-                    const int2 m = S.cm[k];
-                    const int idx = m.x, fl = m.y;
-                    double c;
-                    double dxv[RUN];
-                    if (fl == 0) {
-                        const double dy = s.y - yv;
-                        if (DIM == 3) {
-                            const double dz = s.z - zv;
-                            c = dy * dy + dz * dz;
-                        } else {
-                            c = dy * dy;
-                        }
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q)
-                            dxv[q] = s.x - xr[q];
-                    } else if (!(fl & FL_GENERIC)) {
-                        const double dy = (s.y - yv) + code_off((fl >> 2) & 3, J.L[1]);
-                        if (DIM == 3) {
-                            const double dz = (s.z - zv) + code_off((fl >> 4) & 3, J.L[2]);
-                            c = dy * dy + dz * dz;
-                        } else {
-                            c = dy * dy;
-                        }
-                        const double ox = code_off(fl & 3, J.L[0]);
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q)
-                            dxv[q] = (s.x - xr[q]) + ox;
-                    } else {
-                        const double dy = periodic ? min_image(s.y - yv, J.H[1], J.L[1]) : s.y - yv;
-                        if (DIM == 3) {
-                            const double dz = periodic ? min_image(s.z - zv, J.H[2], J.L[2]) : s.z - zv;
-                            c = dy * dy + dz * dz;
-                        } else {
-                            c = dy * dy;
-                        }
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q)
-                            dxv[q] = periodic ? min_image(s.x - xr[q], J.H[0], J.L[0]) : s.x - xr[q];
-                    }
-                    if (!lex) {
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q) {
-                            const double key = dist_key<KIND>(dxv[q] * dxv[q] + c, s.w, v, rv);
-                            const bool lt = key < best[q];
-                            lab[q] = lt ? idx : lab[q];
-                            best[q] = lt ? key : best[q];
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q) {
-                            const double key = dist_key<KIND>(dxv[q] * dxv[q] + c, s.w, v, rv);
-                            const bool lt = key < best[q] || (key == best[q] && idx < lab[q]);
-                            lab[q] = lt ? idx : lab[q];
-                            best[q] = lt ? key : best[q];
-                        }
-                    }
-                }
-                lex = true;
-                nc = 0;
-                __syncthreads();
+            wave_sync();
+            if (!tile_ovf) {
+                nc = prune_and_sort<KIND, DIM>(S.cs, S.cm, S.cq, nc, lane, J, C, BT);
+                evaluate<KIND, DIM, RUN>(S.cs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
             }
-            if (done)
-                break;
         }
     }
-
-    // ---- coalesced label stores (x fastest)
-    if (mj < J.n[1] && mk < J.n[2]) {
-        int32_t* out = J.labels + (int64_t)mi + (int64_t)J.n[0] * ((int64_t)mj + (int64_t)J.n[1] * mk);
-        if (bad) {
-#pragma unroll
-            for (int q = 0; q < RUN; ++q)
-                lab[q] = -1;
-        }
-        if (mi + RUN <= J.n[0] && ((uintptr_t)out & 15) == 0 && RUN % 4 == 0) {
-#pragma unroll
-            for (int q = 0; q < RUN; q += 4)
-                *(int4*)(out + q) = make_int4(lab[q], lab[q + 1], lab[q + 2], lab[q + 3]);
+    if (G.live) {
+        if (tile_ovf) {
+            // leave this tile to the fallback kernel
+            if (lane == 0) {
+                const int pos = atomicAdd(J.ovf_count, 1);
+                J.ovf_list[pos] = (int32_t)(unit * NW + w);
+            }
         } else {
-#pragma unroll
-            for (int q = 0; q < RUN; ++q)
-                if (mi + q < J.n[0])
-                    out[q] = lab[q];
+            store_run<RUN>(J, G.mi, G.mj, G.mk, bad, lab);
         }
     }
 }
 
-// Spreads consecutive tiles over one XCD: workgroups are dispatched to the
-// eight XCDs round-robin, so workgroup b runs on XCD b % 8.  Give each XCD a
-// contiguous range of tiles so that neighbouring tiles share its L2.
-__device__ inline int64_t xcd_tile(int64_t b, int64_t G)
+// One tile of the overflow list, alone (fallback path, one wavefront).
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
+__device__ void label_tile_alone(const JobDev& J, int64_t r, int w, FallbackLds& S, int lane)
+{
+    const LaneGeo G = lane_geometry<DIM, RUN, LX, LY, LZ, RX, RY, RZ>(J, r, w, lane);
+    if (!G.live)
+        return;
+    double xr[RUN];
+#pragma unroll
+    for (int q = 0; q < RUN; ++q)
+        xr[q] = ((double)(G.mi + q) + 0.5) * J.h[0];
+    const double yv = ((double)G.mj + 0.5) * J.h[1];
+    const double zv = (DIM == 3) ? ((double)G.mk + 0.5) * J.h[2] : 0.0;
+    double best[RUN];
+    int lab[RUN];
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+        best[q] = __builtin_inf();
+        lab[q] = -1;
+    }
+    const bool bad = *(volatile int32_t*)J.status != 0;
+    if (!bad) {
+        const JobConst C = job_const<KIND>(J, DIM);
+        fallback_tile<KIND, DIM, RUN, LX, LY, LZ>(J, C, G.t0, S, lane, xr, yv, zv, best, lab);
+    }
+    store_run<RUN>(J, G.mi, G.mj, G.mk, bad, lab);
+}
+
+// Consecutive regions go to one XCD: workgroups are dispatched to the eight
+// XCDs round-robin, so workgroup b runs on XCD b % 8; give each XCD a
+// contiguous range so that neighbouring regions share its L2.
+__device__ inline int64_t xcd_unit(int64_t b, int64_t G)
 {
     const int64_t x = b & 7, q = G >> 3, r = G & 7;
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 template <int KIND, int DIM, int CFG>
-__global__ __launch_bounds__(WAVE) void k_label_single(JobDev J)
+__device__ inline void region_cfg(const JobDev& J, int64_t r, int64_t unit, Smem& sm, int tid)
 {
-    __shared__ WaveLds S;
     constexpr TileShape T = (DIM == 3) ? kShape3[CFG] : kShape2[CFG];
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    label_tile<KIND, DIM, T.run, T.lx, T.ly, T.lz>(J, tile, S, threadIdx.x);
+    label_region<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rx, T.ry, T.rz>(J, r, unit, sm, tid);
 }
 
-template <int KIND, int DIM>
-__device__ void batch_tile(const JobDev& J, int64_t t, WaveLds& S, int lane)
+template <int KIND, int DIM, int CFG>
+__device__ inline void alone_cfg(const JobDev& J, int64_t r, int w, FallbackLds& S, int lane)
 {
-    constexpr TileShape T = (DIM == 3) ? kShape3[0] : kShape2[0];
-    label_tile<KIND, DIM, T.run, T.lx, T.ly, T.lz>(J, t, S, lane);
+    constexpr TileShape T = (DIM == 3) ? kShape3[CFG] : kShape2[CFG];
+    label_tile_alone<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rx, T.ry, T.rz>(J, r, w, S, lane);
 }
 
-// Persistent batch kernel: the global tile enumeration (jobs one after the
-// other) is cut into eight ranges, one per XCD; each wave takes tiles of its
-// own XCD's range from an atomic counter and then helps the other ranges.
-__global__ __launch_bounds__(WAVE) void k_label_batch(const JobDev* __restrict__ jobs, int njobs,
-                                                      int64_t total, int32_t* counters)
+template <int KIND, int DIM, int CFG>
+__global__ __launch_bounds__(NT) void k_label_single(JobDev J)
 {
-    __shared__ WaveLds S;
+    __shared__ Smem sm;
+    const int64_t r = xcd_unit(blockIdx.x, gridDim.x);
+    region_cfg<KIND, DIM, CFG>(J, r, r, sm, threadIdx.x);
+}
+
+// Tiles the main kernel left over, one wavefront each.
+template <int KIND, int DIM, int CFG>
+__global__ __launch_bounds__(WAVE) void k_label_fallback(JobDev J)
+{
+    __shared__ FallbackLds S;
+    const int n = *(volatile int32_t*)J.ovf_count;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int id = J.ovf_list[i];
+        alone_cfg<KIND, DIM, CFG>(J, id / NW, id % NW, S, threadIdx.x);
+        __syncthreads();
+    }
+}
+
+__device__ inline int job_of_region(const JobDev* jobs, int njobs, int64_t g)
+{
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].region_begin <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+__device__ inline int variant_code(const JobDev& J)
+{
+    return J.kind == KIND_VORONOI ? KV : J.kind == KIND_LAGUERRE ? KL : (J.jm_div ? KJD : KJM);
+}
+
+// Persistent batch kernel: the global region enumeration (jobs one after the
+// other) is cut into eight ranges, one per XCD; each workgroup takes regions of
+// its own XCD's range from an atomic counter, then helps the other ranges.
+__global__ __launch_bounds__(NT) void k_label_batch(const JobDev* __restrict__ jobs, int njobs, int64_t total,
+                                                    int32_t* counters)
+{
+    __shared__ Smem sm;
     __shared__ int64_t got;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int home = blockIdx.x & 7;
     for (int probe = 0; probe < 8; ++probe) {
         const int x = (home + probe) & 7;
         const int64_t rb = total * x / 8, re = total * (x + 1) / 8;
         for (;;) {
-            if (lane == 0)
+            if (tid == 0)
                 got = rb + (int64_t)atomicAdd(&counters[x], 1);
             __syncthreads();
             const int64_t g = got;
             __syncthreads();
             if (g >= re)
                 break;
-            // job of tile g: largest j with tile_begin <= g
-            int lo = 0, hi = njobs - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (jobs[mid].tile_begin <= g)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            const int j = __builtin_amdgcn_readfirstlane(lo);
+            const int j = job_of_region(jobs, njobs, g);
             const JobDev& J = jobs[j];
-            const int64_t t = g - J.tile_begin;
-            const int code = J.kind == KIND_VORONOI ? KV
-                             : J.kind == KIND_LAGUERRE ? KL
-                             : (J.jm_div ? KJD : KJM);
+            const int64_t t = g - J.region_begin;
             if (J.ndim == 3) {
-                switch (code) {
-                case KV: batch_tile<KV, 3>(J, t, S, lane); break;
-                case KL: batch_tile<KL, 3>(J, t, S, lane); break;
-                case KJM: batch_tile<KJM, 3>(J, t, S, lane); break;
-                default: batch_tile<KJD, 3>(J, t, S, lane); break;
+                switch (variant_code(J)) {
+                case KV: region_cfg<KV, 3, 0>(J, t, g, sm, tid); break;
+                case KL: region_cfg<KL, 3, 0>(J, t, g, sm, tid); break;
+                case KJM: region_cfg<KJM, 3, 0>(J, t, g, sm, tid); break;
+                default: region_cfg<KJD, 3, 0>(J, t, g, sm, tid); break;
                 }
             } else {
-                switch (code) {
-                case KV: batch_tile<KV, 2>(J, t, S, lane); break;
-                case KL: batch_tile<KL, 2>(J, t, S, lane); break;
-                case KJM: batch_tile<KJM, 2>(J, t, S, lane); break;
-                default: batch_tile<KJD, 2>(J, t, S, lane); break;
+                switch (variant_code(J)) {
+                case KV: region_cfg<KV, 2, 0>(J, t, g, sm, tid); break;
+                case KL: region_cfg<KL, 2, 0>(J, t, g, sm, tid); break;
+                case KJM: region_cfg<KJM, 2, 0>(J, t, g, sm, tid); break;
+                default: region_cfg<KJD, 2, 0>(J, t, g, sm, tid); break;
                 }
             }
             __syncthreads();
@@ -677,37 +1085,84 @@ __global__ __launch_bounds__(WAVE) void k_label_batch(const JobDev* __restrict__
     }
 }
 
-template <int KIND, int DIM>
-hipError_t launch_single_cfg(const JobDev& job, hipStream_t s)
+// Fallback over the batch's overflow list (entries are batch-wide region * 4 + tile).
+__global__ __launch_bounds__(WAVE) void k_label_batch_fallback(const JobDev* __restrict__ jobs, int njobs,
+                                                               const int32_t* list, const int32_t* count)
 {
-    const unsigned grid = (unsigned)job.ntiles;
-    switch (job.cfg) {
-    case 0: k_label_single<KIND, DIM, 0><<<grid, WAVE, 0, s>>>(job); break;
-    case 1: k_label_single<KIND, DIM, 1><<<grid, WAVE, 0, s>>>(job); break;
-    default: k_label_single<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(job); break;
+    __shared__ FallbackLds S;
+    const int n = *(volatile const int32_t*)count;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int id = list[i];
+        const int64_t g = id / NW;
+        const int j = job_of_region(jobs, njobs, g);
+        const JobDev& J = jobs[j];
+        const int64_t t = g - J.region_begin;
+        const int w = id % NW;
+        if (J.ndim == 3) {
+            switch (variant_code(J)) {
+            case KV: alone_cfg<KV, 3, 0>(J, t, w, S, threadIdx.x); break;
+            case KL: alone_cfg<KL, 3, 0>(J, t, w, S, threadIdx.x); break;
+            case KJM: alone_cfg<KJM, 3, 0>(J, t, w, S, threadIdx.x); break;
+            default: alone_cfg<KJD, 3, 0>(J, t, w, S, threadIdx.x); break;
+            }
+        } else {
+            switch (variant_code(J)) {
+            case KV: alone_cfg<KV, 2, 0>(J, t, w, S, threadIdx.x); break;
+            case KL: alone_cfg<KL, 2, 0>(J, t, w, S, threadIdx.x); break;
+            case KJM: alone_cfg<KJM, 2, 0>(J, t, w, S, threadIdx.x); break;
+            default: alone_cfg<KJD, 2, 0>(J, t, w, S, threadIdx.x); break;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kFallbackGrid = 512;
+
+template <int KIND, int DIM>
+hipError_t launch_single_cfg(const JobDev& job, hipStream_t s, bool fallback)
+{
+    const unsigned grid = fallback ? kFallbackGrid : (unsigned)job.nregions;
+    if (fallback) {
+        switch (job.cfg) {
+        case 0: k_label_fallback<KIND, DIM, 0><<<grid, WAVE, 0, s>>>(job); break;
+        case 1: k_label_fallback<KIND, DIM, 1><<<grid, WAVE, 0, s>>>(job); break;
+        default: k_label_fallback<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(job); break;
+        }
+    } else {
+        switch (job.cfg) {
+        case 0: k_label_single<KIND, DIM, 0><<<grid, NT, 0, s>>>(job); break;
+        case 1: k_label_single<KIND, DIM, 1><<<grid, NT, 0, s>>>(job); break;
+        default: k_label_single<KIND, DIM, 2><<<grid, NT, 0, s>>>(job); break;
+        }
     }
     return hipGetLastError();
 }
 
 template <int DIM>
-hipError_t launch_single_dim(const JobDev& job, hipStream_t s)
+hipError_t launch_single_dim(const JobDev& job, hipStream_t s, bool fallback)
 {
     if (job.kind == KIND_VORONOI)
-        return launch_single_cfg<KV, DIM>(job, s);
+        return launch_single_cfg<KV, DIM>(job, s, fallback);
     if (job.kind == KIND_LAGUERRE)
-        return launch_single_cfg<KL, DIM>(job, s);
+        return launch_single_cfg<KL, DIM>(job, s, fallback);
     if (job.jm_div)
-        return launch_single_cfg<KJD, DIM>(job, s);
-    return launch_single_cfg<KJM, DIM>(job, s);
+        return launch_single_cfg<KJD, DIM>(job, s, fallback);
+    return launch_single_cfg<KJM, DIM>(job, s, fallback);
 }
 
 }  // namespace
 
 hipError_t launch_label_single(const JobDev& job, hipStream_t s)
 {
-    if (job.ntiles <= 0 || job.ntiles > 0x7fffffffLL)
+    if (job.nregions <= 0 || job.nregions > 0x7fffffffLL)
         return hipErrorInvalidValue;
-    return job.ndim == 3 ? launch_single_dim<3>(job, s) : launch_single_dim<2>(job, s);
+    return job.ndim == 3 ? launch_single_dim<3>(job, s, false) : launch_single_dim<2>(job, s, false);
+}
+
+hipError_t launch_label_fallback(const JobDev& job, hipStream_t s)
+{
+    return job.ndim == 3 ? launch_single_dim<3>(job, s, true) : launch_single_dim<2>(job, s, true);
 }
 
 int label_batch_grid(int device)
@@ -715,16 +1170,16 @@ int label_batch_grid(int device)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         cus = 256;
-    return cus * 16;
+    return cus * 4;
 }
 
-hipError_t launch_label_batch(const JobDev* jobs_dev, int njobs, int ndim_mask, int64_t total_tiles,
-                              int32_t* counters, int grid, hipStream_t s)
+hipError_t launch_label_batch(const JobDev* jobs_dev, int njobs, int64_t total_regions, int32_t* counters,
+                              int32_t* ovf_list, int32_t* ovf_count, int grid, hipStream_t s)
 {
-    (void)ndim_mask;
-    if (total_tiles <= 0)
+    if (total_regions <= 0)
         return hipSuccess;
-    k_label_batch<<<grid, WAVE, 0, s>>>(jobs_dev, njobs, total_tiles, counters);
+    k_label_batch<<<grid, NT, 0, s>>>(jobs_dev, njobs, total_regions, counters);
+    k_label_batch_fallback<<<kFallbackGrid, WAVE, 0, s>>>(jobs_dev, njobs, ovf_list, ovf_count);
     return hipGetLastError();
 }
 

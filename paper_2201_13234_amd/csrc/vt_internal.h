@@ -22,13 +22,13 @@ struct JobDev {
     int32_t nsites, nbins, pad0;
     int32_t n[3];                  // voxels per axis (n[2] = 1 in 2D)
     int32_t nb[3];                 // bins per axis (nb[2] = 1 in 2D)
-    int32_t nt[3];                 // tiles per axis
+    int32_t nr[3];                 // regions (groups of four tiles) per axis
     int32_t pad1;
     double L[3], h[3], H[3];       // lengths, voxel size, half lengths
     double bs[3], inv_bs[3];       // bin side and its reciprocal
     double growth, rgrowth;        // v and 1/v
-    int64_t nvox, ntiles;
-    int64_t tile_begin;            // first tile of this job in a batch enumeration
+    int64_t nvox, nregions;
+    int64_t region_begin;          // first region of this job in a batch enumeration
     const double* coords;          // [nsites][ndim], caller input
     const double* param;           // [nsites] or null
     int32_t* labels;               // caller output
@@ -40,12 +40,20 @@ struct JobDev {
     double4* sites;                // sorted sites {x, y, z, param}
     int32_t* sidx;                 // sorted -> input index (0-based)
     unsigned long long* pbound;    // [2]: ordered bits of max(param), max(-param)
+    int32_t* ovf_list;             // tiles left to the fallback kernel (region * 4 + tile)
+    int32_t* ovf_count;            // their number
 };
 
-// Tile configurations: lane run length along x, lanes along x, y, z.
-struct TileShape { int run, lx, ly, lz; };
-constexpr TileShape kShape3[3] = {{8, 1, 8, 8}, {8, 2, 8, 4}, {8, 4, 4, 4}};
-constexpr TileShape kShape2[3] = {{8, 4, 16, 1}, {8, 2, 32, 1}, {8, 8, 8, 1}};
+// Tile configurations: lane run length along x, lanes along x, y, z (one
+// wavefront per tile), and tiles per region along x, y, z (one workgroup of
+// four wavefronts per region).
+struct TileShape { int run, lx, ly, lz, rx, ry, rz; };
+// 3D: 8x8x8 tiles in 32x8x8 regions; 8x8x8 tiles in 16x16x8 regions;
+//     16x8x4 tiles in 32x8x8 regions.
+constexpr TileShape kShape3[3] = {{8, 1, 8, 8, 4, 1, 1}, {8, 1, 8, 8, 2, 2, 1}, {8, 2, 8, 4, 2, 1, 2}};
+// 2D: 32x16 tiles in 64x32 regions; 16x32 tiles in 64x32 regions;
+//     64x8 tiles in 64x32 regions.
+constexpr TileShape kShape2[3] = {{8, 4, 16, 1, 2, 2, 1}, {8, 2, 32, 1, 4, 1, 1}, {8, 8, 8, 1, 1, 4, 1}};
 
 inline TileShape shape_of(int ndim, int cfg) { return ndim == 3 ? kShape3[cfg] : kShape2[cfg]; }
 
@@ -64,8 +72,10 @@ hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int 
 
 // Labelling: single job (all its tiles) or a persistent batch launch.
 hipError_t launch_label_single(const JobDev& job, hipStream_t s);
-hipError_t launch_label_batch(const JobDev* jobs_dev, int njobs, int ndim_mask,
-                              int64_t total_tiles, int32_t* counters, int grid, hipStream_t s);
+hipError_t launch_label_fallback(const JobDev& job, hipStream_t s);
+hipError_t launch_label_batch(const JobDev* jobs_dev, int njobs, int64_t total_regions,
+                              int32_t* counters, int32_t* ovf_list, int32_t* ovf_count, int grid,
+                              hipStream_t s);
 int label_batch_grid(int device);
 
 }  // namespace vt
