@@ -50,6 +50,7 @@ enum { KV = 0, KL = 1, KJM = 2, KJD = 3 };  // Johnson-Mehl: multiply by exact 1
 
 struct TileLds {
     double4 cs[CAP_S];  // site {x, y, z, param}
+    double4 cg[CAP_S];  // minimum image {x, y, z} over the tile and e = |image|^2 (- w for Laguerre)
     double2 cq[CAP_S];  // {min, max} distance to the tile box
     int2 cm[CAP_S];     // {site index, flags}
 };
@@ -59,11 +60,11 @@ struct RegionLds {
     int ri[CAP_R];
     int wsum[NW];
     double wred[NW];
-    int flag;
 };
 
 struct FallbackLds {
     double4 cs[CAP_F];
+    double4 cg[CAP_F];
     double2 cb[CAP_F];  // {lower, upper} bound of the key over the tile box
     double2 cq[CAP_F];
     int2 cm[CAP_F];
@@ -103,6 +104,33 @@ __device__ inline double code_off(int c, double L) { return c == 1 ? -L : (c == 
 __device__ inline double min_image(double d, double H, double L)
 {
     return d >= H ? d - L : (d < -H ? d + L : d);
+}
+
+// q = e / d and r = e % d for 0 <= e < 2^30, 1 <= d, through a float
+// reciprocal with an exact integer correction step.
+__device__ inline int divmod_small(int e, int d, float rd, int& r)
+{
+    int q = (int)(((float)e + 0.5f) * rd);
+    r = e - q * d;
+    while (r < 0) {
+        --q;
+        r += d;
+    }
+    while (r >= d) {
+        ++q;
+        r -= d;
+    }
+    return q;
+}
+
+// Periodic bin index in [0, nb) for unwrapped b in [-2 nb, 3 nb).
+__device__ inline int wrap_bin(int b, int nb)
+{
+    b = b < 0 ? b + nb : b;
+    b = b < 0 ? b + nb : b;
+    b = b >= nb ? b - nb : b;
+    b = b >= nb ? b - nb : b;
+    return b;
 }
 
 __device__ inline double from_ordered(unsigned long long u)
@@ -166,6 +194,21 @@ __device__ inline double block_min(double v, double* wred, int tid)
     return r;
 }
 
+__device__ inline double block_max(double v, double* wred, int tid)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    if ((tid & (WAVE - 1)) == 0)
+        wred[tid / WAVE] = v;
+    __syncthreads();
+    double r = wred[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k)
+        r = fmax(r, wred[k]);
+    __syncthreads();
+    return r;
+}
+
 template <int KIND>
 __device__ inline double dist_key(double q, double p, double v, double rv)
 {
@@ -215,15 +258,18 @@ __device__ inline TileBox make_box(const JobDev& J, const int* v0, const int* ve
     return B;
 }
 
-// Bounds of site s over box B: wrap flags, lower/upper bound of the key and
-// min/max distance.
+// Bounds of site s over box B: wrap flags, lower/upper bound of the key,
+// min/max distance, and the linear-form record {image, e} used by the
+// dominance test (image = minimum image of s over the box, e = |image|^2,
+// minus w for Laguerre).
 template <int KIND, int DIM>
 __device__ inline void box_bounds(const JobDev& J, const JobConst& C, const TileBox& B, bool periodic,
                                   const double4& s, int& flags, double& lb, double& ub, double& dmn,
-                                  double& dmx)
+                                  double& dmx, double4& g)
 {
     const double sc[3] = {s.x, s.y, s.z};
-    double qmin = 0.0, qmax = 0.0;
+    double sg3[3] = {0.0, 0.0, 0.0};
+    double qmin = 0.0, qmax = 0.0, e = 0.0;
     flags = 0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -247,21 +293,27 @@ __device__ inline void box_bounds(const JobDev& J, const JobConst& C, const Tile
             dmin = fmax(0.0, fmax(B.lo[a] - sg, sg - B.hi[a]));
             dmax = fmax(fabs(sg - B.lo[a]), fabs(sg - B.hi[a]));
         }
+        sg3[a] = sg;
+        e += sg * sg;
         qmin += dmin * dmin;
         qmax += dmax * dmax;
     }
-    dmn = sqrt(qmin);
-    dmx = sqrt(qmax);
     if (KIND == KV) {
         lb = qmin;
         ub = qmax;
+        dmn = dmx = 0.0;
     } else if (KIND == KL) {
         lb = qmin - s.w;
         ub = qmax - s.w;
+        e -= s.w;
+        dmn = dmx = 0.0;
     } else {
+        dmn = sqrt(qmin);
+        dmx = sqrt(qmax);
         lb = s.w + dmn * C.rv;
         ub = s.w + dmx * C.rv;
     }
+    g = make_double4(sg3[0], sg3[1], sg3[2], e);
 }
 
 // Upper bound only (cheaper: no flags, no lower bound).
@@ -331,61 +383,45 @@ __device__ inline double gap_high(const JobDev& J, const TileBox& B, int a, int 
 }
 
 // True if the listed site e loses to some other listed site on the whole box.
+// Voronoi and Laguerre: key_c - key_t = (e_c - e_t) + 2 x.(image_t - image_c),
+// linear in x, so its minimum over the box is at a corner.  Johnson-Mehl:
+// t_c + d_c/v - (t_t + d_t/v) >= (t_c - t_t) + lbd / v with lbd a lower bound
+// of d_c - d_t over the box, from d_c - d_t = (q_c - q_t) / (d_c + d_t).
 template <int KIND, int DIM>
-__device__ inline bool dominated(const double4* cs, const int2* cm, const double2* cq, int nc, int e,
-                                 const JobDev& J, const JobConst& C, const TileBox& B)
+__device__ inline bool dominated(const double4* cs, const double4* cg, const int2* cm, const double2* cq, int nc,
+                                 int e, const JobConst& C, const TileBox& B)
 {
-    const double4 c = cs[e];
-    const int2 me = cm[e];
+    const double4 gc = cg[e];
+    const double tc = cs[e].w;
     const double2 mq = cq[e];
-    const bool cgen = (me.y & FL_GENERIC) != 0;
-    double sc[3] = {c.x, c.y, c.z};
-    if (!cgen)
-        for (int a = 0; a < DIM; ++a)
-            sc[a] += code_off((me.y >> (2 * a)) & 3, J.L[a]);
+    const bool cgen = (cm[e].y & FL_GENERIC) != 0;
+    const double gcv[3] = {gc.x, gc.y, gc.z};
     bool dom = false;
     for (int t = 0; t < nc; ++t) {
-        const double4 o = cs[t];
-        const int2 om = cm[t];
-        if (t == e)
-            continue;
-        if (KIND == KV || KIND == KL) {
-            if (cgen || (om.y & FL_GENERIC))
-                continue;
-            // key_c - key_t = sum_a (sc - so)(sc + so - 2 x_a) - w_c + w_t, linear in x
-            const double oc[3] = {o.x, o.y, o.z};
-            double D = 0.0;
+        const double4 go = cg[t];
+        const bool ogen = (cm[t].y & FL_GENERIC) != 0;
+        double Dq = 0.0;
+        if (!cgen && !ogen) {
+            const double gov[3] = {go.x, go.y, go.z};
+            double lin = 0.0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                const double so = oc[a] + code_off((om.y >> (2 * a)) & 3, J.L[a]);
-                const double al = sc[a] - so;
-                const double xs = al > 0.0 ? B.hi[a] : B.lo[a];
-                D += al * ((sc[a] + so) - 2.0 * xs);
+                const double al = gov[a] - gcv[a];
+                lin += fmin(al * B.lo[a], al * B.hi[a]);
             }
-            if (KIND == KL)
-                D = D - c.w + o.w;
-            dom = dom || D > C.M;
+            Dq = (gc.w - go.w) + 2.0 * lin;
+        }
+        if (KIND == KV || KIND == KL) {
+            dom = dom || (t != e && !cgen && !ogen && Dq > C.M);
         } else {
-            // t_c + d_c/v - (t_t + d_t/v) >= (t_c - t_t) + lbd / v, lbd a lower
-            // bound of d_c - d_t over the box.
             const double2 oq = cq[t];
             double lbd = mq.x - oq.y;
-            if (!cgen && !(om.y & FL_GENERIC)) {
-                const double oc[3] = {o.x, o.y, o.z};
-                double Dq = 0.0;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    const double so = oc[a] + code_off((om.y >> (2 * a)) & 3, J.L[a]);
-                    const double al = sc[a] - so;
-                    const double xs = al > 0.0 ? B.hi[a] : B.lo[a];
-                    Dq += al * ((sc[a] + so) - 2.0 * xs);
-                }
-                const double floor_den = C.sqrtL2 * 0x1p-10;
+            if (!cgen && !ogen) {
                 const double den = Dq > 0.0 ? mq.y + oq.y : mq.x + oq.x;
-                if (den >= floor_den)
+                if (den >= C.sqrtL2 * 0x1p-10)
                     lbd = fmax(lbd, Dq / den);
             }
-            dom = dom || ((c.w - o.w) + lbd * C.rv) > C.M;
+            dom = dom || (t != e && ((tc - cs[t].w) + lbd * C.rv) > C.M);
         }
     }
     return dom;
@@ -394,13 +430,13 @@ __device__ inline bool dominated(const double4* cs, const int2* cm, const double
 // Drops dominated entries of a wavefront's list (one entry per lane, nc <= 64),
 // then sorts the rest by site index.  Returns the new count.
 template <int KIND, int DIM>
-__device__ inline int prune_and_sort(double4* cs, int2* cm, double2* cq, int nc, int lane, const JobDev& J,
+__device__ inline int prune_and_sort(double4* cs, double4* cg, int2* cm, double2* cq, int nc, int lane,
                                      const JobConst& C, const TileBox& B)
 {
     const bool mine = lane < nc;
     bool keep = mine;
-    if (nc > 1 && mine)
-        keep = !dominated<KIND, DIM>(cs, cm, cq, nc, lane, J, C, B);
+    if (nc > 1)
+        keep = !dominated<KIND, DIM>(cs, cg, cm, cq, nc, mine ? lane : 0, C, B) && mine;
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
     int2 m = make_int2(0, 0);
     if (mine) {
@@ -434,7 +470,9 @@ __device__ inline void evaluate(const double4* cs, const int2* cm, int nc, bool 
     for (int k = 0; k < nc; ++k) {
         const double4 s = cs[k];
         const int2 m = cm[k];
-        const int idx = m.x, fl = m.y;
+        // the list entry is the same for every lane: keep index and flags in
+        // scalar registers so that the branches below are scalar
+        const int idx = __builtin_amdgcn_readfirstlane(m.x), fl = __builtin_amdgcn_readfirstlane(m.y);
         double c;
         double dxv[RUN];
         if (fl == 0) {
@@ -623,7 +661,7 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
             }
             const int p = ch_off + lane;
             const bool valid = p < ch_T;
-            double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+            double4 s = make_double4(0.0, 0.0, 0.0, 0.0), g = s;
             int sid = 0, flags = 0;
             double lb = __builtin_inf(), ub = __builtin_inf(), dmn = 0.0, dmx = 0.0;
             if (valid) {
@@ -639,7 +677,7 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
                 const int pos = S.bsrc[lo] + (p - excl);
                 s = J.sites[pos];
                 sid = J.sidx[pos];
-                box_bounds<KIND, DIM>(J, C, B, periodic, s, flags, lb, ub, dmn, dmx);
+                box_bounds<KIND, DIM>(J, C, B, periodic, s, flags, lb, ub, dmn, dmx, g);
             }
             UB = fmin(UB, wave_min(ub));
             const bool keep = valid && lb <= UB + C.M;
@@ -647,6 +685,7 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
             if (keep) {
                 const int slot = nc + __popcll(km & lanes_below(lane));
                 S.cs[slot] = s;
+                S.cg[slot] = g;
                 S.cb[slot] = make_double2(lb, ub);
                 S.cq[slot] = make_double2(dmn, dmx);
                 S.cm[slot] = make_int2(sid, flags);
@@ -662,12 +701,13 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
         if (nc > 0) {
             // keep the entries under the current UB, then prune, sort, evaluate
             const double thr = UB + C.M;
-            double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+            double4 s = make_double4(0.0, 0.0, 0.0, 0.0), g = s;
             double2 q = make_double2(0.0, 0.0);
             int2 m = make_int2(0, 0);
             bool keep = false;
             if (lane < nc) {
                 s = S.cs[lane];
+                g = S.cg[lane];
                 q = S.cq[lane];
                 m = S.cm[lane];
                 keep = S.cb[lane].x <= thr;
@@ -677,12 +717,13 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
             if (keep) {
                 const int d = __popcll(km & lanes_below(lane));
                 S.cs[d] = s;
+                S.cg[d] = g;
                 S.cq[d] = q;
                 S.cm[d] = m;
             }
             nc = __popcll(km);
             wave_sync();
-            nc = prune_and_sort<KIND, DIM>(S.cs, S.cm, S.cq, nc, lane, J, C, B);
+            nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, nc, lane, C, B);
             evaluate<KIND, DIM, RUN>(S.cs, S.cm, nc, lex, J, C, periodic, xr, yv, zv, best, lab);
             lex = true;
             nc = 0;
@@ -701,14 +742,23 @@ struct LaneGeo {
     int mi, mj, mk; // first voxel of the lane's run
 };
 
+// Region coordinates of region r (regions are numbered x fastest; fewer
+// than 2^31 per job).
+__device__ inline void region_coords(const JobDev& J, int64_t r, int& rx, int& ry, int& rz)
+{
+    const unsigned u = (unsigned)r, n0 = (unsigned)J.nr[0], n1 = (unsigned)J.nr[1];
+    const unsigned q = u / n0;
+    rx = (int)(u - q * n0);
+    rz = (int)(q / n1);
+    ry = (int)(q - (unsigned)rz * n1);
+}
+
 template <int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
 __device__ inline LaneGeo lane_geometry(const JobDev& J, int64_t r, int w, int lane)
 {
     constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
-    const int rx = (int)(r % J.nr[0]);
-    const int64_t rr = r / J.nr[0];
-    const int ry = (int)(rr % J.nr[1]);
-    const int rz = (int)(rr / J.nr[1]);
+    int rx, ry, rz;
+    region_coords(J, r, rx, ry, rz);
     LaneGeo G;
     G.t0[0] = rx * TX * RX + (w % RX) * TX;
     G.t0[1] = ry * TY * RY + ((w / RX) % RY) * TY;
@@ -734,10 +784,8 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
     const int lane = tid & (WAVE - 1), w = tid / WAVE;
 
     // ---- region and tile geometry
-    const int rx = (int)(r % J.nr[0]);
-    const int64_t rr = r / J.nr[0];
-    const int ry = (int)(rr % J.nr[1]);
-    const int rz = (int)(rr / J.nr[1]);
+    int rx, ry, rz;
+    region_coords(J, r, rx, ry, rz);
     const int r0[3] = {rx * TX * RX, ry * TY * RY, rz * TZ * RZ};
     const int re[3] = {min(r0[0] + TX * RX, J.n[0]) - 1, min(r0[1] + TY * RY, J.n[1]) - 1,
                        min(r0[2] + TZ * RZ, J.n[2]) - 1};
@@ -792,28 +840,34 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             olo[a] = 1;
             ohi[a] = 0;
         }
-        int nR = 0;
+        int nR = 0, nDone = 0;
         bool overflow = false;
+        double ubT = __builtin_inf();  // this tile's upper bound (wave-uniform)
         for (int round = 0;; ++round) {
             // load every bin of the box that is not in the previous box
             const int nbx = bhi[0] - blo[0] + 1, nby = bhi[1] - blo[1] + 1, nbz = bhi[2] - blo[2] + 1;
             const int64_t nbox = (int64_t)nbx * nby * nbz;
+            if (nbox >= (1 << 30)) {  // beyond the bin decoding's range: leave it to the fallback
+                overflow = true;
+                break;
+            }
+            const float rnx = 1.0f / (float)nbx, rnxy = 1.0f / (float)(nbx * nby);
             for (int64_t base = 0; base < nbox; base += NT) {
                 const int64_t e = base + tid;
                 int cnt = 0, src = 0;
                 if (e < nbox) {
-                    const int ex = (int)(e % nbx);
-                    const int64_t e2 = e / nbx;
-                    const int ey = (int)(e2 % nby), ez = (int)(e2 / nby);
+                    int rxy, ex;
+                    const int ez = divmod_small((int)e, nbx * nby, rnxy, rxy);
+                    const int ey = divmod_small(rxy, nbx, rnx, ex);
                     const int bx = blo[0] + ex, by = blo[1] + ey, bz = blo[2] + ez;
                     const bool old = bx >= olo[0] && bx <= ohi[0] && by >= olo[1] && by <= ohi[1] && bz >= olo[2] &&
                                      bz <= ohi[2];
                     if (!old) {
                         int wx = bx, wy = by, wz = bz;
                         if (periodic) {
-                            wx = ((wx % J.nb[0]) + J.nb[0]) % J.nb[0];
-                            wy = ((wy % J.nb[1]) + J.nb[1]) % J.nb[1];
-                            wz = ((wz % J.nb[2]) + J.nb[2]) % J.nb[2];
+                            wx = wrap_bin(wx, J.nb[0]);
+                            wy = wrap_bin(wy, J.nb[1]);
+                            wz = wrap_bin(wz, J.nb[2]);
                         }
                         const int lin = wx + J.nb[0] * (wy + J.nb[1] * wz);
                         src = J.bin_start[lin];
@@ -835,11 +889,15 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             if (overflow)
                 break;
             __syncthreads();
-            // UB over the region from every listed site
+            // Each tile's upper bound from the sites added in this round; the
+            // region's stopping level is the largest of them (every voxel of
+            // the region then has a winning key below it).
             double ubm = __builtin_inf();
-            for (int e = tid; e < nR; e += NT)
-                ubm = fmin(ubm, box_upper<KIND, DIM>(J, C, BR, periodic, R.rs[e]));
-            const double UB = block_min(ubm, R.wred, tid);
+            for (int e = nDone + lane; e < nR; e += WAVE)
+                ubm = fmin(ubm, box_upper<KIND, DIM>(J, C, BT, periodic, R.rs[e]));
+            ubT = fmin(ubT, wave_min(ubm));
+            nDone = nR;
+            const double UB = block_max(G.live ? ubT : -__builtin_inf(), R.wred, tid);
             // move the faces that are too close
             const double reach = needed_reach<KIND>(C, UB);
             const double need = reach + reach * 0x1p-20 + 1e-300;
@@ -861,7 +919,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     continue;
                 }
                 if (gap_low(J, BR, a, lo, periodic) <= need) {
-                    int t = (int)fmax(floor((BR.lo[a] - need) * J.inv_bs[a]), -2.0 * nb - 2.0);
+                    int t = (int)fmax(floor((BR.lo[a] - need) * J.inv_bs[a]), -1.0 * nb - 1.0);
                     lo = min(lo - 1, t);
                     if (!periodic)
                         lo = max(lo, 0);
@@ -869,7 +927,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                         --lo;
                 }
                 if (gap_high(J, BR, a, hi, periodic) <= need) {
-                    int t = (int)fmin(floor((BR.hi[a] + need) * J.inv_bs[a]), 3.0 * nb + 2.0);
+                    int t = (int)fmin(floor((BR.hi[a] + need) * J.inv_bs[a]), 2.0 * nb + 1.0);
                     hi = max(hi + 1, t);
                     if (!periodic)
                         hi = min(hi, nb - 1);
@@ -903,19 +961,16 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
         tile_ovf = overflow;
         if (!overflow && G.live) {
             TileLds& S = sm.r.tile[w];
-            double ubm = __builtin_inf();
-            for (int e = lane; e < nR; e += WAVE)
-                ubm = fmin(ubm, box_upper<KIND, DIM>(J, C, BT, periodic, R.rs[e]));
-            const double thr = wave_min(ubm) + C.M;
+            const double thr = ubT + C.M;
             int nc = 0;
             for (int ebase = 0; ebase < nR; ebase += WAVE) {
                 const int e = ebase + lane;
                 int flags = 0;
                 double lb = __builtin_inf(), ub, dmn = 0.0, dmx = 0.0;
-                double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+                double4 s = make_double4(0.0, 0.0, 0.0, 0.0), g = s;
                 if (e < nR) {
                     s = R.rs[e];
-                    box_bounds<KIND, DIM>(J, C, BT, periodic, s, flags, lb, ub, dmn, dmx);
+                    box_bounds<KIND, DIM>(J, C, BT, periodic, s, flags, lb, ub, dmn, dmx, g);
                 }
                 const bool keep = e < nR && lb <= thr;
                 const unsigned long long km = __ballot(keep);
@@ -926,6 +981,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 if (keep) {
                     const int slot = nc + __popcll(km & lanes_below(lane));
                     S.cs[slot] = s;
+                    S.cg[slot] = g;
                     S.cq[slot] = make_double2(dmn, dmx);
                     S.cm[slot] = make_int2(R.ri[e], flags);
                 }
@@ -933,7 +989,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             }
             wave_sync();
             if (!tile_ovf) {
-                nc = prune_and_sort<KIND, DIM>(S.cs, S.cm, S.cq, nc, lane, J, C, BT);
+                nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, nc, lane, C, BT);
                 evaluate<KIND, DIM, RUN>(S.cs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
             }
         }
