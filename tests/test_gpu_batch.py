@@ -1,0 +1,137 @@
+"""Batched persistent launches, resident bins, the serving loop and the
+autotuner: every job's labels must equal the same job run alone and the
+oracle, bit for bit."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13234_amd import inputs as I
+from gpu_util import describe_mismatch, run_oracle, to_dev, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2201_13234_amd import vtess
+    c = vtess.Context(0)
+    yield c
+    c.close()
+
+
+def mixed_jobs(n, seed, max3=40, max2=150):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n):
+        d = 2 + int(rng.integers(0, 2))
+        side = tuple(int(v) for v in rng.integers(1, (max3 if d == 3 else max2) + 1, d))
+        kind = int(rng.integers(0, 3))
+        ns = int(rng.integers(1, 500))
+        g = float(rng.choice([1.0, 0.5, 3.0]))
+        out.append(I.make(side, kind, bool(rng.integers(0, 2)), ns, seed=5000 + 31 * seed + j, growth=g))
+    return out
+
+
+def test_batch_equals_alone_equals_oracle(ctx):
+    import torch
+    ws = mixed_jobs(40, 1)
+    jobs = [to_dev(w) for w in ws]
+    status = torch.full((len(jobs),), 99, dtype=torch.int32, device="cuda:0")
+    ctx.tessellate_batch(jobs, status=status)
+    torch.cuda.synchronize()
+    assert status.cpu().tolist() == [0] * len(jobs)
+    for w, j in zip(ws, jobs):
+        got = j.labels.cpu().numpy()
+        ref = run_oracle(w)
+        assert np.array_equal(got, ref), f"{w.name}: " + describe_mismatch(got, ref)
+        alone = to_dev(w)
+        ctx.tessellate(alone)
+        torch.cuda.synchronize()
+        assert np.array_equal(alone.labels.cpu().numpy(), got)
+
+
+def test_batch_with_large_and_tiny_jobs(ctx):
+    import torch
+    ws = [I.m1(), I.make((1, 1, 1), 0, True, 3, 7), I.make((300, 200), 2, False, 4000, 8),
+          I.make((90, 70, 50), 1, True, 5000, 9), I.make((5, 300), 0, False, 1, 10)]
+    jobs = [to_dev(w) for w in ws]
+    ctx.tessellate_batch(jobs)
+    torch.cuda.synchronize()
+    for w, j in zip(ws, jobs):
+        assert np.array_equal(j.labels.cpu().numpy(), run_oracle(w)), w.name
+
+
+def test_one_bad_job_fails_alone(ctx):
+    import torch
+    ws = mixed_jobs(8, 2)
+    bad = ws[3]
+    bad.coords = bad.coords.copy()
+    bad.coords[0, 0] = -1.0
+    jobs = [to_dev(w) for w in ws]
+    status = torch.zeros(len(jobs), dtype=torch.int32, device="cuda:0")
+    ctx.tessellate_batch(jobs, status=status)
+    torch.cuda.synchronize()
+    st = status.cpu().tolist()
+    assert st[3] == 5 and np.all(jobs[3].labels.cpu().numpy() == -1)
+    for k, (w, j) in enumerate(zip(ws, jobs)):
+        if k != 3:
+            assert st[k] == 0
+            assert np.array_equal(j.labels.cpu().numpy(), run_oracle(w)), w.name
+
+
+def test_resident_bins_and_label_batches(ctx):
+    import torch
+    ws = mixed_jobs(12, 3)
+    s_bin, s_lab = torch.cuda.Stream(), torch.cuda.Stream()
+    jobs = [to_dev(w) for w in ws]
+    torch.cuda.synchronize()
+    st_b = torch.full((len(jobs),), 99, dtype=torch.int32, device="cuda:0")
+    bins = [ctx.bins_build(j, status=st_b[k:k + 1], stream=s_bin) for k, j in enumerate(jobs)]
+    ev = torch.cuda.Event()
+    ev.record(s_bin)
+    s_lab.wait_event(ev)
+    status = torch.full((6,), 99, dtype=torch.int32, device="cuda:0")
+    ctx.label_batch(bins[:6], status=status, stream=s_lab)
+    ctx.label_batch(bins[6:], stream=s_lab)
+    for b in bins:
+        b.free(stream=s_lab)
+    s_lab.synchronize()
+    assert status.cpu().tolist() == [0] * 6
+    assert st_b.cpu().tolist() == [0] * 12
+    for w, j in zip(ws, jobs):
+        assert np.array_equal(j.labels.cpu().numpy(), run_oracle(w)), w.name
+
+
+def test_serving_mix_equals_alone(ctx):
+    from paper_2201_13234_amd import serve as S
+    ex = S.GpuExecutor(ctx)
+    reqs = S.make_stream(40, rate=400.0, side_scale=0.12)
+    srv = S.Server(ex, mem_budget=1 << 30, max_batch=16)
+    mixed = srv.run([S.Request(r.rid, r.workload, r.arrival) for r in reqs])
+    alone = S.Server(ex).run_one_by_one([S.Request(r.rid, r.workload, r.arrival) for r in reqs])
+    assert all(r.status == 0 for r in mixed) and all(r.status == 0 for r in alone)
+    assert [r.digest for r in mixed] == [r.digest for r in alone]
+    for r in mixed[::5]:
+        assert r.digest == S.digest_host(run_oracle(r.workload)), r.workload.name
+    assert max(srv.batches) > 1
+
+
+def test_autotune_roundtrip(ctx, tmp_path):
+    import torch
+    from paper_2201_13234_amd import vtess
+    w = I.make((96, 80, 64), 0, True, 3000, 12)
+    path = str(tmp_path / "tune.json")
+    ctx.autotune([to_dev(w)], cache_path=path)
+    text = open(path).read()
+    assert '"tile_cfg"' in text and '"bin_factor"' in text
+    c2 = vtess.Context(0)
+    c2.load_tuning(path)
+    plan = c2.plan(to_dev(w))
+    assert plan["tile_cfg"] in (0, 1, 2)
+    job = to_dev(w)
+    c2.tessellate(job)
+    torch.cuda.synchronize()
+    assert np.array_equal(job.labels.cpu().numpy(), run_oracle(w))
+    c2.close()
