@@ -34,6 +34,7 @@ class Request:
     digest: int = 0           # hash of the label image
     error: str = ""
     state: dict = field(default_factory=dict)
+    labels: object = None     # device label image kept after completion
 
     @property
     def nvox(self):
@@ -54,7 +55,8 @@ def device_bytes(w):
 
 class Executor:
     """Device operations the scheduler needs (all asynchronous except
-    run_alone)."""
+    run_alone).  max_inflight: labelling launches that may run at once."""
+    max_inflight = 1
 
     def prepare(self, req):           # allocate and upload; raises MemoryError
         raise NotImplementedError
@@ -71,7 +73,7 @@ class Executor:
     def labelling_done(self, token):
         raise NotImplementedError
 
-    def finish(self, req):            # status + digest, release device memory
+    def finish(self, req):            # status, release device memory
         raise NotImplementedError
 
     def run_alone(self, req):         # prepare + tessellate + finish, synchronous
@@ -79,22 +81,40 @@ class Executor:
 
 
 class GpuExecutor(Executor):
-    """Executor over the device library, two HIP streams (binning, labelling)."""
+    """Executor over the device library.
 
-    def __init__(self, ctx, device="cuda:0"):
+    Uploads run on their own stream.  Labelling launches alternate between
+    `lanes` (context, stream) pairs so that one batch can be binned while the
+    previous one is still labelling.  Two modes:
+      resident_bins=False  each launch is one vt_tessellate_batch call:
+                           segmented binning of the batch plus one persistent
+                           labelling launch;
+      resident_bins=True   every request is binned on arrival (vt_bins_build,
+                           bins stay on the device) and a launch is one
+                           vt_label_batch over the resident bins.
+    With keep_labels the label images stay on the device after completion so
+    that digest_all() can hash them outside the timed replay.
+    """
+
+    def __init__(self, ctx, device="cuda:0", lanes=2, resident_bins=False, keep_labels=True):
         import torch
+        from . import vtess
         self.torch = torch
-        self.ctx = ctx
         self.dev = torch.device(device)
-        self.s_bin = torch.cuda.Stream(device=self.dev)
-        self.s_lab = torch.cuda.Stream(device=self.dev)
+        self.ctxs = [ctx] + [vtess.Context(self.dev.index or 0) for _ in range(lanes - 1)]
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
+        self.s_up = torch.cuda.Stream(device=self.dev)
+        self.free_lanes = list(range(lanes))
+        self.max_inflight = lanes
+        self.resident_bins = resident_bins
+        self.keep_labels = keep_labels
 
     def _job(self, req):
         from . import vtess
         torch = self.torch
         w = req.workload
         st = req.state
-        with torch.cuda.stream(self.s_bin):
+        with torch.cuda.stream(self.s_up):
             st["coords"] = torch.from_numpy(np.ascontiguousarray(w.coords)).pin_memory().to(
                 self.dev, non_blocking=True)
             st["param"] = None if w.param is None else torch.from_numpy(
@@ -109,51 +129,68 @@ class GpuExecutor(Executor):
 
     def start_binning(self, req):
         st = req.state
-        st["bins"] = self.ctx.bins_build(st["job"], status=st["status"], stream=self.s_bin)
+        if self.resident_bins:
+            st["bins"] = self.ctxs[0].bins_build(st["job"], status=st["status"], stream=self.s_up)
         ev = self.torch.cuda.Event()
-        ev.record(self.s_bin)
-        st["ev_bin"] = ev
+        ev.record(self.s_up)
+        st["ev_ready"] = ev
 
     def binning_done(self, req):
-        return req.state["ev_bin"].query()
+        return req.state["ev_ready"].query()
 
     def start_labelling(self, reqs):
         torch = self.torch
+        lane = self.free_lanes.pop(0)
+        s = self.streams[lane]
         for r in reqs:
-            self.s_lab.wait_event(r.state["ev_bin"])
-        self.ctx.label_batch([r.state["bins"] for r in reqs], stream=self.s_lab)
-        with torch.cuda.stream(self.s_lab):
-            for r in reqs:
-                r.state["hash"] = digest_device(r.state["labels"])
+            s.wait_event(r.state["ev_ready"])
+        if self.resident_bins:
+            st = torch.empty(len(reqs), dtype=torch.int32, device=self.dev)
+            self.ctxs[lane].label_batch([r.state["bins"] for r in reqs], status=st, stream=s)
+        else:
+            with torch.cuda.stream(s):
+                st = torch.empty(len(reqs), dtype=torch.int32, device=self.dev)
+            self.ctxs[lane].tessellate_batch([r.state["job"] for r in reqs], status=st, stream=s)
+        for k, r in enumerate(reqs):
+            r.state["status"] = st[k:k + 1]
         ev = torch.cuda.Event()
-        ev.record(self.s_lab)
-        return ev
+        ev.record(s)
+        return (lane, ev)
 
     def labelling_done(self, token):
-        return token.query()
+        if token[1].query():
+            if token[0] not in self.free_lanes:
+                self.free_lanes.append(token[0])
+            return True
+        return False
 
     def finish(self, req):
         st = req.state
         req.status = int(st["status"].item())
-        req.digest = int(st["hash"].item())
-        st["bins"].free(stream=self.s_lab)
+        if self.resident_bins:
+            st["bins"].free(stream=self.s_up)
+        if self.keep_labels:
+            req.labels = st["labels"]
         req.state = {}
 
     def run_alone(self, req):
-        torch = self.torch
         job = self._job(req)
         st = req.state
-        self.s_lab.wait_stream(self.s_bin)
-        self.ctx.tessellate(job, status=st["status"], stream=self.s_lab)
-        with torch.cuda.stream(self.s_lab):
-            h = digest_device(st["labels"])
-        self.s_lab.synchronize()
+        s = self.streams[0]
+        s.wait_stream(self.s_up)
+        self.ctxs[0].tessellate(job, status=st["status"], stream=s)
+        s.synchronize()
         req.status = int(st["status"].item())
-        req.digest = int(h.item())
+        if self.keep_labels:
+            req.labels = st["labels"]
         req.state = {}
 
-    def labels_of(self, req):
-        return req.state.get("labels")
+    def digest_all(self, reqs):
+        """Hashes the kept label images (after the replay) and drops them."""
+        for r in reqs:
+            if getattr(r, "labels", None) is not None:
+                r.digest = int(digest_device(r.labels).item())
+                r.labels = None
 
 
 # Order-sensitive hash of a label image: sum over voxels i of
@@ -206,7 +243,7 @@ class Server:
         queue = list(reqs)            # not yet admitted, arrival order
         binning = []                  # admitted, bins being built
         ready = []                    # bins ready, waiting for a labelling launch
-        running = None                # (token, [requests]) of the launch in flight
+        running = []                  # (token, [requests]) of the launches in flight
         active = 0
         done = []
         while queue or binning or ready or running:
@@ -242,7 +279,7 @@ class Server:
                 active += 1
                 binning.append(r)
                 progressed = True
-            # bins that finished
+            # requests whose inputs (or bins) are ready
             still = []
             for r in binning:
                 if self.ex.binning_done(r):
@@ -251,22 +288,26 @@ class Server:
                 else:
                     still.append(r)
             binning = still
-            # retire the running launch
-            if running is not None and self.ex.labelling_done(running[0]):
-                t_done = now()
-                for r in running[1]:
-                    r.done = t_done
-                    nbytes = r.state.get("bytes", 0)
-                    self.ex.finish(r)
-                    self.mem_in_use -= nbytes
-                    active -= 1
-                    done.append(r)
-                running = None
-                progressed = True
-            # launch everything that is ready while the labelling stream is idle
-            if running is None and ready:
+            # retire finished launches
+            keep = []
+            for token, batch in running:
+                if self.ex.labelling_done(token):
+                    t_done = now()
+                    for r in batch:
+                        r.done = t_done
+                        nbytes = r.state.get("bytes", 0)
+                        self.ex.finish(r)
+                        self.mem_in_use -= nbytes
+                        active -= 1
+                        done.append(r)
+                    progressed = True
+                else:
+                    keep.append((token, batch))
+            running = keep
+            # launch what is ready while a lane is free
+            if ready and len(running) < self.ex.max_inflight:
                 batch, ready = ready[: self.max_batch], ready[self.max_batch:]
-                running = (self.ex.start_labelling(batch), batch)
+                running.append((self.ex.start_labelling(batch), batch))
                 self.batches.append(len(batch))
                 progressed = True
             if not progressed:
@@ -314,29 +355,35 @@ def make_stream(n_jobs, rate, side_scale=0.25, first_job=0):
             for i in range(n_jobs)]
 
 
-def benchmark(ctx, n_jobs=96, side_scale=0.25, load=0.8, mem_budget=8 << 30):
+def benchmark(ctx, n_jobs=96, side_scale=0.25, load=0.8, mem_budget=8 << 30, lanes=2):
     """Replays a request stream twice on the GPU -- continuous batching and one
     by one -- with the same arrival times.  The arrival rate is `load` times
-    the one-by-one service rate measured on a warm-up of the first jobs.
+    the one-by-one service rate, measured on the same jobs run back to back.
     Returns p50/p99 latency and throughput of both, and whether every job's
     labels are identical in both modes."""
-    ex = GpuExecutor(ctx)
-    warm = make_stream(min(16, n_jobs), 1.0, side_scale)
-    for r in warm:                       # warm-up and service-rate calibration
-        r.arrival = 0.0
-    Server(ex).run_one_by_one(warm)
-    t0 = time.perf_counter()
-    Server(ex).run_one_by_one([Request(r.rid, r.workload, 0.0) for r in warm])
-    service = (time.perf_counter() - t0) / len(warm)
+    ex = GpuExecutor(ctx, lanes=lanes)
+    jobs = make_stream(n_jobs, 1.0, side_scale)
+    # warm-up of both paths, then the one-by-one service time of exactly these
+    # jobs, back to back
+    Server(ex).run_one_by_one([Request(r.rid, r.workload, 0.0) for r in jobs[:16]])
+    Server(ex).run([Request(r.rid, r.workload, 0.0) for r in jobs[:16]])
+    cal = Server(ex).run_one_by_one([Request(r.rid, r.workload, 0.0) for r in jobs])
+    service = max(r.done for r in cal) / len(cal)
+    for r in cal:
+        r.labels = None
     rate = load / service
-    stream = make_stream(n_jobs, rate, side_scale)
+    from . import inputs
+    t = inputs.arrivals(n_jobs, rate)
+    stream = [Request(r.rid, r.workload, float(t[k])) for k, r in enumerate(jobs)]
     srv = Server(ex, mem_budget=mem_budget)
     batched = srv.run([Request(r.rid, r.workload, r.arrival) for r in stream])
+    ex.digest_all(batched)
     alone = Server(ex, mem_budget=mem_budget).run_one_by_one(
         [Request(r.rid, r.workload, r.arrival) for r in stream])
+    ex.digest_all(alone)
     same = all(a.digest == b.digest and a.status == b.status for a, b in zip(batched, alone))
     return {"jobs": n_jobs, "side_scale": side_scale, "rate_per_s": round(rate, 2),
-            "service_ms_alone": round(service * 1e3, 3),
+            "service_ms_alone": round(service * 1e3, 3), "lanes": lanes,
             "batched": summarize(batched), "one_by_one": summarize(alone),
             "mean_batch": round(float(np.mean(srv.batches)), 2) if srv.batches else 0,
             "labels_identical": bool(same)}

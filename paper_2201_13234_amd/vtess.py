@@ -46,6 +46,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"device library not built: {LIB_PATH} is missing "
                                "(run __graft_entry__.build())")
+        # PyTorch ships its own HIP runtime under the same soname.  Load it
+        # first so that the library binds to that one runtime: tensors and
+        # streams then come from the runtime the kernels launch on.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         P = ctypes.POINTER

@@ -104,13 +104,16 @@ def test_resident_bins_and_label_batches(ctx):
         assert np.array_equal(j.labels.cpu().numpy(), run_oracle(w)), w.name
 
 
-def test_serving_mix_equals_alone(ctx):
+@pytest.mark.parametrize("resident", [False, True])
+def test_serving_mix_equals_alone(ctx, resident):
     from paper_2201_13234_amd import serve as S
-    ex = S.GpuExecutor(ctx)
+    ex = S.GpuExecutor(ctx, resident_bins=resident)
     reqs = S.make_stream(40, rate=400.0, side_scale=0.12)
     srv = S.Server(ex, mem_budget=1 << 30, max_batch=16)
     mixed = srv.run([S.Request(r.rid, r.workload, r.arrival) for r in reqs])
+    ex.digest_all(mixed)
     alone = S.Server(ex).run_one_by_one([S.Request(r.rid, r.workload, r.arrival) for r in reqs])
+    ex.digest_all(alone)
     assert all(r.status == 0 for r in mixed) and all(r.status == 0 for r in alone)
     assert [r.digest for r in mixed] == [r.digest for r in alone]
     for r in mixed[::5]:
