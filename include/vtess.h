@@ -114,8 +114,8 @@ vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path);
 
 /* Forces the tile configuration and bin-size factor of later calls
  * (tile_cfg < 0 and bin_factor <= 0 restore the tuned/default choice).
- * Tile configurations: 3D 0 = 8x8x8, 1 = 16x8x4, 2 = 32x4x4;
- * 2D 0 = 32x16, 1 = 16x32, 2 = 64x8 (voxels, x first). */
+ * Tile configurations (voxels, x first): 3D 0 = 8x16x8, 1 = 8x8x8,
+ * 2 = 16x16x4; 2D 0 = 32x32, 1 = 32x16, 2 = 16x64. */
 vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor);
 
 /* Bins per axis and tile configuration the next call would use for job. */

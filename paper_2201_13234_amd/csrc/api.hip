@@ -208,7 +208,7 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d, bool batch)
     d->nbins = (int32_t)nbins;
 
     const vt::TileShape sh = vt::shape_of(j->ndim, cfg);
-    const int R[3] = {sh.run * sh.lx * sh.rx, sh.ly * sh.ry, j->ndim == 3 ? sh.lz * sh.rz : 1};
+    const int R[3] = {sh.run * sh.lx * sh.rx, sh.ly * sh.rows * sh.ry, j->ndim == 3 ? sh.lz * sh.rz : 1};
     int64_t nregions = 1;
     for (int a = 0; a < 3; ++a) {
         d->nr[a] = (d->n[a] + R[a] - 1) / R[a];

@@ -41,6 +41,7 @@ constexpr int NT = NW * WAVE;  // threads per workgroup
 constexpr int CAP_R = 384;     // region candidate capacity (LDS)
 constexpr int CAP_S = 64;      // tile candidate capacity (LDS, per wavefront)
 constexpr int CAP_F = 64;      // fallback per-tile capacity (LDS, per wavefront)
+constexpr int R_DOM = 8;       // dominance references: the candidates with the smallest upper bounds
 
 // flags: wrap code per axis in bits 2a..2a+1 (0 none, 1 subtract L, 2 add L),
 // bit 6 = some axis needs a per-voxel minimum-image test.
@@ -52,6 +53,7 @@ struct TileLds {
     double4 cs[CAP_S];  // site {x, y, z, param}
     double4 cg[CAP_S];  // minimum image {x, y, z} over the tile and e = |image|^2 (- w for Laguerre)
     double2 cq[CAP_S];  // {min, max} distance to the tile box
+    double cu[CAP_S];   // upper bound of the key over the tile box
     int2 cm[CAP_S];     // {site index, flags}
 };
 
@@ -67,6 +69,7 @@ struct FallbackLds {
     double4 cg[CAP_F];
     double2 cb[CAP_F];  // {lower, upper} bound of the key over the tile box
     double2 cq[CAP_F];
+    double cu[CAP_F];
     int2 cm[CAP_F];
     int bcnt[WAVE];
     int bsrc[WAVE];
@@ -388,8 +391,8 @@ __device__ inline double gap_high(const JobDev& J, const TileBox& B, int a, int 
 // t_c + d_c/v - (t_t + d_t/v) >= (t_c - t_t) + lbd / v with lbd a lower bound
 // of d_c - d_t over the box, from d_c - d_t = (q_c - q_t) / (d_c + d_t).
 template <int KIND, int DIM>
-__device__ inline bool dominated(const double4* cs, const double4* cg, const int2* cm, const double2* cq, int nc,
-                                 int e, const JobConst& C, const TileBox& B)
+__device__ inline bool dominated(const double4* cs, const double4* cg, const int2* cm, const double2* cq, int e,
+                                 unsigned long long refs, const JobConst& C, const TileBox& B)
 {
     const double4 gc = cg[e];
     const double tc = cs[e].w;
@@ -397,7 +400,9 @@ __device__ inline bool dominated(const double4* cs, const double4* cg, const int
     const bool cgen = (cm[e].y & FL_GENERIC) != 0;
     const double gcv[3] = {gc.x, gc.y, gc.z};
     bool dom = false;
-    for (int t = 0; t < nc; ++t) {
+    while (refs) {
+        const int t = __ffsll((unsigned long long)refs) - 1;
+        refs &= refs - 1;
         const double4 go = cg[t];
         const bool ogen = (cm[t].y & FL_GENERIC) != 0;
         double Dq = 0.0;
@@ -428,15 +433,27 @@ __device__ inline bool dominated(const double4* cs, const double4* cg, const int
 }
 
 // Drops dominated entries of a wavefront's list (one entry per lane, nc <= 64),
-// then sorts the rest by site index.  Returns the new count.
+// then sorts the rest by site index.  Each entry is tested against the R_DOM
+// entries with the smallest upper bounds (the sites nearest the tile, which
+// beat far sites on the whole tile); a dropped entry is always beaten by a
+// listed site, so the winner of every voxel stays.  Returns the new count.
 template <int KIND, int DIM>
-__device__ inline int prune_and_sort(double4* cs, double4* cg, int2* cm, double2* cq, int nc, int lane,
-                                     const JobConst& C, const TileBox& B)
+__device__ inline int prune_and_sort(double4* cs, double4* cg, int2* cm, double2* cq, const double* cu, int nc,
+                                     int lane, const JobConst& C, const TileBox& B)
 {
     const bool mine = lane < nc;
     bool keep = mine;
-    if (nc > 1)
-        keep = !dominated<KIND, DIM>(cs, cg, cm, cq, nc, mine ? lane : 0, C, B) && mine;
+    if (nc > 1) {
+        // rank of this entry by upper bound (ties by position)
+        const double u = mine ? cu[lane] : 0.0;
+        int ru = 0;
+        for (int t = 0; t < nc; ++t) {
+            const double ut = cu[t];
+            ru += (ut < u || (ut == u && t < lane)) ? 1 : 0;
+        }
+        const unsigned long long refs = __ballot(mine && ru < R_DOM);
+        keep = !dominated<KIND, DIM>(cs, cg, cm, cq, mine ? lane : 0, refs, C, B) && mine;
+    }
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
     int2 m = make_int2(0, 0);
     if (mine) {
@@ -461,10 +478,12 @@ __device__ inline int prune_and_sort(double4* cs, double4* cg, int2* cm, double2
     return n;
 }
 
-// Exact keys of the listed sites (ascending index) at the lane's run.
-template <int KIND, int DIM, int RUN>
+// Exact keys of the listed sites (ascending index) at the lane's ROWS runs of
+// RUN voxels (row r at y = yv[r]).  The x terms d0*d0 are shared by the rows;
+// the sum keeps the grouping d0*d0 + (d1*d1 + d2*d2).
+template <int KIND, int DIM, int RUN, int ROWS>
 __device__ inline void evaluate(const double4* cs, const int2* cm, int nc, bool lex, const JobDev& J,
-                                const JobConst& C, bool periodic, const double* xr, double yv, double zv,
+                                const JobConst& C, bool periodic, const double* xr, const double* yv, double zv,
                                 double* best, int* lab)
 {
     for (int k = 0; k < nc; ++k) {
@@ -473,82 +492,98 @@ __device__ inline void evaluate(const double4* cs, const int2* cm, int nc, bool 
         // the list entry is the same for every lane: keep index and flags in
         // scalar registers so that the branches below are scalar
         const int idx = __builtin_amdgcn_readfirstlane(m.x), fl = __builtin_amdgcn_readfirstlane(m.y);
-        double c;
-        double dxv[RUN];
+        double c[ROWS];
+        double dx2[RUN];
         if (fl == 0) {
-            const double dy = s.y - yv;
-            if (DIM == 3) {
-                const double dz = s.z - zv;
-                c = dy * dy + dz * dz;
-            } else {
-                c = dy * dy;
+            const double dz = (DIM == 3) ? s.z - zv : 0.0;
+            const double dz2 = dz * dz;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double dy = s.y - yv[r];
+                c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
             }
 #pragma unroll
-            for (int q = 0; q < RUN; ++q)
-                dxv[q] = s.x - xr[q];
+            for (int q = 0; q < RUN; ++q) {
+                const double dx = s.x - xr[q];
+                dx2[q] = dx * dx;
+            }
         } else if (!(fl & FL_GENERIC)) {
-            const double dy = (s.y - yv) + code_off((fl >> 2) & 3, J.L[1]);
-            if (DIM == 3) {
-                const double dz = (s.z - zv) + code_off((fl >> 4) & 3, J.L[2]);
-                c = dy * dy + dz * dz;
-            } else {
-                c = dy * dy;
+            const double dz = (DIM == 3) ? (s.z - zv) + code_off((fl >> 4) & 3, J.L[2]) : 0.0;
+            const double dz2 = dz * dz;
+            const double oy = code_off((fl >> 2) & 3, J.L[1]);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double dy = (s.y - yv[r]) + oy;
+                c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
             }
             const double ox = code_off(fl & 3, J.L[0]);
 #pragma unroll
-            for (int q = 0; q < RUN; ++q)
-                dxv[q] = (s.x - xr[q]) + ox;
+            for (int q = 0; q < RUN; ++q) {
+                const double dx = (s.x - xr[q]) + ox;
+                dx2[q] = dx * dx;
+            }
         } else {
-            const double dy = periodic ? min_image(s.y - yv, J.H[1], J.L[1]) : s.y - yv;
-            if (DIM == 3) {
-                const double dz = periodic ? min_image(s.z - zv, J.H[2], J.L[2]) : s.z - zv;
-                c = dy * dy + dz * dz;
-            } else {
-                c = dy * dy;
+            const double dz = (DIM == 3) ? (periodic ? min_image(s.z - zv, J.H[2], J.L[2]) : s.z - zv) : 0.0;
+            const double dz2 = dz * dz;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double dy = periodic ? min_image(s.y - yv[r], J.H[1], J.L[1]) : s.y - yv[r];
+                c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
             }
 #pragma unroll
-            for (int q = 0; q < RUN; ++q)
-                dxv[q] = periodic ? min_image(s.x - xr[q], J.H[0], J.L[0]) : s.x - xr[q];
+            for (int q = 0; q < RUN; ++q) {
+                const double dx = periodic ? min_image(s.x - xr[q], J.H[0], J.L[0]) : s.x - xr[q];
+                dx2[q] = dx * dx;
+            }
         }
-        if (!lex) {
 #pragma unroll
-            for (int q = 0; q < RUN; ++q) {
-                const double key = dist_key<KIND>(dxv[q] * dxv[q] + c, s.w, C.v, C.rv);
-                lab[q] = key < best[q] ? idx : lab[q];
-                best[q] = fmin(best[q], key);
-            }
-        } else {
+        for (int r = 0; r < ROWS; ++r) {
+            if (!lex) {
 #pragma unroll
-            for (int q = 0; q < RUN; ++q) {
-                const double key = dist_key<KIND>(dxv[q] * dxv[q] + c, s.w, C.v, C.rv);
-                const bool lt = key < best[q] || (key == best[q] && idx < lab[q]);
-                lab[q] = lt ? idx : lab[q];
-                best[q] = fmin(best[q], key);
+                for (int q = 0; q < RUN; ++q) {
+                    const double key = dist_key<KIND>(dx2[q] + c[r], s.w, C.v, C.rv);
+                    lab[r * RUN + q] = key < best[r * RUN + q] ? idx : lab[r * RUN + q];
+                    best[r * RUN + q] = fmin(best[r * RUN + q], key);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < RUN; ++q) {
+                    const double key = dist_key<KIND>(dx2[q] + c[r], s.w, C.v, C.rv);
+                    const bool lt = key < best[r * RUN + q] || (key == best[r * RUN + q] && idx < lab[r * RUN + q]);
+                    lab[r * RUN + q] = lt ? idx : lab[r * RUN + q];
+                    best[r * RUN + q] = fmin(best[r * RUN + q], key);
+                }
             }
         }
     }
 }
 
-template <int RUN>
-__device__ inline void store_run(const JobDev& J, int mi, int mj, int mk, bool bad, int* lab)
+template <int RUN, int ROWS>
+__device__ inline void store_runs(const JobDev& J, int mi, int mj, int mk, bool bad, int* lab)
 {
-    if (mj >= J.n[1] || mk >= J.n[2] || mi >= J.n[0])
+    if (mk >= J.n[2] || mi >= J.n[0])
         return;
-    int32_t* out = J.labels + (int64_t)mi + (int64_t)J.n[0] * ((int64_t)mj + (int64_t)J.n[1] * mk);
-    if (bad) {
 #pragma unroll
-        for (int q = 0; q < RUN; ++q)
-            lab[q] = -1;
-    }
-    if (mi + RUN <= J.n[0] && ((uintptr_t)out & 15) == 0 && RUN % 4 == 0) {
+    for (int r = 0; r < ROWS; ++r) {
+        if (mj + r >= J.n[1])
+            break;
+        int32_t* out = J.labels + (int64_t)mi + (int64_t)J.n[0] * ((int64_t)(mj + r) + (int64_t)J.n[1] * mk);
+        int* l = lab + r * RUN;
+        if (bad) {
 #pragma unroll
-        for (int q = 0; q < RUN; q += 4)
-            *(int4*)(out + q) = make_int4(lab[q], lab[q + 1], lab[q + 2], lab[q + 3]);
-    } else {
+            for (int q = 0; q < RUN; ++q)
+                l[q] = -1;
+        }
+        if (mi + RUN <= J.n[0] && ((uintptr_t)out & 15) == 0 && RUN % 4 == 0) {
 #pragma unroll
-        for (int q = 0; q < RUN; ++q)
-            if (mi + q < J.n[0])
-                out[q] = lab[q];
+            for (int q = 0; q < RUN; q += 4)
+                *(int4*)(out + q) = make_int4(l[q], l[q + 1], l[q + 2], l[q + 3]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < RUN; ++q)
+                if (mi + q < J.n[0])
+                    out[q] = l[q];
+        }
     }
 }
 
@@ -558,11 +593,11 @@ __device__ inline void store_run(const JobDev& J, int mi, int mj, int mk, bool b
 // win somewhere in the tile and evaluates them in batches of at most CAP_F
 // (the first batch with a strict '<' in index order, later ones with the
 // lexicographic (key, index) order).  Used when a region's sites overflow LDS.
-template <int KIND, int DIM, int RUN, int LX, int LY, int LZ>
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int ROWS>
 __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0, FallbackLds& S, int lane,
-                              double* xr, double yv, double zv, double* best, int* lab)
+                              double* xr, const double* yv, double zv, double* best, int* lab)
 {
-    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
+    constexpr int TX = RUN * LX, TY = LY * ROWS, TZ = (DIM == 3) ? LZ : 1;
     const bool periodic = J.bc != 0;
     const int ve[3] = {min(v0[0] + TX, J.n[0]) - 1, min(v0[1] + TY, J.n[1]) - 1, min(v0[2] + TZ, J.n[2]) - 1};
     const TileBox B = make_box<DIM>(J, v0, ve);
@@ -686,6 +721,7 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
                 const int slot = nc + __popcll(km & lanes_below(lane));
                 S.cs[slot] = s;
                 S.cg[slot] = g;
+                S.cu[slot] = ub;
                 S.cb[slot] = make_double2(lb, ub);
                 S.cq[slot] = make_double2(dmn, dmx);
                 S.cm[slot] = make_int2(sid, flags);
@@ -703,11 +739,13 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
             const double thr = UB + C.M;
             double4 s = make_double4(0.0, 0.0, 0.0, 0.0), g = s;
             double2 q = make_double2(0.0, 0.0);
+            double u = 0.0;
             int2 m = make_int2(0, 0);
             bool keep = false;
             if (lane < nc) {
                 s = S.cs[lane];
                 g = S.cg[lane];
+                u = S.cu[lane];
                 q = S.cq[lane];
                 m = S.cm[lane];
                 keep = S.cb[lane].x <= thr;
@@ -718,13 +756,14 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
                 const int d = __popcll(km & lanes_below(lane));
                 S.cs[d] = s;
                 S.cg[d] = g;
+                S.cu[d] = u;
                 S.cq[d] = q;
                 S.cm[d] = m;
             }
             nc = __popcll(km);
             wave_sync();
-            nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, nc, lane, C, B);
-            evaluate<KIND, DIM, RUN>(S.cs, S.cm, nc, lex, J, C, periodic, xr, yv, zv, best, lab);
+            nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, S.cu, nc, lane, C, B);
+            evaluate<KIND, DIM, RUN, ROWS>(S.cs, S.cm, nc, lex, J, C, periodic, xr, yv, zv, best, lab);
             lex = true;
             nc = 0;
             wave_sync();
@@ -753,10 +792,10 @@ __device__ inline void region_coords(const JobDev& J, int64_t r, int& rx, int& r
     ry = (int)(q - (unsigned)rz * n1);
 }
 
-template <int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
+template <int DIM, int RUN, int LX, int LY, int LZ, int ROWS, int RX, int RY, int RZ>
 __device__ inline LaneGeo lane_geometry(const JobDev& J, int64_t r, int w, int lane)
 {
-    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
+    constexpr int TX = RUN * LX, TY = LY * ROWS, TZ = (DIM == 3) ? LZ : 1;
     int rx, ry, rz;
     region_coords(J, r, rx, ry, rz);
     LaneGeo G;
@@ -766,7 +805,7 @@ __device__ inline LaneGeo lane_geometry(const JobDev& J, int64_t r, int w, int l
     G.live = G.t0[0] < J.n[0] && G.t0[1] < J.n[1] && G.t0[2] < J.n[2];
     const int lx = lane % LX, ly = (lane / LX) % LY, lz = lane / (LX * LY);
     G.mi = G.t0[0] + lx * RUN;
-    G.mj = G.t0[1] + ly;
+    G.mj = G.t0[1] + ly * ROWS;
     G.mk = (DIM == 3) ? G.t0[2] + lz : 0;
     return G;
 }
@@ -774,10 +813,10 @@ __device__ inline LaneGeo lane_geometry(const JobDev& J, int64_t r, int w, int l
 // Region `r` of job J: NW tiles of shape T (tile w of the region is processed
 // by wavefront w), RX x RY x RZ tiles.  `unit` numbers the region in the
 // launch (job-local, or batch-wide) for the overflow list.
-template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int ROWS, int RX, int RY, int RZ>
 __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm, const int tid)
 {
-    constexpr int TX = RUN * LX, TY = LY, TZ = (DIM == 3) ? LZ : 1;
+    constexpr int TX = RUN * LX, TY = LY * ROWS, TZ = (DIM == 3) ? LZ : 1;
     static_assert(LX * LY * LZ == WAVE, "64 lanes per tile");
     static_assert(RX * RY * RZ == NW, "one tile per wavefront");
     const bool periodic = J.bc != 0;
@@ -790,7 +829,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
     const int re[3] = {min(r0[0] + TX * RX, J.n[0]) - 1, min(r0[1] + TY * RY, J.n[1]) - 1,
                        min(r0[2] + TZ * RZ, J.n[2]) - 1};
     const TileBox BR = make_box<DIM>(J, r0, re);
-    const LaneGeo G = lane_geometry<DIM, RUN, LX, LY, LZ, RX, RY, RZ>(J, r, w, lane);
+    const LaneGeo G = lane_geometry<DIM, RUN, LX, LY, LZ, ROWS, RX, RY, RZ>(J, r, w, lane);
     const int te[3] = {min(G.t0[0] + TX, J.n[0]) - 1, min(G.t0[1] + TY, J.n[1]) - 1,
                        min(G.t0[2] + TZ, J.n[2]) - 1};
     const TileBox BT = make_box<DIM>(J, G.t0, te);
@@ -799,12 +838,15 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
 #pragma unroll
     for (int q = 0; q < RUN; ++q)
         xr[q] = ((double)(G.mi + q) + 0.5) * J.h[0];
-    const double yv = ((double)G.mj + 0.5) * J.h[1];
-    const double zv = (DIM == 3) ? ((double)G.mk + 0.5) * J.h[2] : 0.0;
-    double best[RUN];
-    int lab[RUN];
+    double yv[ROWS];
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) {
+    for (int rr = 0; rr < ROWS; ++rr)
+        yv[rr] = ((double)(G.mj + rr) + 0.5) * J.h[1];
+    const double zv = (DIM == 3) ? ((double)G.mk + 0.5) * J.h[2] : 0.0;
+    double best[ROWS * RUN];
+    int lab[ROWS * RUN];
+#pragma unroll
+    for (int q = 0; q < ROWS * RUN; ++q) {
         best[q] = __builtin_inf();
         lab[q] = -1;
     }
@@ -983,14 +1025,15 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     S.cs[slot] = s;
                     S.cg[slot] = g;
                     S.cq[slot] = make_double2(dmn, dmx);
+                    S.cu[slot] = ub;
                     S.cm[slot] = make_int2(R.ri[e], flags);
                 }
                 nc += __popcll(km);
             }
             wave_sync();
             if (!tile_ovf) {
-                nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, nc, lane, C, BT);
-                evaluate<KIND, DIM, RUN>(S.cs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
+                nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, S.cu, nc, lane, C, BT);
+                evaluate<KIND, DIM, RUN, ROWS>(S.cs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
             }
         }
     }
@@ -1002,37 +1045,40 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 J.ovf_list[pos] = (int32_t)(unit * NW + w);
             }
         } else {
-            store_run<RUN>(J, G.mi, G.mj, G.mk, bad, lab);
+            store_runs<RUN, ROWS>(J, G.mi, G.mj, G.mk, bad, lab);
         }
     }
 }
 
 // One tile of the overflow list, alone (fallback path, one wavefront).
-template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int RX, int RY, int RZ>
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int ROWS, int RX, int RY, int RZ>
 __device__ void label_tile_alone(const JobDev& J, int64_t r, int w, FallbackLds& S, int lane)
 {
-    const LaneGeo G = lane_geometry<DIM, RUN, LX, LY, LZ, RX, RY, RZ>(J, r, w, lane);
+    const LaneGeo G = lane_geometry<DIM, RUN, LX, LY, LZ, ROWS, RX, RY, RZ>(J, r, w, lane);
     if (!G.live)
         return;
     double xr[RUN];
 #pragma unroll
     for (int q = 0; q < RUN; ++q)
         xr[q] = ((double)(G.mi + q) + 0.5) * J.h[0];
-    const double yv = ((double)G.mj + 0.5) * J.h[1];
-    const double zv = (DIM == 3) ? ((double)G.mk + 0.5) * J.h[2] : 0.0;
-    double best[RUN];
-    int lab[RUN];
+    double yv[ROWS];
 #pragma unroll
-    for (int q = 0; q < RUN; ++q) {
+    for (int rr = 0; rr < ROWS; ++rr)
+        yv[rr] = ((double)(G.mj + rr) + 0.5) * J.h[1];
+    const double zv = (DIM == 3) ? ((double)G.mk + 0.5) * J.h[2] : 0.0;
+    double best[ROWS * RUN];
+    int lab[ROWS * RUN];
+#pragma unroll
+    for (int q = 0; q < ROWS * RUN; ++q) {
         best[q] = __builtin_inf();
         lab[q] = -1;
     }
     const bool bad = *(volatile int32_t*)J.status != 0;
     if (!bad) {
         const JobConst C = job_const<KIND>(J, DIM);
-        fallback_tile<KIND, DIM, RUN, LX, LY, LZ>(J, C, G.t0, S, lane, xr, yv, zv, best, lab);
+        fallback_tile<KIND, DIM, RUN, LX, LY, LZ, ROWS>(J, C, G.t0, S, lane, xr, yv, zv, best, lab);
     }
-    store_run<RUN>(J, G.mi, G.mj, G.mk, bad, lab);
+    store_runs<RUN, ROWS>(J, G.mi, G.mj, G.mk, bad, lab);
 }
 
 // Consecutive regions go to one XCD: workgroups are dispatched to the eight
@@ -1048,14 +1094,14 @@ template <int KIND, int DIM, int CFG>
 __device__ inline void region_cfg(const JobDev& J, int64_t r, int64_t unit, Smem& sm, int tid)
 {
     constexpr TileShape T = (DIM == 3) ? kShape3[CFG] : kShape2[CFG];
-    label_region<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rx, T.ry, T.rz>(J, r, unit, sm, tid);
+    label_region<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rows, T.rx, T.ry, T.rz>(J, r, unit, sm, tid);
 }
 
 template <int KIND, int DIM, int CFG>
 __device__ inline void alone_cfg(const JobDev& J, int64_t r, int w, FallbackLds& S, int lane)
 {
     constexpr TileShape T = (DIM == 3) ? kShape3[CFG] : kShape2[CFG];
-    label_tile_alone<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rx, T.ry, T.rz>(J, r, w, S, lane);
+    label_tile_alone<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rows, T.rx, T.ry, T.rz>(J, r, w, S, lane);
 }
 
 template <int KIND, int DIM, int CFG>
