@@ -6,7 +6,10 @@ the sites plus labelling of all 134,217,728 voxels, inputs already resident
 in HBM.  The line printed at the end also carries
   - roofline: the labelling kernel's algorithmic HBM write bytes (4 B per
     voxel) over its average duration, timed with HIP events recorded by the
-    library on the stream the kernel runs on, against 8 TB/s;
+    library on the stream the kernel runs on, against 8 TB/s, with the HBM
+    traffic and the FP64 / VALU issue rates measured by hardware counters
+    (committed counter summary, used only while it matches the kernel
+    source);
   - cpu_baseline: the CPU oracle (paper's two-step ball algorithm) timed on
     the host's cores on the same workload;
   - serving: a short request stream replayed through the continuous-batching
@@ -23,22 +26,99 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
+# second (a wavefront-64 instruction occupies a SIMD for four cycles).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+LABEL_KERNEL_SRC = os.path.join(ROOT, "paper_2201_13234_amd", "csrc", "label_kernel.hip")
 
 
-def traffic_from_profiles(nvox):
-    """HBM bytes per labelling launch from the committed counter summary, if
-    it was taken on the current kernel source."""
+def counters_path(workload):
+    return os.path.join(ROOT, "profiles", f"label_counters_{workload.split('_')[0].lower()}.json")
+
+
+def source_digest():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "label_traffic_m2.json")
-    src = os.path.join(ROOT, "paper_2201_13234_amd", "csrc", "label_kernel.hip")
+    return hashlib.sha256(open(LABEL_KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def load_counters(workload):
+    """Committed counter summary for this workload, if it was taken on the
+    current labelling kernel source (else None)."""
     try:
-        rec = json.load(open(path))
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if rec.get("label_kernel_sha256") != digest:
-            return None
-        return rec.get("hbm_bytes_per_launch")
+        rec = json.load(open(counters_path(workload)))
     except (OSError, ValueError):
         return None
+    if rec.get("label_kernel_sha256") != source_digest() or rec.get("workload") != workload:
+        return None
+    return rec
+
+
+def _pmc_rows(path):
+    """Per-kernel sums of each counter and the number of dispatches, from a
+    rocprofv3 counter_collection.csv."""
+    import csv
+    import collections
+    sums = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for r in csv.DictReader(open(path)):
+        k = r["Kernel_Name"]
+        sums[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp[k].add(r["Dispatch_Id"])
+    return sums, {k: len(v) for k, v in disp.items()}
+
+
+def _per_dispatch(path, counter, match):
+    sums, nd = _pmc_rows(path)
+    hits = [k for k in sums if match(k) and counter in sums[k]]
+    if not hits:
+        raise SystemExit(f"{path}: no kernel matching the probe has {counter}")
+    tot = sum(sums[k][counter] for k in hits)
+    n = sum(nd[k] for k in hits)
+    return tot / n, n, hits
+
+
+def summarize_counters(args):
+    """Turns three rocprofv3 --pmc runs of `bench.py --copy-probe-mib M`
+    (the probe is the run's only two-operand elementwise kernel)
+    (FETCH_SIZE, WRITE_SIZE, SQ instruction counters) into the committed
+    counter summary.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled
+    by what they read for the plain copy of known size in the same run."""
+    fetch_csv, write_csv, sq_csv = args.summarize
+    copy_bytes = args.copy_probe_mib * 2 ** 20
+    is_label = lambda k: "k_label_single" in k
+    is_copy = lambda k: "elementwise_kernel" in k and "array<char*, 2" in k
+    lf, n_lf, names = _per_dispatch(fetch_csv, "FETCH_SIZE", is_label)
+    cf, n_cf, cnames = _per_dispatch(fetch_csv, "FETCH_SIZE", is_copy)
+    lw, _, _ = _per_dispatch(write_csv, "WRITE_SIZE", is_label)
+    cw, _, _ = _per_dispatch(write_csv, "WRITE_SIZE", is_copy)
+    fetch_scale = copy_bytes / (cf * 1024.0)
+    write_scale = copy_bytes / (cw * 1024.0)
+    rec = {
+        "workload": args.workload_name,
+        "label_kernel_sha256": source_digest(),
+        "kernel": names[0],
+        "copy_probe": {"kernel": cnames[0], "bytes_read": copy_bytes, "bytes_written": copy_bytes,
+                       "fetch_kib": round(cf, 1), "write_kib": round(cw, 1),
+                       "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4)},
+        "label_fetch_kib": round(lf, 1),
+        "label_write_kib": round(lw, 1),
+        "hbm_read_bytes_per_launch": round(lf * 1024.0 * fetch_scale),
+        "hbm_write_bytes_per_launch": round(lw * 1024.0 * write_scale),
+        "dispatches": n_lf,
+        "commands": args.commands,
+    }
+    rec["hbm_bytes_per_launch"] = rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
+    if sq_csv != "-":
+        sums, nd = _pmc_rows(sq_csv)
+        ks = [k for k in sums if is_label(k)]
+        per = {c: sum(sums[k][c] for k in ks) / sum(nd[k] for k in ks)
+               for c in sums[ks[0]]}
+        rec["sq_per_launch"] = {c: round(v) for c, v in sorted(per.items())}
+    out = counters_path(args.workload_name)
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(w):
@@ -62,7 +142,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream replay")
     ap.add_argument("--serving-jobs", type=int, default=96)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this size three times (a plain "
+                         "copy kernel of known traffic, for scaling HBM counters)")
+    ap.add_argument("--summarize", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "SQ_CSV"),
+                    help="no GPU run: write the counter summary of --config from three rocprofv3 "
+                         "counter_collection.csv files (SQ_CSV may be '-')")
+    ap.add_argument("--commands", default="", help="with --summarize: the commands that made the CSVs")
     args = ap.parse_args()
+    if args.summarize:
+        from paper_2201_13234_amd import inputs
+        args.workload_name = inputs.CONFIGS[args.config]().name
+        if args.copy_probe_mib <= 0:
+            raise SystemExit("--summarize needs --copy-probe-mib (the size the runs copied)")
+        summarize_counters(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the labelling path "
               "has no multi-GPU part; see DESIGN.md for how it would shard.", file=sys.stderr)
@@ -94,15 +188,48 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ctx.profile_enable(False)
-    bin_ms, label_ms, calls = ctx.profile_read()
+    bin_ms, label_ms, ovf_ms, calls = ctx.profile_read()
     print(f"[bench] {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib * 2 ** 20
+        # int32 -> float32 conversion: one elementwise kernel per call that
+        # reads and writes nb bytes (a same-type copy_ would go to the
+        # runtime's blit kernels, mixed with other transfers).
+        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ms_per_step = elapsed * 1e3 / args.steps
     gvox = w.nvox * args.steps / elapsed / 1e9
     label_avg_ms = label_ms / max(calls, 1)
     bin_avg_ms = bin_ms / max(calls, 1)
+    ovf_avg_ms = ovf_ms / max(calls, 1)
     write_bytes = 4.0 * w.nvox
     achieved = write_bytes / (label_avg_ms * 1e-3) / 1e9
+    cnt = load_counters(w.name)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
+                "kernel": "k_label_single (main labelling kernel)",
+                "kernel_avg_ms": round(label_avg_ms, 4),
+                "algorithmic_bytes": write_bytes}
+    if cnt and "sq_per_launch" in cnt:
+        sq = cnt["sq_per_launch"]
+        sec = label_avg_ms * 1e-3
+        if "SQ_INSTS_VALU_FLOPS_FP64" in sq:
+            # the counter sums FP64 operations per wavefront instruction (FMA = 2);
+            # times 64 lanes (an upper bound: it assumes full execution masks)
+            f64 = sq["SQ_INSTS_VALU_FLOPS_FP64"] * 64 / sec / 1e12
+            roofline["fp64"] = {"achieved": round(f64, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": round(f64 / FP64_PEAK_TFLOPS, 4)}
+        if "SQ_INSTS_VALU" in sq:
+            v = sq["SQ_INSTS_VALU"] * 64 / sec / 1e12
+            roofline["valu_issue"] = {"achieved": round(v, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                                      "unit": "Tlane-op/s", "frac": round(v / VALU_PEAK_TOPS, 4)}
     out = {
         "metric": "Gvoxels/s at 3D 512^3/100k sites; batched p50/p99 latency vs one-by-one",
         "value": round(gvox, 3),
@@ -118,13 +245,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.n), "sites": w.nsites,
                    "kind": inputs.KIND_NAMES[w.kind], "periodic": w.periodic,
-                   "seed": w.meta.get("seed"), "path": "plain (vt_tessellate)"},
-        "phases_ms": {"binning": round(bin_avg_ms, 4), "labelling": round(label_avg_ms, 4)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_from_profiles(w.nvox),
-                     "kernel": "k_label_single (labelling)",
-                     "algorithmic_bytes": write_bytes},
+                   "seed": w.meta.get("seed"), "path": "plain (vt_tessellate)",
+                   "plan": ctx.plan(job)},
+        "phases_ms": {"binning": round(bin_avg_ms, 4), "labelling": round(label_avg_ms, 4),
+                      "overflow": round(ovf_avg_ms, 4)},
+        "roofline": roofline,
     }
     # correctness of the timed configuration: sampled voxels against the oracle
     import oracle

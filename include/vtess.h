@@ -131,12 +131,15 @@ vt_status vt_numerics_probe(vt_ctx* ctx, const double* x, const double* den, dou
                             double* div_out, int64_t n, void* stream);
 
 /* Phase timing of the plain path, for benchmarks.  While enabled, every
- * vt_tessellate call records three HIP events on its own stream: before the
- * binning kernels, before the labelling kernel and after it.  vt_profile_read
- * waits for the recorded events, returns the summed milliseconds of the two
- * phases and the number of calls recorded, and clears the record. */
+ * vt_tessellate call records four HIP events on its own stream: before the
+ * binning kernels, before the main labelling kernel, after it, and after the
+ * overflow kernel that labels the tiles the main kernel left over.
+ * vt_profile_read waits for the recorded events, returns the summed
+ * milliseconds of the three phases and the number of calls recorded, and
+ * clears the record.  Any output pointer may be NULL. */
 vt_status vt_profile_enable(vt_ctx* ctx, int32_t enable);
-vt_status vt_profile_read(vt_ctx* ctx, double* bin_ms, double* label_ms, int64_t* calls);
+vt_status vt_profile_read(vt_ctx* ctx, double* bin_ms, double* label_ms, double* overflow_ms,
+                          int64_t* calls);
 
 const char* vt_status_string(vt_status s);
 /* Detail text of the last error of the calling thread. */

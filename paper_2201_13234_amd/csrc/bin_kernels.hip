@@ -57,50 +57,74 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDe
                                                       int njobs, const int64_t* __restrict__ prefix,
                                                       int64_t total)
 {
-    int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (g >= total)
-        return;
+    const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const bool live = g < total;
     int j = 0;
     int64_t i = g;
-    if (jobs) {
+    if (jobs && live) {
         j = find_segment(prefix, njobs, g);
         i = g - prefix[j];
     }
-    const JobDev& J = jobs ? jobs[j] : single;
-    const int nd = J.ndim;
-    bool ok = true;
-    int b[3] = {0, 0, 0};
-    for (int a = 0; a < 3; ++a) {
-        if (a < nd) {
-            double c = J.coords[i * nd + a];
-            if (!(c >= 0.0 && c < J.L[a])) {
-                ok = false;
-            } else {
-                int v = (int)(c * J.inv_bs[a]);  // c >= 0: truncation is floor
-                b[a] = v < 0 ? 0 : (v >= J.nb[a] ? J.nb[a] - 1 : v);
+    unsigned long long hi = 0ull, lo = 0ull;  // ordered bits of param and -param, 0 = none
+    bool weighted = false;
+    if (live) {
+        const JobDev& J = jobs ? jobs[j] : single;
+        const int nd = J.ndim;
+        weighted = J.kind != KIND_VORONOI;
+        bool ok = true;
+        int b[3] = {0, 0, 0};
+        for (int a = 0; a < 3; ++a) {
+            if (a < nd) {
+                double c = J.coords[i * nd + a];
+                if (!(c >= 0.0 && c < J.L[a])) {
+                    ok = false;
+                } else {
+                    int v = (int)(c * J.inv_bs[a]);  // c >= 0: truncation is floor
+                    b[a] = v < 0 ? 0 : (v >= J.nb[a] ? J.nb[a] - 1 : v);
+                }
             }
         }
+        double p = 0.0;
+        if (weighted) {
+            p = J.param[i];
+            if (!isfinite(p))
+                ok = false;
+        }
+        if (!ok) {
+            b[0] = b[1] = b[2] = 0;
+            atomicOr(J.status, ST_INPUT);
+        }
+        int lin = b[0] + J.nb[0] * (b[1] + J.nb[1] * b[2]);
+        int rank = atomicAdd(&J.bin_count[lin], 1);
+        J.site_bin[i] = lin;
+        J.site_rank[i] = rank;
+        if (weighted && ok) {
+            hi = ordered_bits(p);
+            lo = ordered_bits(-p);
+        }
     }
-    double p = 0.0;
-    if (J.kind != KIND_VORONOI) {
-        p = J.param[i];
-        if (!isfinite(p))
-            ok = false;
+    // Parameter bounds: when every live lane of the wavefront belongs to one
+    // job, reduce over the wavefront (all lanes take part, dead lanes carry 0)
+    // and let the first live lane issue the atomics; otherwise one atomic per
+    // site.
+    const int j0 = __shfl(j, 0);
+    if (__all(!live || j == j0)) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
+            hi = h2 > hi ? h2 : hi;
+            lo = l2 > lo ? l2 : lo;
+        }
+        const unsigned long long lv = __ballot(live);
+        if (!live || __lane_id() != (unsigned)(__ffsll(lv) - 1))
+            return;
+    } else if (!live) {
+        return;
     }
-    if (!ok) {
-        b[0] = b[1] = b[2] = 0;
-        atomicOr(J.status, ST_INPUT);
-    }
-    int lin = b[0] + J.nb[0] * (b[1] + J.nb[1] * b[2]);
-    int rank = atomicAdd(&J.bin_count[lin], 1);
-    J.site_bin[i] = lin;
-    J.site_rank[i] = rank;
-    if (ok && J.kind != KIND_VORONOI) {
-        unsigned long long hi = ordered_bits(p), lo = ordered_bits(-p);
-        // The racy pre-read only skips atomics that cannot change the value.
-        if (hi > J.pbound[0])
+    if (weighted) {
+        const JobDev& J = jobs ? jobs[j] : single;
+        if (hi)
             atomicMax(&J.pbound[0], hi);
-        if (lo > J.pbound[1])
+        if (lo)
             atomicMax(&J.pbound[1], lo);
     }
 }

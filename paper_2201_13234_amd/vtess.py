@@ -67,7 +67,7 @@ def lib():
         L.vt_plan.argtypes = [vp, P(VtJob), P(i32), P(i32), P(dbl)]
         L.vt_numerics_probe.argtypes = [vp, vp, vp, vp, vp, i64, vp]
         L.vt_profile_enable.argtypes = [vp, i32]
-        L.vt_profile_read.argtypes = [vp, P(dbl), P(dbl), P(i64)]
+        L.vt_profile_read.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(i64)]
         L.vt_status_string.argtypes = [ctypes.c_int]
         L.vt_status_string.restype = ctypes.c_char_p
         L.vt_last_error.restype = ctypes.c_char_p
@@ -229,11 +229,12 @@ class Context:
         _check(lib().vt_profile_enable(self.handle, 1 if enable else 0), "vt_profile_enable")
 
     def profile_read(self):
-        """(binning ms, labelling ms, calls) summed over the recorded calls."""
-        b, l, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        _check(lib().vt_profile_read(self.handle, ctypes.byref(b), ctypes.byref(l), ctypes.byref(n)),
-               "vt_profile_read")
-        return b.value, l.value, n.value
+        """(binning ms, main labelling kernel ms, overflow kernel ms, calls)
+        summed over the recorded calls."""
+        b, l, o, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().vt_profile_read(self.handle, ctypes.byref(b), ctypes.byref(l), ctypes.byref(o),
+                                     ctypes.byref(n)), "vt_profile_read")
+        return b.value, l.value, o.value, n.value
 
     def numerics_probe(self, x, den, stream=None):
         """Device sqrt(x) and x / den (binary64), for checking IEEE rounding."""
