@@ -38,7 +38,7 @@ namespace {
 
 constexpr int NW = 4;          // wavefronts per workgroup = tiles per region
 constexpr int NT = NW * WAVE;  // threads per workgroup
-constexpr int CAP_R = 384;     // region candidate capacity (LDS)
+constexpr int CAP_R = 576;     // region candidate capacity (LDS)
 constexpr int CAP_S = 64;      // tile candidate capacity (LDS, per wavefront)
 constexpr int CAP_F = 64;      // fallback per-tile capacity (LDS, per wavefront)
 constexpr int R_DOM = 8;       // dominance references: the candidates with the smallest upper bounds
@@ -49,17 +49,22 @@ constexpr int FL_GENERIC = 64;
 
 enum { KV = 0, KL = 1, KJM = 2, KJD = 3 };  // Johnson-Mehl: multiply by exact 1/v, or divide
 
+// A tile list entry refers to its site record in the region list through the
+// position stored above the flags (cm.y >> 8).
 struct TileLds {
-    double4 cs[CAP_S];  // site {x, y, z, param}
     double4 cg[CAP_S];  // minimum image {x, y, z} over the tile and e = |image|^2 (- w for Laguerre)
     double2 cq[CAP_S];  // {min, max} distance to the tile box
-    double cu[CAP_S];   // upper bound of the key over the tile box
     int2 cm[CAP_S];     // {site index, flags}
+    union {
+        int ci[CAP_S];      // region-list positions that passed the lower-bound test, then
+        unsigned ck[CAP_S]; // 32-bit ranking keys (upper bound, then site index)
+    };
 };
 
 struct RegionLds {
     double4 rs[CAP_R];
     int ri[CAP_R];
+    int rf[CAP_R];  // wrap code per axis of the site's image in the gather box (2 bits per axis)
     int wsum[NW];
     double wred[NW];
 };
@@ -69,8 +74,8 @@ struct FallbackLds {
     double4 cg[CAP_F];
     double2 cb[CAP_F];  // {lower, upper} bound of the key over the tile box
     double2 cq[CAP_F];
-    double cu[CAP_F];
     int2 cm[CAP_F];
+    unsigned ck[CAP_F];
     int bcnt[WAVE];
     int bsrc[WAVE];
 };
@@ -319,31 +324,137 @@ __device__ inline void box_bounds(const JobDev& J, const JobConst& C, const Tile
     g = make_double4(sg3[0], sg3[1], sg3[2], e);
 }
 
-// Upper bound only (cheaper: no flags, no lower bound).
-template <int KIND, int DIM>
-__device__ inline double box_upper(const JobDev& J, const JobConst& C, const TileBox& B, bool periodic,
-                                   const double4& s)
+// Coordinates of a site's image given its wrap codes (2 bits per axis).
+// `wrapped` is false when no bin of the gather box lies outside the grid: the
+// codes are then all zero and the image is the site itself.
+template <int DIM>
+__device__ inline void site_image(const JobDev& J, const double4& s, int code, bool wrapped, double* sg)
 {
     const double sc[3] = {s.x, s.y, s.z};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        sg[a] = sc[a];
+    if (wrapped) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int c = (code >> (2 * a)) & 3;
+            sg[a] = sc[a] + (double)((c >> 1) - (c & 1)) * J.L[a];
+        }
+    }
+}
+
+// Upper bound of the key over box B through a given image of the site.  Any
+// image bounds the minimum-image distance from above, so this is valid for
+// every gather box.
+template <int KIND, int DIM>
+__device__ inline double image_upper(const JobConst& C, const TileBox& B, const double* sg, double p)
+{
     double qmax = 0.0;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double dmax;
-        if (periodic) {
-            const int c1 = wrap_code(sc[a] - B.lo[a], J.H[a]);
-            const int c2 = wrap_code(sc[a] - B.hi[a], J.H[a]);
-            const double sg = sc[a] + code_off(c1, J.L[a]);
-            dmax = c1 == c2 ? fmax(fabs(sg - B.lo[a]), fabs(sg - B.hi[a])) : J.H[a];
-        } else {
-            dmax = fmax(fabs(sc[a] - B.lo[a]), fabs(sc[a] - B.hi[a]));
-        }
+        const double dmax = fmax(fabs(sg[a] - B.lo[a]), fabs(sg[a] - B.hi[a]));
         qmax += dmax * dmax;
     }
     if (KIND == KV)
         return qmax;
     if (KIND == KL)
-        return qmax - s.w;
-    return s.w + sqrt(qmax) * C.rv;
+        return qmax - p;
+    return p + sqrt(qmax) * C.rv;
+}
+
+// Lower bound of the key over box B through the site's minimum image sg.
+template <int KIND, int DIM>
+__device__ inline double image_lower(const JobConst& C, const TileBox& B, const double* sg, double p)
+{
+    double qmin = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double dmin = fmax(0.0, fmax(B.lo[a] - sg[a], sg[a] - B.hi[a]));
+        qmin += dmin * dmin;
+    }
+    if (KIND == KV)
+        return qmin;
+    if (KIND == KL)
+        return qmin - p;
+    return p + sqrt(qmin) * C.rv;
+}
+
+// image_lower that also returns the minimum distance to the box (Johnson-Mehl
+// only; 0 otherwise).
+template <int KIND, int DIM>
+__device__ inline double image_lower_d(const JobConst& C, const TileBox& B, const double* sg, double p, double& dmin)
+{
+    double qmin = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double d = fmax(0.0, fmax(B.lo[a] - sg[a], sg[a] - B.hi[a]));
+        qmin += d * d;
+    }
+    dmin = 0.0;
+    if (KIND == KV)
+        return qmin;
+    if (KIND == KL)
+        return qmin - p;
+    dmin = sqrt(qmin);
+    return p + dmin * C.rv;
+}
+
+// True if site c (minimum image sg, parameter p, minimum distance dminc to
+// the box) loses to the reference site b on the whole box by more than the
+// margin.  Voronoi / Laguerre: key_c - key_b = (e_c - e_b) + 2 x.(g_b - g_c)
+// is linear in x, so its minimum over the box is at a corner (e = |g|^2, and
+// - w for Laguerre).  Johnson-Mehl: key_c - key_b >= (t_c - t_b) +
+// (min distance of c - max distance of b) / v.
+template <int KIND, int DIM>
+__device__ inline bool beaten_by(const JobConst& C, const TileBox& B, const double* sg, double p, double dminc,
+                                 const double* gb, double eb, double tb, double dbmax)
+{
+    if (KIND == KV || KIND == KL) {
+        double ec = 0.0, lin = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            ec += sg[a] * sg[a];
+            const double al = gb[a] - sg[a];
+            lin += fmin(al * B.lo[a], al * B.hi[a]);
+        }
+        if (KIND == KL)
+            ec -= p;
+        return (ec - eb) + 2.0 * lin > C.M;
+    }
+    return (p - tb) + (dminc - dbmax) * C.rv > C.M;
+}
+
+// Every bound of the tile list entry through the site's minimum image sg
+// (same outputs as box_bounds for a site whose wrap codes are uniform).
+template <int KIND, int DIM>
+__device__ inline void image_bounds(const JobConst& C, const TileBox& B, const double* sg, double p, double& lb,
+                                    double& ub, double& dmn, double& dmx, double4& g)
+{
+    double qmin = 0.0, qmax = 0.0, e = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double dmin = fmax(0.0, fmax(B.lo[a] - sg[a], sg[a] - B.hi[a]));
+        const double dmax = fmax(fabs(sg[a] - B.lo[a]), fabs(sg[a] - B.hi[a]));
+        e += sg[a] * sg[a];
+        qmin += dmin * dmin;
+        qmax += dmax * dmax;
+    }
+    if (KIND == KV) {
+        lb = qmin;
+        ub = qmax;
+        dmn = dmx = 0.0;
+    } else if (KIND == KL) {
+        lb = qmin - p;
+        ub = qmax - p;
+        e -= p;
+        dmn = dmx = 0.0;
+    } else {
+        dmn = sqrt(qmin);
+        dmx = sqrt(qmax);
+        lb = p + dmn * C.rv;
+        ub = p + dmx * C.rv;
+    }
+    g = make_double4(sg[0], DIM > 1 ? sg[1] : 0.0, DIM > 2 ? sg[2] : 0.0, e);
 }
 
 // Distance a face of the visited bin box must keep from the box of voxel
@@ -369,20 +480,48 @@ __device__ inline double outside_lower_bound(const JobConst& C, double G)
     return C.pmin + G * C.rv;
 }
 
+template <typename T>
+__device__ inline T sel3(int a, T v0, T v1, T v2)
+{
+    return a == 0 ? v0 : (a == 1 ? v1 : v2);
+}
+
+// Gap between voxel-centre coordinate c (the low / high end of a box) and the
+// low face of bin blo / the high face of bin bhi on an axis of length La with
+// bins of side bsa (+inf where no site can lie beyond the face).
+__device__ inline double face_gap_low(double c, int blo, double bsa, double La, bool periodic)
+{
+    if (!periodic && blo <= 0)
+        return __builtin_inf();
+    return c - ((double)blo * bsa + La * 0x1p-30);
+}
+
+__device__ inline double face_gap_high(double c, int bhi, int nb, double bsa, double La, bool periodic)
+{
+    if (!periodic && bhi >= nb - 1)
+        return __builtin_inf();
+    return ((double)(bhi + 1) * bsa - La * 0x1p-30) - c;
+}
+
 // Gap between the box of voxel centres and the low / high face of the bin
 // box [blo, bhi] along axis a (+inf where no site can lie beyond the face).
 __device__ inline double gap_low(const JobDev& J, const TileBox& B, int a, int blo, bool periodic)
 {
-    if (!periodic && blo <= 0)
-        return __builtin_inf();
-    return B.lo[a] - ((double)blo * J.bs[a] + J.L[a] * 0x1p-30);
+    return face_gap_low(B.lo[a], blo, J.bs[a], J.L[a], periodic);
 }
 
 __device__ inline double gap_high(const JobDev& J, const TileBox& B, int a, int bhi, bool periodic)
 {
-    if (!periodic && bhi >= J.nb[a] - 1)
-        return __builtin_inf();
-    return ((double)(bhi + 1) * J.bs[a] - J.L[a] * 0x1p-30) - B.hi[a];
+    return face_gap_high(B.hi[a], bhi, J.nb[a], J.bs[a], J.L[a], periodic);
+}
+
+// Where the site records of a list live: in the list itself (IND false,
+// entry k at base[k]) or in the region list (IND true, entry k at
+// base[cm[k].y >> 8]).
+template <bool IND>
+__device__ inline double4 site_at(const double4* base, int k, int flags)
+{
+    return IND ? base[flags >> 8] : base[k];
 }
 
 // True if the listed site e loses to some other listed site on the whole box.
@@ -390,12 +529,12 @@ __device__ inline double gap_high(const JobDev& J, const TileBox& B, int a, int 
 // linear in x, so its minimum over the box is at a corner.  Johnson-Mehl:
 // t_c + d_c/v - (t_t + d_t/v) >= (t_c - t_t) + lbd / v with lbd a lower bound
 // of d_c - d_t over the box, from d_c - d_t = (q_c - q_t) / (d_c + d_t).
-template <int KIND, int DIM>
-__device__ inline bool dominated(const double4* cs, const double4* cg, const int2* cm, const double2* cq, int e,
+template <int KIND, int DIM, bool IND>
+__device__ inline bool dominated(const double4* base, const double4* cg, const int2* cm, const double2* cq, int e,
                                  unsigned long long refs, const JobConst& C, const TileBox& B)
 {
     const double4 gc = cg[e];
-    const double tc = cs[e].w;
+    const double tc = KIND == KJM || KIND == KJD ? site_at<IND>(base, e, cm[e].y).w : 0.0;
     const double2 mq = cq[e];
     const bool cgen = (cm[e].y & FL_GENERIC) != 0;
     const double gcv[3] = {gc.x, gc.y, gc.z};
@@ -426,10 +565,20 @@ __device__ inline bool dominated(const double4* cs, const double4* cg, const int
                 if (den >= C.sqrtL2 * 0x1p-10)
                     lbd = fmax(lbd, Dq / den);
             }
-            dom = dom || (t != e && ((tc - cs[t].w) + lbd * C.rv) > C.M);
+            dom = dom || (t != e && ((tc - site_at<IND>(base, t, cm[t].y).w) + lbd * C.rv) > C.M);
         }
     }
     return dom;
+}
+
+// 32-bit ranking key of an upper bound: the high word of the order-preserving
+// integer image of the double, with the list position in the low 6 bits
+// (distinct keys; close upper bounds may rank in either order, which only
+// changes the choice of dominance references).
+__device__ inline unsigned ub_key(double u, int pos)
+{
+    const unsigned hw = (unsigned)((unsigned long long)__double_as_longlong(u) >> 32);
+    return (((hw >> 31) ? ~hw : (hw | 0x80000000u)) & ~63u) | (unsigned)pos;
 }
 
 // Drops dominated entries of a wavefront's list (one entry per lane, nc <= 64),
@@ -437,41 +586,53 @@ __device__ inline bool dominated(const double4* cs, const double4* cg, const int
 // entries with the smallest upper bounds (the sites nearest the tile, which
 // beat far sites on the whole tile); a dropped entry is always beaten by a
 // listed site, so the winner of every voxel stays.  Returns the new count.
-template <int KIND, int DIM>
-__device__ inline int prune_and_sort(double4* cs, double4* cg, int2* cm, double2* cq, const double* cu, int nc,
-                                     int lane, const JobConst& C, const TileBox& B)
+// IND false: the list holds the site records (cs, permuted with the list);
+// IND true: they stay in the region list `base` (cs unused).
+template <int KIND, int DIM, bool IND>
+__device__ inline int prune_and_sort(const double4* base, double4* cs, double4* cg, int2* cm, double2* cq,
+                                     unsigned* ck, int nc, int lane, const JobConst& C, const TileBox& B)
 {
+    static_assert(CAP_S == WAVE && CAP_F == WAVE, "one list entry per lane");
     const bool mine = lane < nc;
     bool keep = mine;
     if (nc > 1) {
-        // rank of this entry by upper bound (ties by position)
-        const double u = mine ? cu[lane] : 0.0;
+        // Rank of this entry by upper bound through the keys of ub_key (the
+        // caller stored them for entries below nc).
+        if (!mine)
+            ck[lane] = 0xffffffffu;
+        wave_sync();
+        const unsigned key = mine ? ck[lane] : 0xffffffffu;
         int ru = 0;
-        for (int t = 0; t < nc; ++t) {
-            const double ut = cu[t];
-            ru += (ut < u || (ut == u && t < lane)) ? 1 : 0;
+        for (int t = 0; t < nc; t += 4) {
+            const uint4 k4 = *(const uint4*)(ck + t);
+            ru += (int)(k4.x < key) + (int)(k4.y < key) + (int)(k4.z < key) + (int)(k4.w < key);
         }
         const unsigned long long refs = __ballot(mine && ru < R_DOM);
-        keep = !dominated<KIND, DIM>(cs, cg, cm, cq, mine ? lane : 0, refs, C, B) && mine;
+        keep = !dominated<KIND, DIM, IND>(base, cg, cm, cq, mine ? lane : 0, refs, C, B) && mine;
     }
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
     int2 m = make_int2(0, 0);
     if (mine) {
-        s = cs[lane];
+        if (!IND)
+            s = cs[lane];
         m = cm[lane];
     }
-    const unsigned long long km = __ballot(keep);
-    const int n = __popcll(km);
+    const int n = __popcll(__ballot(keep));
+    // rank among the kept entries by site index (indices are distinct and
+    // below 2^31; dropped entries carry the largest key)
+    const unsigned idx = (unsigned)m.x;
     wave_sync();
-    // rank among the kept entries by site index (indices are distinct)
+    ck[lane] = keep ? idx : 0xffffffffu;
+    wave_sync();
     int rank = 0;
-    for (int t = 0; t < nc; ++t) {
-        const int it = cm[t].x;
-        rank += (((km >> t) & 1ull) != 0 && it < m.x) ? 1 : 0;
+    for (int t = 0; t < nc; t += 4) {
+        const uint4 k4 = *(const uint4*)(ck + t);
+        rank += (int)(k4.x < idx) + (int)(k4.y < idx) + (int)(k4.z < idx) + (int)(k4.w < idx);
     }
     wave_sync();
     if (keep) {
-        cs[rank] = s;
+        if (!IND)
+            cs[rank] = s;
         cm[rank] = m;
     }
     wave_sync();
@@ -481,17 +642,18 @@ __device__ inline int prune_and_sort(double4* cs, double4* cg, int2* cm, double2
 // Exact keys of the listed sites (ascending index) at the lane's ROWS runs of
 // RUN voxels (row r at y = yv[r]).  The x terms d0*d0 are shared by the rows;
 // the sum keeps the grouping d0*d0 + (d1*d1 + d2*d2).
-template <int KIND, int DIM, int RUN, int ROWS>
-__device__ inline void evaluate(const double4* cs, const int2* cm, int nc, bool lex, const JobDev& J,
+template <int KIND, int DIM, int RUN, int ROWS, bool IND>
+__device__ inline void evaluate(const double4* base, const int2* cm, int nc, bool lex, const JobDev& J,
                                 const JobConst& C, bool periodic, const double* xr, const double* yv, double zv,
                                 double* best, int* lab)
 {
     for (int k = 0; k < nc; ++k) {
-        const double4 s = cs[k];
         const int2 m = cm[k];
         // the list entry is the same for every lane: keep index and flags in
         // scalar registers so that the branches below are scalar
-        const int idx = __builtin_amdgcn_readfirstlane(m.x), fl = __builtin_amdgcn_readfirstlane(m.y);
+        const int idx = __builtin_amdgcn_readfirstlane(m.x), f = __builtin_amdgcn_readfirstlane(m.y);
+        const int fl = f & 0xff;
+        const double4 s = site_at<IND>(base, k, f);
         double c[ROWS];
         double dx2[RUN];
         if (fl == 0) {
@@ -721,7 +883,6 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
                 const int slot = nc + __popcll(km & lanes_below(lane));
                 S.cs[slot] = s;
                 S.cg[slot] = g;
-                S.cu[slot] = ub;
                 S.cb[slot] = make_double2(lb, ub);
                 S.cq[slot] = make_double2(dmn, dmx);
                 S.cm[slot] = make_int2(sid, flags);
@@ -745,10 +906,11 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
             if (lane < nc) {
                 s = S.cs[lane];
                 g = S.cg[lane];
-                u = S.cu[lane];
+                const double2 b = S.cb[lane];
+                u = b.y;
                 q = S.cq[lane];
                 m = S.cm[lane];
-                keep = S.cb[lane].x <= thr;
+                keep = b.x <= thr;
             }
             const unsigned long long km = __ballot(keep);
             wave_sync();
@@ -756,14 +918,14 @@ __device__ void fallback_tile(const JobDev& J, const JobConst& C, const int* v0,
                 const int d = __popcll(km & lanes_below(lane));
                 S.cs[d] = s;
                 S.cg[d] = g;
-                S.cu[d] = u;
+                S.ck[d] = ub_key(u, d);
                 S.cq[d] = q;
                 S.cm[d] = m;
             }
             nc = __popcll(km);
             wave_sync();
-            nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, S.cu, nc, lane, C, B);
-            evaluate<KIND, DIM, RUN, ROWS>(S.cs, S.cm, nc, lex, J, C, periodic, xr, yv, zv, best, lab);
+            nc = prune_and_sort<KIND, DIM, false>(S.cs, S.cs, S.cg, S.cm, S.cq, S.ck, nc, lane, C, B);
+            evaluate<KIND, DIM, RUN, ROWS, false>(S.cs, S.cm, nc, lex, J, C, periodic, xr, yv, zv, best, lab);
             lex = true;
             nc = 0;
             wave_sync();
@@ -885,6 +1047,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
         int nR = 0, nDone = 0;
         bool overflow = false;
         double ubT = __builtin_inf();  // this tile's upper bound (wave-uniform)
+        int ubPos = -1;                // region-list position of a site attaining it
         for (int round = 0;; ++round) {
             // load every bin of the box that is not in the previous box
             const int nbx = bhi[0] - blo[0] + 1, nby = bhi[1] - blo[1] + 1, nbz = bhi[2] - blo[2] + 1;
@@ -896,7 +1059,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             const float rnx = 1.0f / (float)nbx, rnxy = 1.0f / (float)(nbx * nby);
             for (int64_t base = 0; base < nbox; base += NT) {
                 const int64_t e = base + tid;
-                int cnt = 0, src = 0;
+                int cnt = 0, src = 0, code = 0;
                 if (e < nbox) {
                     int rxy, ex;
                     const int ez = divmod_small((int)e, nbx * nby, rnxy, rxy);
@@ -910,6 +1073,11 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                             wx = wrap_bin(wx, J.nb[0]);
                             wy = wrap_bin(wy, J.nb[1]);
                             wz = wrap_bin(wz, J.nb[2]);
+                            // image of the bin's sites: shifted by -L below the
+                            // grid (code 1), by +L above it (code 2)
+                            code = (bx < 0 ? 1 : (bx >= J.nb[0] ? 2 : 0)) |
+                                   ((by < 0 ? 1 : (by >= J.nb[1] ? 2 : 0)) << 2) |
+                                   ((bz < 0 ? 1 : (bz >= J.nb[2] ? 2 : 0)) << 4);
                         }
                         const int lin = wx + J.nb[0] * (wy + J.nb[1] * wz);
                         src = J.bin_start[lin];
@@ -925,6 +1093,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 for (int k = 0; k < cnt; ++k) {
                     R.rs[nR + off + k] = J.sites[src + k];
                     R.ri[nR + off + k] = J.sidx[src + k];
+                    R.rf[nR + off + k] = code;
                 }
                 nR += total;
             }
@@ -934,55 +1103,89 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             // Each tile's upper bound from the sites added in this round; the
             // region's stopping level is the largest of them (every voxel of
             // the region then has a winning key below it).
+            bool wrapped = false;
+            if (periodic)
+                for (int a = 0; a < DIM; ++a)
+                    wrapped = wrapped || blo[a] < 0 || bhi[a] >= J.nb[a];
             double ubm = __builtin_inf();
-            for (int e = nDone + lane; e < nR; e += WAVE)
-                ubm = fmin(ubm, box_upper<KIND, DIM>(J, C, BT, periodic, R.rs[e]));
-            ubT = fmin(ubT, wave_min(ubm));
+            int posm = -1;
+            for (int e = nDone + lane; e < nR; e += WAVE) {
+                const double4 sv = R.rs[e];
+                double sg[3];
+                site_image<DIM>(J, sv, R.rf[e], wrapped, sg);
+                const double u = image_upper<KIND, DIM>(C, BT, sg, sv.w);
+                posm = u < ubm ? e : posm;
+                ubm = fmin(ubm, u);
+            }
+            const double rmin = wave_min(ubm);
+            if (rmin < ubT) {
+                ubT = rmin;
+                ubPos = __builtin_amdgcn_readlane(posm, __ffsll((unsigned long long)__ballot(ubm == rmin)) - 1);
+            }
             nDone = nR;
             const double UB = block_max(G.live ? ubT : -__builtin_inf(), R.wred, tid);
             // move the faces that are too close
             const double reach = needed_reach<KIND>(C, UB);
             const double need = reach + reach * 0x1p-20 + 1e-300;
+            // One lane per face of the bin box (lane 2a: low face of axis a,
+            // lane 2a + 1: high face): move it out until the gap between the
+            // region's voxel centres and the face exceeds `need`.
+            int fnew = 0;
+            if (lane < 2 * DIM) {
+                const int a = lane >> 1;
+                const bool high = (lane & 1) != 0;
+                const int nb = sel3(a, J.nb[0], J.nb[1], J.nb[2]);
+                const double La = sel3(a, J.L[0], J.L[1], J.L[2]), bsa = sel3(a, J.bs[0], J.bs[1], J.bs[2]);
+                const double inv = sel3(a, J.inv_bs[0], J.inv_bs[1], J.inv_bs[2]);
+                const double blo_c = sel3(a, BR.lo[0], BR.lo[1], BR.lo[2]), bhi_c = sel3(a, BR.hi[0], BR.hi[1], BR.hi[2]);
+                const int lo0 = sel3(a, blo[0], blo[1], blo[2]), hi0 = sel3(a, bhi[0], bhi[1], bhi[2]);
+                int res = high ? hi0 : lo0;
+                if (!(periodic && hi0 - lo0 + 1 >= nb)) {
+                    if (periodic && need >= La) {
+                        res = high ? lo0 + nb - 1 : lo0;
+                    } else if (!high) {
+                        int lo = lo0;
+                        if (face_gap_low(blo_c, lo, bsa, La, periodic) <= need) {
+                            const int t = (int)fmax(floor((blo_c - need) * inv), -1.0 * nb - 1.0);
+                            lo = min(lo - 1, t);
+                            if (!periodic)
+                                lo = max(lo, 0);
+                            while (face_gap_low(blo_c, lo, bsa, La, periodic) <= need && (periodic || lo > 0))
+                                --lo;
+                        }
+                        res = lo;
+                    } else {
+                        int hi = hi0;
+                        if (face_gap_high(bhi_c, hi, nb, bsa, La, periodic) <= need) {
+                            const int t = (int)fmin(floor((bhi_c + need) * inv), 2.0 * nb + 1.0);
+                            hi = max(hi + 1, t);
+                            if (!periodic)
+                                hi = min(hi, nb - 1);
+                            while (face_gap_high(bhi_c, hi, nb, bsa, La, periodic) <= need &&
+                                   (periodic || hi < nb - 1))
+                                ++hi;
+                        }
+                        res = hi;
+                    }
+                }
+                fnew = res;
+            }
             bool moved = false;
             int nlo[3], nhi[3];
+#pragma unroll
             for (int a = 0; a < 3; ++a) {
                 nlo[a] = blo[a];
                 nhi[a] = bhi[a];
-            }
-            for (int a = 0; a < DIM; ++a) {
-                const int nb = J.nb[a];
-                if (periodic && bhi[a] - blo[a] + 1 >= nb)
-                    continue;
-                int lo = blo[a], hi = bhi[a];
-                if (periodic && need >= J.L[a]) {
-                    nlo[a] = blo[a];
-                    nhi[a] = blo[a] + nb - 1;
-                    moved = true;
-                    continue;
+                if (a < DIM) {
+                    int lo = __builtin_amdgcn_readlane(fnew, 2 * a), hi = __builtin_amdgcn_readlane(fnew, 2 * a + 1);
+                    if (periodic && hi - lo + 1 >= J.nb[a]) {
+                        lo = blo[a];
+                        hi = blo[a] + J.nb[a] - 1;
+                    }
+                    moved = moved || lo != blo[a] || hi != bhi[a];
+                    nlo[a] = lo;
+                    nhi[a] = hi;
                 }
-                if (gap_low(J, BR, a, lo, periodic) <= need) {
-                    int t = (int)fmax(floor((BR.lo[a] - need) * J.inv_bs[a]), -1.0 * nb - 1.0);
-                    lo = min(lo - 1, t);
-                    if (!periodic)
-                        lo = max(lo, 0);
-                    while (gap_low(J, BR, a, lo, periodic) <= need && (periodic || lo > 0))
-                        --lo;
-                }
-                if (gap_high(J, BR, a, hi, periodic) <= need) {
-                    int t = (int)fmin(floor((BR.hi[a] + need) * J.inv_bs[a]), 2.0 * nb + 1.0);
-                    hi = max(hi + 1, t);
-                    if (!periodic)
-                        hi = min(hi, nb - 1);
-                    while (gap_high(J, BR, a, hi, periodic) <= need && (periodic || hi < nb - 1))
-                        ++hi;
-                }
-                if (periodic && hi - lo + 1 >= nb) {
-                    lo = blo[a];
-                    hi = blo[a] + nb - 1;
-                }
-                moved = moved || lo != blo[a] || hi != bhi[a];
-                nlo[a] = lo;
-                nhi[a] = hi;
             }
             if (!moved)
                 break;
@@ -1000,40 +1203,112 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
         __syncthreads();
 
         // ======== 2-3. per tile: prune and evaluate (one wavefront)
+        // The images the gather assigned by bin are the minimum images for
+        // every voxel of the region when, on each periodic axis, the gather
+        // box stays within half a period of the region's voxels: the wrap
+        // decision d >= L/2 / d < -L/2 on d = s - x is then the same for all
+        // of them (the slack covers bin-edge rounding).
+        bool img_ok = true, wrapped = false;
+        if (periodic) {
+            for (int a = 0; a < DIM; ++a)
+                wrapped = wrapped || blo[a] < 0 || bhi[a] >= J.nb[a];
+            for (int a = 0; a < DIM; ++a) {
+                const double ext = fmax((double)(bhi[a] + 1) * J.bs[a] - BR.lo[a], BR.hi[a] - (double)blo[a] * J.bs[a]);
+                img_ok = img_ok && ext < J.H[a] - J.L[a] * 0x1p-30;
+            }
+        }
         tile_ovf = overflow;
         if (!overflow && G.live) {
             TileLds& S = sm.r.tile[w];
             const double thr = ubT + C.M;
             int nc = 0;
-            for (int ebase = 0; ebase < nR; ebase += WAVE) {
-                const int e = ebase + lane;
-                int flags = 0;
-                double lb = __builtin_inf(), ub, dmn = 0.0, dmx = 0.0;
-                double4 s = make_double4(0.0, 0.0, 0.0, 0.0), g = s;
-                if (e < nR) {
-                    s = R.rs[e];
-                    box_bounds<KIND, DIM>(J, C, BT, periodic, s, flags, lb, ub, dmn, dmx, g);
+            if (img_ok) {
+                // Lower-bound test over the whole region list, together with
+                // a dominance test against the site attaining the tile's
+                // upper bound (the site nearest the tile); then the full
+                // bounds of the survivors only.
+                double gb[3] = {0.0, 0.0, 0.0}, eb = 0.0, tb = 0.0, dbmax = 0.0;
+                if (ubPos >= 0) {
+                    const double4 sb = R.rs[ubPos];
+                    site_image<DIM>(J, sb, R.rf[ubPos], wrapped, gb);
+                    double qb = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        eb += gb[a] * gb[a];
+                        const double dmax = fmax(fabs(gb[a] - BT.lo[a]), fabs(gb[a] - BT.hi[a]));
+                        qb += dmax * dmax;
+                    }
+                    if (KIND == KL)
+                        eb -= sb.w;
+                    tb = sb.w;
+                    if (KIND == KJM || KIND == KJD)
+                        dbmax = sqrt(qb);
                 }
-                const bool keep = e < nR && lb <= thr;
-                const unsigned long long km = __ballot(keep);
-                if (nc + __popcll(km) > CAP_S) {
-                    tile_ovf = true;
-                    break;
+                for (int ebase = 0; ebase < nR; ebase += WAVE) {
+                    const int e = ebase + lane;
+                    bool keep = false;
+                    if (e < nR) {
+                        const double4 sv = R.rs[e];
+                        double sg[3];
+                        site_image<DIM>(J, sv, R.rf[e], wrapped, sg);
+                        double dminc;
+                        keep = image_lower_d<KIND, DIM>(C, BT, sg, sv.w, dminc) <= thr;
+                        if (keep && ubPos >= 0 && e != ubPos)
+                            keep = !beaten_by<KIND, DIM>(C, BT, sg, sv.w, dminc, gb, eb, tb, dbmax);
+                    }
+                    const unsigned long long km = __ballot(keep);
+                    if (nc + __popcll(km) > CAP_S) {
+                        tile_ovf = true;
+                        break;
+                    }
+                    if (keep)
+                        S.ci[nc + __popcll(km & lanes_below(lane))] = e;
+                    nc += __popcll(km);
                 }
-                if (keep) {
-                    const int slot = nc + __popcll(km & lanes_below(lane));
-                    S.cs[slot] = s;
-                    S.cg[slot] = g;
-                    S.cq[slot] = make_double2(dmn, dmx);
-                    S.cu[slot] = ub;
-                    S.cm[slot] = make_int2(R.ri[e], flags);
+                wave_sync();
+                if (!tile_ovf && lane < nc) {
+                    const int e = S.ci[lane];
+                    const double4 sv = R.rs[e];
+                    const int code = R.rf[e];
+                    double sg[3], lb, ub, dmn, dmx;
+                    double4 g;
+                    site_image<DIM>(J, sv, code, wrapped, sg);
+                    image_bounds<KIND, DIM>(C, BT, sg, sv.w, lb, ub, dmn, dmx, g);
+                    S.cg[lane] = g;
+                    S.cq[lane] = make_double2(dmn, dmx);
+                    S.ck[lane] = ub_key(ub, lane);  // replaces this lane's ci entry, read above
+                    S.cm[lane] = make_int2(R.ri[e], code | (e << 8));
                 }
-                nc += __popcll(km);
+            } else {
+                for (int ebase = 0; ebase < nR; ebase += WAVE) {
+                    const int e = ebase + lane;
+                    int flags = 0;
+                    double lb = __builtin_inf(), ub, dmn = 0.0, dmx = 0.0;
+                    double4 s = make_double4(0.0, 0.0, 0.0, 0.0), g = s;
+                    if (e < nR) {
+                        s = R.rs[e];
+                        box_bounds<KIND, DIM>(J, C, BT, periodic, s, flags, lb, ub, dmn, dmx, g);
+                    }
+                    const bool keep = e < nR && lb <= thr;
+                    const unsigned long long km = __ballot(keep);
+                    if (nc + __popcll(km) > CAP_S) {
+                        tile_ovf = true;
+                        break;
+                    }
+                    if (keep) {
+                        const int slot = nc + __popcll(km & lanes_below(lane));
+                        S.cg[slot] = g;
+                        S.cq[slot] = make_double2(dmn, dmx);
+                        S.ck[slot] = ub_key(ub, slot);
+                        S.cm[slot] = make_int2(R.ri[e], flags | (e << 8));
+                    }
+                    nc += __popcll(km);
+                }
             }
             wave_sync();
             if (!tile_ovf) {
-                nc = prune_and_sort<KIND, DIM>(S.cs, S.cg, S.cm, S.cq, S.cu, nc, lane, C, BT);
-                evaluate<KIND, DIM, RUN, ROWS>(S.cs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
+                nc = prune_and_sort<KIND, DIM, true>(R.rs, S.cg, S.cg, S.cm, S.cq, S.ck, nc, lane, C, BT);
+                evaluate<KIND, DIM, RUN, ROWS, true>(R.rs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
             }
         }
     }
@@ -1165,7 +1440,7 @@ __global__ __launch_bounds__(NT) void k_label_batch(const JobDev* __restrict__ j
             if (g >= re)
                 break;
             const int j = job_of_region(jobs, njobs, g);
-            const JobDev& J = jobs[j];
+            const JobDev J = jobs[j];  // by value: the job record is read once, not through a generic pointer
             const int64_t t = g - J.region_begin;
             if (J.ndim == 3) {
                 switch (variant_code(J)) {
