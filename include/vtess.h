@@ -74,15 +74,21 @@ vt_status vt_create(int device, vt_ctx** out);
 void vt_destroy(vt_ctx* ctx);
 
 /* Plain single-diagram path: bins the sites (counting sort into a uniform
- * bin grid) and labels every voxel.  status_dev (nullable): one device int32,
- * set to VT_OK or VT_ERR_INPUT by the kernels.  May grow the context's
- * scratch, which synchronises the device. */
+ * bin grid; for Johnson-Mehl also drops the sites that never win, as for
+ * vt_tessellate_batch) and labels every voxel.  status_dev (nullable): one
+ * device int32, set to VT_OK or VT_ERR_INPUT by the kernels.  May grow the
+ * context's scratch, which synchronises the device. */
 vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
 
 /* Many diagrams, of any sizes, kinds and boundaries: one segmented binning
- * pass and one persistent labelling launch over all of them.  status_dev
- * (nullable): njobs device int32, one per job.  A job with bad sites gets -1
- * labels and VT_ERR_INPUT without affecting the others. */
+ * pass over all of them, then one persistent labelling launch per group of
+ * jobs that share kind, dimension and tile configuration (each group runs a
+ * kernel compiled for it).  status_dev (nullable): njobs device int32, one
+ * per job, in the order of `jobs`.  A job with bad sites gets -1 labels and
+ * VT_ERR_INPUT without affecting the others.  Johnson-Mehl jobs first drop
+ * from their bins the sites that provably never win (a site s whose
+ * nucleation another site's grain reaches first: t_r + |s - r| / v < t_s by
+ * more than the rounding margin); labels are unchanged by it. */
 vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs,
                               int32_t* status_dev, void* stream);
 
@@ -93,8 +99,9 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs,
 vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out,
                         int32_t* status_dev, void* stream);
 
-/* Labels the jobs behind n resident bin objects in one persistent launch,
- * writing each into the labels buffer given at vt_bins_build.  status_dev
+/* Labels the jobs behind n resident bin objects (one persistent launch per
+ * group, as for vt_tessellate_batch), writing each into the labels buffer
+ * given at vt_bins_build.  status_dev
  * (nullable): n device int32 (VT_ERR_INPUT for jobs whose binning flagged bad
  * input, else VT_OK). */
 vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n,
@@ -129,6 +136,17 @@ vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3,
  * device memory of n doubles. */
 vt_status vt_numerics_probe(vt_ctx* ctx, const double* x, const double* den, double* sqrt_out,
                             double* div_out, int64_t n, void* stream);
+
+/* Order-sensitive checksum of a label image, for checking results without
+ * copying them to the host (serving, benchmarks).  Adds
+ *     sum over i < n of (labels[i] + 3) * ((i * 48271 + 97) mod P),
+ * taken mod P = 2^31 - 1 per workgroup, to *acc_dev (a device uint64 that the
+ * caller zeroes; fewer than 2^32 workgroups so the total does not wrap).  The
+ * checksum is *acc_dev mod P once the stream reaches this point.  labels is a
+ * device int32 array of n entries; nothing is allocated.  VT_ERR_INVALID for
+ * n < 0 or NULL pointers with n > 0. */
+vt_status vt_label_digest(vt_ctx* ctx, const int32_t* labels, int64_t n, unsigned long long* acc_dev,
+                          void* stream);
 
 /* Phase timing of the plain path, for benchmarks.  While enabled, every
  * vt_tessellate call records four HIP events on its own stream: before the

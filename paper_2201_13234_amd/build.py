@@ -15,11 +15,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvtess.so")
-SOURCES = ["bin_kernels.hip", "label_kernel.hip", "api.hip"]
+SOURCES = ["label_batch.hip", "label_kernel.hip", "bin_kernels.hip", "api.hip"]
 # The labelling kernel never sees a NaN (sites are checked by the binning
 # pass and a job with bad input is skipped), so min/max need no quieting;
 # infinities stay honoured.
-EXTRA = {"label_kernel.hip": ["-fno-honor-nans"]}
+EXTRA = {"label_kernel.hip": ["-fno-honor-nans"], "label_batch.hip": ["-fno-honor-nans"]}
 ARCH = os.environ.get("VT_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

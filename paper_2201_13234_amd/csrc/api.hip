@@ -113,20 +113,25 @@ const TuneEntry* find_tune(const vt_ctx* ctx, const vt_job* j, int64_t nvox)
 }
 
 // Tile configuration and bin size: forced, tuned, or default.  The defaults
-// are the fastest measured settings for 3D Poisson sites: a Voronoi diagram
-// gathers from slightly larger bins (fewer bin visits per region); a
-// Johnson-Mehl diagram, whose cells reach further, labels best with the
-// smaller 8x8x8 tiles.  Batched launches use configuration 0.
-void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, bool batch, int* cfg_out,
-                   double* bf_out)
+// are the fastest measured settings for 3D uniform random sites: Voronoi and
+// Laguerre diagrams gather from bins larger than the mean site spacing (fewer
+// bin visits per region; Laguerre cells vary more in size); a Johnson-Mehl
+// diagram, whose cells reach further, labels best with the smaller 8x8x8
+// tiles.  Batched launches group jobs by configuration, so the same choice
+// holds there.
+void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_out, double* bf_out)
 {
     int cfg = 0;
     double bf = 1.0;
     if (j->ndim == 3) {
-        if (j->kind == VT_VORONOI)
-            bf = 1.3;
-        else if (j->kind == VT_JOHNSON_MEHL)
+        if (j->kind == VT_VORONOI) {
+            bf = 1.4;
+        } else if (j->kind == VT_LAGUERRE) {
+            bf = 2.0;
+        } else {
             cfg = 1;
+            bf = 1.2;
+        }
     }
     if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
         cfg = t->cfg;
@@ -136,14 +141,14 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, bool batch,
         cfg = ctx->force_cfg;
     if (ctx->force_bin > 0.0)
         bf = ctx->force_bin;
-    if (batch || cfg < 0 || cfg > 2)
+    if (cfg < 0 || cfg > 2)
         cfg = 0;
     *cfg_out = cfg;
     *bf_out = bf;
 }
 
 // Checks the scalars of a job and fills the geometry of its device record.
-vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d, bool batch)
+vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
 {
     if (!j)
         return fail(VT_ERR_INVALID, "job is NULL");
@@ -196,7 +201,7 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d, bool batch)
 
     int cfg;
     double bf;
-    choose_params(ctx, j, nvox, batch, &cfg, &bf);
+    choose_params(ctx, j, nvox, &cfg, &bf);
     d->cfg = cfg;
 
     // Bins: side ~ bf times the mean site spacing (V / N)^(1/d), at most
@@ -348,6 +353,8 @@ vt_status bin_single(const JobDev& d, char* base, const SingleLayout& L, hipStre
     VT_HIP(vt::launch_bin_count(d, nullptr, 1, nullptr, d.nsites, s));
     VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (int32_t*)(base + L.partial), L.partial_cap, s));
     VT_HIP(vt::launch_bin_scatter(d, nullptr, 1, nullptr, d.nsites, s));
+    if (d.kind == vt::KIND_JM)
+        VT_HIP(vt::launch_jm_prune(d, nullptr, 1, nullptr, d.nsites, d.nbins, s));
     return VT_OK;
 }
 
@@ -360,11 +367,12 @@ __global__ void k_probe(const double* x, const double* den, double* so, double* 
     }
 }
 
-__global__ void k_copy_status(const JobDev* jobs, int n, int32_t* out)
+// out[order[k]] = status of table entry k.
+__global__ void k_copy_status(const JobDev* jobs, int n, const int32_t* order, int32_t* out)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n)
-        out[i] = *jobs[i].status;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n)
+        out[order[k]] = *jobs[k].status;
 }
 
 // Stream-ordered device allocation for per-call tables (freed by the caller
@@ -389,6 +397,60 @@ vt_status stage_copy(vt_ctx* ctx, void* dev, const void* host, size_t bytes, hip
     VT_HIP(hipMemcpyAsync(dev, ctx->pinned, bytes, hipMemcpyHostToDevice, s));
     VT_HIP(hipEventRecord(ctx->staging_evt, s));
     ctx->staging_used = true;
+    return VT_OK;
+}
+
+// One launch group of a batch: jobs of one kernel variant, dimension and tile
+// configuration, contiguous in the table.
+struct Group {
+    int first, count, variant, ndim, cfg;
+    int64_t regions, ovf_off;
+};
+
+// Orders a batch's jobs into launch groups (stable within a group), numbers
+// each group's regions from 0 (region_begin) and places its overflow list.
+// order[k] is the caller's index of table entry k; group_of[k] its group.
+void make_groups(std::vector<JobDev>& tab, std::vector<int>& order, std::vector<int>& group_of,
+                 std::vector<Group>& groups)
+{
+    const int n = (int)tab.size();
+    auto key = [](const JobDev& d) { return (d.ndim * 8 + vt::label_variant(d)) * 4 + d.cfg; };
+    order.resize(n);
+    for (int i = 0; i < n; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(tab[a]) < key(tab[b]); });
+    std::vector<JobDev> sorted((size_t)n);
+    for (int k = 0; k < n; ++k)
+        sorted[k] = tab[order[k]];
+    tab.swap(sorted);
+    groups.clear();
+    group_of.assign(n, 0);
+    int64_t ovf = 0;
+    for (int k = 0; k < n;) {
+        Group g{k, 0, vt::label_variant(tab[k]), tab[k].ndim, tab[k].cfg, 0, ovf};
+        int kk = k;
+        while (kk < n && key(tab[kk]) == key(tab[k])) {
+            tab[kk].region_begin = g.regions;
+            g.regions += tab[kk].nregions;
+            group_of[kk] = (int)groups.size();
+            ++kk;
+        }
+        g.count = kk - k;
+        ovf += g.regions * 4;
+        groups.push_back(g);
+        k = kk;
+    }
+}
+
+vt_status launch_groups(vt_ctx* ctx, const JobDev* djobs, const std::vector<Group>& groups, int32_t* counters,
+                        int32_t* ovf_counts, int32_t* ovf_list, hipStream_t s)
+{
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group& g = groups[gi];
+        VT_HIP(vt::launch_label_group(djobs + g.first, g.count, g.variant, g.ndim, g.cfg, g.regions,
+                                      counters + 8 * gi, ovf_list + g.ovf_off, ovf_counts + gi, ctx->batch_grid,
+                                      s));
+    }
     return VT_OK;
 }
 
@@ -469,7 +531,7 @@ vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3, int32
     if (!ctx)
         return fail(VT_ERR_INVALID, "ctx is NULL");
     JobDev d;
-    vt_status st = plan_job(ctx, job, &d, false);
+    vt_status st = plan_job(ctx, job, &d);
     if (st != VT_OK)
         return st;
     if (bins_per_axis3)
@@ -479,7 +541,7 @@ vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3, int32
         *tile_cfg = d.cfg;
     if (bin_factor) {
         int cfg;
-        choose_params(ctx, job, d.nvox, false, &cfg, bin_factor);
+        choose_params(ctx, job, d.nvox, &cfg, bin_factor);
     }
     return VT_OK;
 }
@@ -490,7 +552,7 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
         return fail(VT_ERR_INVALID, "ctx is NULL");
     hipStream_t s = (hipStream_t)stream;
     JobDev d;
-    vt_status st = plan_job(ctx, job, &d, false);
+    vt_status st = plan_job(ctx, job, &d);
     if (st != VT_OK)
         return st;
     VT_HIP(hipSetDevice(ctx->device));
@@ -565,29 +627,37 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
         return fail(VT_ERR_INVALID, "need at least one job");
     hipStream_t s = (hipStream_t)stream;
     std::vector<JobDev> host((size_t)njobs);
-    std::vector<int64_t> prefix((size_t)njobs + 1, 0);
-    int64_t total_bins = 0, total_tiles = 0;
     for (int i = 0; i < njobs; ++i) {
-        vt_status st = plan_job(ctx, &jobs[i], &host[i], true);
+        vt_status st = plan_job(ctx, &jobs[i], &host[i]);
         if (st != VT_OK)
             return fail(st, "job " + std::to_string(i) + ": " + g_last_error);
-        prefix[i + 1] = prefix[i] + host[i].nsites;
-        host[i].region_begin = total_tiles;
-        total_tiles += host[i].nregions;
-        total_bins += host[i].nbins;
+    }
+    std::vector<int> order, group_of;
+    std::vector<Group> groups;
+    make_groups(host, order, group_of, groups);
+    const int ng = (int)groups.size();
+    std::vector<int64_t> prefix((size_t)njobs + 1, 0);
+    int64_t total_bins = 0, total_tiles = 0;
+    for (int k = 0; k < njobs; ++k) {
+        prefix[k + 1] = prefix[k] + host[k].nsites;
+        host[k].site_begin = prefix[k];
+        host[k].bin_begin = total_bins;
+        total_tiles += host[k].nregions;
+        total_bins += host[k].nbins;
     }
     const int64_t total_sites = prefix[njobs];
     if (total_sites > 0x7fffffffLL || total_bins > 0x7ffffffeLL)
         return fail(VT_ERR_BUSY, "batch too large: more than 2^31 sites or bins");
     VT_HIP(hipSetDevice(ctx->device));
-    // Layout: [pbound 2/job][status 1/job][bin_count][counters 8] zeroed together,
-    // then bin_start, site arrays, scan partials.
+    // Layout: [pbound 2/job][status 1/job][bin_count][counters 8/group][overflow
+    // count 1/group] zeroed together, then bin_start, site arrays, scan
+    // partials, overflow lists.
     Carver c;
     const size_t o_pb = c.take<unsigned long long>(2 * (int64_t)njobs);
     const size_t o_st = c.take<int32_t>(njobs, 8);
     const size_t o_cnt = c.take<int32_t>(total_bins, 4);
-    const size_t o_ctr = c.take<int32_t>(8, 4);
-    const size_t o_ovfc = c.take<int32_t>(1, 4);
+    const size_t o_ctr = c.take<int32_t>(8 * (int64_t)ng, 4);
+    const size_t o_ovfc = c.take<int32_t>(ng, 4);
     const size_t zero_end = c.off;
     const size_t o_start = c.take<int32_t>(total_bins + 1);
     const size_t o_sbin = c.take<int32_t>(total_sites);
@@ -601,20 +671,19 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     if (st != VT_OK)
         return st;
     char* base = (char*)ctx->scratch;
-    int64_t bin_off = 0;
-    for (int i = 0; i < njobs; ++i) {
-        JobDev& d = host[i];
-        d.pbound = (unsigned long long*)(base + o_pb) + 2 * i;
-        d.status = status_dev ? status_dev + i : (int32_t*)(base + o_st) + i;
-        d.bin_count = (int32_t*)(base + o_cnt) + bin_off;
-        d.bin_start = (int32_t*)(base + o_start) + bin_off;  // values index the batch-wide site arrays
-        d.site_bin = (int32_t*)(base + o_sbin) + prefix[i];
-        d.site_rank = (int32_t*)(base + o_srank) + prefix[i];
+    for (int k = 0; k < njobs; ++k) {
+        JobDev& d = host[k];
+        const Group& g = groups[group_of[k]];
+        d.pbound = (unsigned long long*)(base + o_pb) + 2 * k;
+        d.status = status_dev ? status_dev + order[k] : (int32_t*)(base + o_st) + k;
+        d.bin_count = (int32_t*)(base + o_cnt) + d.bin_begin;
+        d.bin_start = (int32_t*)(base + o_start) + d.bin_begin;  // values index the batch-wide site arrays
+        d.site_bin = (int32_t*)(base + o_sbin) + prefix[k];
+        d.site_rank = (int32_t*)(base + o_srank) + prefix[k];
         d.sites = (double4*)(base + o_sites);
         d.sidx = (int32_t*)(base + o_sidx);
-        d.ovf_count = (int32_t*)(base + o_ovfc);
-        d.ovf_list = (int32_t*)(base + o_ovf);
-        bin_off += d.nbins;
+        d.ovf_count = (int32_t*)(base + o_ovfc) + group_of[k];
+        d.ovf_list = (int32_t*)(base + o_ovf) + g.ovf_off;
     }
     // job table and site prefix in one stream-ordered allocation
     const size_t jb = align_up(host.size() * sizeof(JobDev), 256);
@@ -637,8 +706,10 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     VT_HIP(vt::launch_scan((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins,
                            (int32_t*)(base + o_part), pcap, s));
     VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
-    VT_HIP(vt::launch_label_batch(djobs, njobs, total_tiles, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovf),
-                                  (int32_t*)(base + o_ovfc), ctx->batch_grid, s));
+    VT_HIP(vt::launch_jm_prune(dummy, djobs, njobs, dprefix, total_sites, total_bins, s));
+    if ((st = launch_groups(ctx, djobs, groups, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovfc),
+                            (int32_t*)(base + o_ovf), s)) != VT_OK)
+        return st;
     VT_HIP(hipFreeAsync(table, s));
     return VT_OK;
 }
@@ -650,7 +721,7 @@ vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out, int32_t* 
     *out = nullptr;
     hipStream_t s = (hipStream_t)stream;
     JobDev d;
-    vt_status st = plan_job(ctx, job, &d, true);
+    vt_status st = plan_job(ctx, job, &d);
     if (st != VT_OK)
         return st;
     VT_HIP(hipSetDevice(ctx->device));
@@ -679,37 +750,49 @@ vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n, int32_t* 
         return fail(VT_ERR_INVALID, "need a context and at least one bins object");
     hipStream_t s = (hipStream_t)stream;
     std::vector<JobDev> host((size_t)n);
-    int64_t total_tiles = 0;
     for (int i = 0; i < n; ++i) {
         if (!bins[i])
             return fail(VT_ERR_INVALID, "bins[" + std::to_string(i) + "] is NULL");
         host[i] = bins[i]->job;
-        host[i].region_begin = total_tiles;
-        total_tiles += host[i].nregions;
     }
+    std::vector<int> order, group_of;
+    std::vector<Group> groups;
+    make_groups(host, order, group_of, groups);
+    const int ng = (int)groups.size();
+    int64_t total_tiles = 0;
+    for (const JobDev& d : host)
+        total_tiles += d.nregions;
     VT_HIP(hipSetDevice(ctx->device));
-    // One stream-ordered allocation: job table, then eight region counters and
-    // the overflow count (zeroed on the device), then the overflow list.
+    // One stream-ordered allocation: job table, the caller's order, then eight
+    // region counters per group and one overflow count per group (zeroed on the
+    // device), then the overflow lists.
     const size_t jb = align_up((size_t)n * sizeof(JobDev), 256);
-    const size_t bytes = jb + 16 * sizeof(int32_t) + (size_t)total_tiles * 4 * sizeof(int32_t);
+    const size_t ob = align_up((size_t)n * sizeof(int32_t), 256);
+    const size_t cb = align_up((size_t)ng * 9 * sizeof(int32_t), 256);
+    const size_t bytes = jb + ob + cb + (size_t)total_tiles * 4 * sizeof(int32_t);
     void* table = nullptr;
     vt_status st = alloc_table(bytes, s, &table);
     if (st != VT_OK)
         return st;
-    int32_t* counters = (int32_t*)((char*)table + jb);
-    int32_t* ovf_count = counters + 8;
-    int32_t* ovf_list = counters + 16;
-    for (JobDev& d : host) {
-        d.ovf_count = ovf_count;
-        d.ovf_list = ovf_list;
+    int32_t* dorder = (int32_t*)((char*)table + jb);
+    int32_t* counters = (int32_t*)((char*)table + jb + ob);
+    int32_t* ovf_counts = counters + 8 * ng;
+    int32_t* ovf_list = (int32_t*)((char*)table + jb + ob + cb);
+    for (int k = 0; k < n; ++k) {
+        host[k].ovf_count = ovf_counts + group_of[k];
+        host[k].ovf_list = ovf_list + groups[group_of[k]].ovf_off;
     }
-    if ((st = stage_copy(ctx, table, host.data(), (size_t)n * sizeof(JobDev), s)) != VT_OK)
+    std::vector<char> blob(jb + ob);
+    std::memcpy(blob.data(), host.data(), (size_t)n * sizeof(JobDev));
+    std::memcpy(blob.data() + jb, order.data(), (size_t)n * sizeof(int32_t));
+    if ((st = stage_copy(ctx, table, blob.data(), blob.size(), s)) != VT_OK)
         return st;
-    VT_HIP(vt::launch_fill_i32(counters, 9, 0, s));
-    VT_HIP(vt::launch_label_batch((const JobDev*)table, n, total_tiles, counters, ovf_list, ovf_count,
-                                  ctx->batch_grid, s));
+    VT_HIP(vt::launch_fill_i32(counters, 9 * (int64_t)ng, 0, s));
+    const JobDev* djobs = (const JobDev*)table;
+    if ((st = launch_groups(ctx, djobs, groups, counters, ovf_counts, ovf_list, s)) != VT_OK)
+        return st;
     if (status_dev)
-        k_copy_status<<<(n + 255) / 256, 256, 0, s>>>((const JobDev*)table, n, status_dev);
+        k_copy_status<<<(n + 255) / 256, 256, 0, s>>>(djobs, n, dorder, status_dev);
     VT_HIP(hipGetLastError());
     VT_HIP(hipFreeAsync(table, s));
     return VT_OK;
@@ -726,6 +809,54 @@ vt_status vt_bins_free(vt_ctx* ctx, vt_bins* bins, void* stream)
     delete bins;
     if (e != hipSuccess)
         return hip_fail(e, "hipFreeAsync");
+    return VT_OK;
+}
+
+constexpr unsigned long long kDigestP = 2147483647ull;  // 2^31 - 1
+
+// x mod (2^31 - 1) for x < 2^63, by folding the bits above 31 (2^31 = 1 mod P).
+__device__ inline unsigned long long mod_p31(unsigned long long x)
+{
+    x = (x & kDigestP) + (x >> 31);  // < 2^32 + 2^31
+    x = (x & kDigestP) + (x >> 31);  // <= P + 3
+    return x >= kDigestP ? x - kDigestP : x;
+}
+
+__global__ __launch_bounds__(256) void k_digest(const int32_t* __restrict__ lab, int64_t n,
+                                                unsigned long long* acc)
+{
+    // Every product is below 2^62 and each partial sum is reduced after every
+    // term, so unsigned 64-bit arithmetic is exact.
+    __shared__ unsigned long long part[256 / 64];
+    unsigned long long h = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned long long w = mod_p31((unsigned long long)i * 48271ull + 97ull);
+        const long long t = (long long)lab[i] + 3;  // any int32 label; the mod is the non-negative one
+        const unsigned long long v = t >= 0 ? mod_p31((unsigned long long)t)
+                                            : mod_p31(kDigestP - mod_p31((unsigned long long)(-t)));
+        h = mod_p31(h + v * w);
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        h += __shfl_xor(h, o);  // 64 terms below 2^31: no wrap
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x / 64] = mod_p31(h);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd(acc, mod_p31(part[0] + part[1] + part[2] + part[3]));
+}
+
+vt_status vt_label_digest(vt_ctx* ctx, const int32_t* labels, int64_t n, unsigned long long* acc_dev, void* stream)
+{
+    if (!ctx || n < 0 || !acc_dev || (n > 0 && !labels))
+        return fail(VT_ERR_INVALID, "bad digest arguments");
+    if (n == 0)
+        return VT_OK;
+    VT_HIP(hipSetDevice(ctx->device));
+    int64_t g = (n + 255) / 256;
+    g = std::min<int64_t>(g, 4 * 1024 * 16);
+    k_digest<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(labels, n, acc_dev);
+    VT_HIP(hipGetLastError());
     return VT_OK;
 }
 
@@ -792,7 +923,7 @@ vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char*
     for (int i = 0; i < n && result == VT_OK; ++i) {
         const vt_job* j = &samples[i];
         JobDev d;
-        if ((result = plan_job(ctx, j, &d, false)) != VT_OK)
+        if ((result = plan_job(ctx, j, &d)) != VT_OK)
             break;
         TuneEntry best{};
         best.ms = 1e300;

@@ -156,6 +156,156 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const Job
     J.sidx[pos] = (int32_t)i;
 }
 
+// ---- Johnson-Mehl: sites that never win ----
+//
+// A site s never wins, nor ties, at any voxel if another site r satisfies
+// t_r + d(r, s) / v < t_s - M: by the triangle inequality (which the periodic
+// distance obeys too) t_r + d(x, r) / v <= t_r + d(r, s) / v + d(x, s) / v <
+// t_s + d(x, s) / v - M for every x, and M (2^-36 of the key scale) is far
+// above the rounding error of any computed key.  The paper notes that such
+// nucleation sites are ineffective (Sec. 4); dropping them from the bins leaves
+// the labels unchanged and shortens every candidate list.  A swallowing site
+// lies within (t_s - min t) * v of s, so the search only visits bins that
+// close; a site whose search box exceeds kPruneMaxBins bins is kept.
+
+constexpr int kPruneMaxBins = 4096;
+
+__device__ inline double from_ordered_bits(unsigned long long u)
+{
+    unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double((long long)b);
+}
+
+__device__ inline int find_bin_job(const JobDev* jobs, int n, int64_t g)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].bin_begin <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Marks (in site_bin, indexed by the job's sorted position) the sites that
+// some other site swallows.  One wavefront per site; its lanes take the bins
+// of the search box in parallel.
+__global__ __launch_bounds__(kBlock) void k_jm_mark(JobDev single, const JobDev* __restrict__ jobs, int njobs,
+                                                    const int64_t* __restrict__ prefix, int64_t total)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t g = blockIdx.x * (int64_t)(kBlock / WAVE) + threadIdx.x / WAVE;  // wave-uniform
+    if (g >= total)
+        return;
+    const int j = jobs ? find_segment(prefix, njobs, g) : 0;
+    const JobDev& J = jobs ? jobs[j] : single;
+    if (J.kind != KIND_JM)
+        return;
+    const int nd = J.ndim;
+    const double4 s = J.sites[g];
+    const double sc[3] = {s.x, s.y, s.z};
+    const double tmin = -from_ordered_bits(J.pbound[1]), tmax = from_ordered_bits(J.pbound[0]);
+    double sumL2 = 0.0;
+    for (int a = 0; a < nd; ++a)
+        sumL2 += J.L[a] * J.L[a];
+    const double M = (sqrt(sumL2) * J.rgrowth + 2.0 * fmax(fabs(tmin), fabs(tmax))) * 0x1p-36;
+    const bool periodic = J.bc != 0;
+    bool inside = true;
+    for (int a = 0; a < nd; ++a)
+        inside = inside && sc[a] >= 0.0 && sc[a] < J.L[a];  // invalid input (reported by the count kernel): keep
+    const double gap = (s.w - M) - tmin;
+    bool dead = false;
+    if (inside && gap > 0.0) {
+        const double R = gap * J.growth * (1.0 + 0x1p-20) + J.L[0] * 0x1p-30;
+        int lo[3] = {0, 0, 0}, cnt3[3] = {1, 1, 1};
+        int64_t nbox = 1;
+        for (int a = 0; a < nd; ++a) {
+            const int nb = J.nb[a];
+            const double l = floor((sc[a] - R) * J.inv_bs[a]), h = floor((sc[a] + R) * J.inv_bs[a]);
+            int la, ha;
+            if (!(h - l + 1.0 < (double)nb)) {  // the whole axis (also catches a huge R)
+                la = 0;
+                ha = nb - 1;
+            } else if (periodic) {
+                la = (int)l;  // in (-nb, 2 nb): wrapped below
+                ha = (int)h;
+            } else {
+                la = max((int)l, 0);
+                ha = min((int)h, nb - 1);
+            }
+            lo[a] = la;
+            cnt3[a] = ha - la + 1;
+            nbox *= cnt3[a];
+        }
+        if (nbox <= kPruneMaxBins) {
+            const int nx = cnt3[0], nxy = cnt3[0] * cnt3[1];
+            for (int e0 = 0; e0 < (int)nbox && !dead; e0 += WAVE) {
+                const int e = e0 + lane;
+                bool hit = false;
+                if (e < (int)nbox) {
+                    const int ez = e / nxy, rem = e - ez * nxy, ey = rem / nx, ex = rem - ey * nx;
+                    const int bb[3] = {lo[0] + ex, lo[1] + ey, lo[2] + ez};
+                    int w3[3];
+                    for (int a = 0; a < 3; ++a) {
+                        const int nb = J.nb[a];
+                        w3[a] = bb[a] < 0 ? bb[a] + nb : (bb[a] >= nb ? bb[a] - nb : bb[a]);
+                    }
+                    const int lin = w3[0] + J.nb[0] * (w3[1] + J.nb[1] * w3[2]);
+                    const int b0 = J.bin_start[lin], cnt = J.bin_count[lin];
+                    for (int k = 0; k < cnt && !hit; ++k) {
+                        const int64_t r = b0 + k;
+                        if (r == g)
+                            continue;
+                        const double4 q = J.sites[r];
+                        const double qc[3] = {q.x, q.y, q.z};
+                        double d2 = 0.0;
+                        for (int a = 0; a < nd; ++a) {
+                            double d = sc[a] - qc[a];
+                            if (periodic)
+                                d = d >= 0.5 * J.L[a] ? d - J.L[a] : (d < -0.5 * J.L[a] ? d + J.L[a] : d);
+                            d2 += d * d;
+                        }
+                        hit = q.w + sqrt(d2) * J.rgrowth < s.w - M;
+                    }
+                }
+                dead = __ballot(hit) != 0;
+            }
+        }
+    }
+    if (lane == 0)
+        J.site_bin[g - J.site_begin] = dead ? 1 : 0;
+}
+
+// Moves the live sites of each bin to the front of its range and stores their
+// number in bin_count.
+__global__ __launch_bounds__(kBlock) void k_jm_compact(JobDev single, const JobDev* __restrict__ jobs, int njobs,
+                                                       int64_t total_bins)
+{
+    const int64_t gb = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (gb >= total_bins)
+        return;
+    const int j = jobs ? find_bin_job(jobs, njobs, gb) : 0;
+    const JobDev& J = jobs ? jobs[j] : single;
+    if (J.kind != KIND_JM)
+        return;
+    const int64_t b = gb - J.bin_begin;
+    const int b0 = J.bin_start[b], cnt = J.bin_count[b];
+    int w = 0;
+    for (int k = 0; k < cnt; ++k) {
+        const int r = b0 + k;
+        if (J.site_bin[r - J.site_begin] != 0)
+            continue;
+        if (w != k) {
+            J.sites[b0 + w] = J.sites[r];
+            J.sidx[b0 + w] = J.sidx[r];
+        }
+        ++w;
+    }
+    J.bin_count[b] = w;
+}
+
 // ---- exclusive prefix scan of int32 counts: reduce, scan partials, final ----
 
 constexpr int kScanThreads = 256;
@@ -293,6 +443,17 @@ hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int 
         return hipSuccess;
     k_bin_scatter<<<grid_for(total_sites, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs,
                                                                   site_prefix_dev, total_sites);
+    return hipGetLastError();
+}
+
+hipError_t launch_jm_prune(const JobDev& single, const JobDev* jobs_dev, int njobs,
+                           const int64_t* site_prefix_dev, int64_t total_sites, int64_t total_bins, hipStream_t s)
+{
+    if (total_sites <= 0 || total_bins <= 0)
+        return hipSuccess;
+    k_jm_mark<<<grid_for(total_sites, kBlock / WAVE), kBlock, 0, s>>>(single, jobs_dev, njobs, site_prefix_dev,
+                                                                     total_sites);
+    k_jm_compact<<<grid_for(total_bins, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs, total_bins);
     return hipGetLastError();
 }
 

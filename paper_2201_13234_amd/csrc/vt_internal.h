@@ -29,11 +29,13 @@ struct JobDev {
     double growth, rgrowth;        // v and 1/v
     int64_t nvox, nregions;
     int64_t region_begin;          // first region of this job in a batch enumeration
+    int64_t site_begin;            // first sorted site of this job in a batch (0 for a single job)
+    int64_t bin_begin;             // first bin of this job in a batch (0 for a single job)
     const double* coords;          // [nsites][ndim], caller input
     const double* param;           // [nsites] or null
     int32_t* labels;               // caller output
     int32_t* status;               // one word, written by the kernels
-    int32_t* bin_count;            // [nbins]
+    int32_t* bin_count;            // [nbins] sites per bin (live sites after pruning)
     int32_t* bin_start;            // [nbins + 1], indexes `sites`
     int32_t* site_bin;             // [nsites]
     int32_t* site_rank;            // [nsites]
@@ -71,13 +73,22 @@ hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* part
 int64_t scan_partials_needed(int64_t n);
 hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int njobs,
                               const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s);
+// Johnson-Mehl jobs: drop from their bins the sites that provably never win
+// (after binning; other kinds are left alone).  total_bins covers all jobs.
+hipError_t launch_jm_prune(const JobDev& single, const JobDev* jobs_dev, int njobs,
+                           const int64_t* site_prefix_dev, int64_t total_sites, int64_t total_bins, hipStream_t s);
 
 // Labelling: single job (all its tiles) or a persistent batch launch.
 hipError_t launch_label_single(const JobDev& job, hipStream_t s);
 hipError_t launch_label_fallback(const JobDev& job, hipStream_t s);
-hipError_t launch_label_batch(const JobDev* jobs_dev, int njobs, int64_t total_regions,
-                              int32_t* counters, int32_t* ovf_list, int32_t* ovf_count, int grid,
-                              hipStream_t s);
+// Persistent launch over one group of a batch: jobs of one kernel variant
+// (label_variant), dimension and tile configuration, contiguous in the device
+// table with region_begin counted from 0 over the group.  counters: 8 zeroed
+// ints; ovf_list: 4 entries per region; ovf_count: one zeroed int.
+hipError_t launch_label_group(const JobDev* jobs_dev, int njobs, int variant, int ndim, int cfg,
+                              int64_t total_regions, int32_t* counters, int32_t* ovf_list, int32_t* ovf_count,
+                              int grid, hipStream_t s);
+int label_variant(const JobDev& J);  // 0 Voronoi, 1 Laguerre, 2/3 Johnson-Mehl (multiply / divide by v)
 int label_batch_grid(int device);
 
 }  // namespace vt

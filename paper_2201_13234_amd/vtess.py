@@ -19,7 +19,7 @@ OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BUSY, ERR_INPUT = range(6)
 # Symbols declared in include/vtess.h.
 EXPORTS = ["vt_create", "vt_destroy", "vt_tessellate", "vt_tessellate_batch", "vt_bins_build",
            "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_load_tuning", "vt_set_params",
-           "vt_plan", "vt_numerics_probe", "vt_profile_enable", "vt_profile_read",
+           "vt_plan", "vt_numerics_probe", "vt_label_digest", "vt_profile_enable", "vt_profile_read",
            "vt_status_string", "vt_last_error"]
 
 
@@ -66,6 +66,7 @@ def lib():
         L.vt_set_params.argtypes = [vp, i32, dbl]
         L.vt_plan.argtypes = [vp, P(VtJob), P(i32), P(i32), P(dbl)]
         L.vt_numerics_probe.argtypes = [vp, vp, vp, vp, vp, i64, vp]
+        L.vt_label_digest.argtypes = [vp, vp, i64, vp, vp]
         L.vt_profile_enable.argtypes = [vp, i32]
         L.vt_profile_read.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(i64)]
         L.vt_status_string.argtypes = [ctypes.c_int]
@@ -224,6 +225,21 @@ class Context:
         _check(lib().vt_plan(self.handle, ctypes.byref(cj), nb, ctypes.byref(cfg), ctypes.byref(bf)),
                "vt_plan")
         return dict(bins=tuple(nb), tile_cfg=cfg.value, bin_factor=bf.value)
+
+    def label_digest_async(self, labels, acc, stream=None):
+        """Adds the checksum terms of a device int32 label image to `acc` (a
+        zeroed int64 device tensor of one element); the checksum is
+        int(acc) % (2**31 - 1) once the stream reaches this point."""
+        _check(lib().vt_label_digest(self.handle, _ptr(labels), labels.numel(), _ptr(acc), _stream(stream)),
+               "vt_label_digest")
+
+    def label_digest(self, labels, stream=None):
+        """Checksum of a device label image (waits for the stream)."""
+        import torch
+        acc = torch.zeros(1, dtype=torch.int64, device=labels.device)
+        self.label_digest_async(labels, acc, stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        return int(acc.item()) % 2147483647
 
     def profile_enable(self, enable=True):
         _check(lib().vt_profile_enable(self.handle, 1 if enable else 0), "vt_profile_enable")

@@ -184,6 +184,36 @@ def test_dominant_weight_and_swallowed_sites(ctx):
             check(ctx, workload(n, 2, periodic, pts, t, g, name=f"jm_swallow{g}"))
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_jm_ineffective_sites(ctx, d):
+    """Johnson-Mehl sites that a neighbour's grain reaches before they
+    nucleate are dropped from the bins; the labels must not change."""
+    rng = np.random.default_rng(31 + d)
+    n = (40, 36, 30)[:d] if d == 3 else (160, 130)
+    ns = 400
+    pts = I.uniform_sites(rng, ns, [float(v) for v in n])
+    t = rng.uniform(0.0, 40.0, ns)               # wide spread: about half the sites are swallowed
+    pts[1] = pts[0]                               # duplicates with equal times: neither may go
+    t[1] = t[0]
+    pts[3] = pts[2]
+    t[3] = np.nextafter(t[2], np.inf)             # a duplicate one ulp later: it never wins either
+    for g in (1.0, 0.3, 2.5):
+        for periodic in (True, False):
+            check(ctx, workload(n, 2, periodic, pts, t, g, name=f"jm_ineff{d}_{g}"))
+
+
+def test_jm_swallow_exact_boundary(ctx):
+    # t_s == t_r + |s - r| / v exactly (a 3-4-5 triangle): s is kept and the
+    # lowest index wins where the keys tie.
+    n = (32, 32, 24)
+    pts = np.array([[10.5, 10.5, 10.5], [13.5, 14.5, 10.5], [20.5, 3.5, 12.5], [25.5, 27.5, 17.5]])
+    for order in (1, -1):
+        t = np.array([0.0, 5.0, 1.0, 2.0])[::order]
+        p = pts[::order]
+        for periodic in (True, False):
+            check(ctx, workload(n, 2, periodic, p, t, 1.0, name="jm_edge"))
+
+
 def test_periodic_half_period_boundary(ctx):
     # |s - x| == L/2 exactly: both images are at the same distance.
     n = (8, 8, 8)
