@@ -141,7 +141,10 @@ def main():
     ap.add_argument("--config", default="M2", help="M1..M4 (default M2, the headline workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream replay")
-    ap.add_argument("--serving-jobs", type=int, default=96)
+    ap.add_argument("--serving-jobs", type=int, default=2000,
+                    help="request-stream length (the stream of 2,000 seeded jobs by default)")
+    ap.add_argument("--serving-scale", type=float, default=1.0,
+                    help="scale of the request-stream grid sides (1.0 = full size)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this size three times (a plain "
                          "copy kernel of known traffic, for scaling HBM counters)")
@@ -264,7 +267,9 @@ def main():
     if not args.no_serving:
         from paper_2201_13234_amd import serve
         print(f"[bench] serving replay ({args.serving_jobs} jobs)", file=sys.stderr, flush=True)
-        out["serving"] = serve.benchmark(ctx, n_jobs=args.serving_jobs)
+        out["serving"] = serve.benchmark(ctx, n_jobs=args.serving_jobs, side_scale=args.serving_scale,
+                                         log=lambda m: print(f"[bench] serving: {m}", file=sys.stderr,
+                                                             flush=True))
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

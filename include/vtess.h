@@ -33,6 +33,7 @@
 #ifndef VTESS_H
 #define VTESS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -72,6 +73,12 @@ typedef struct {
  * file named by the environment variable VT_TUNE_CACHE if it is set. */
 vt_status vt_create(int device, vt_ctx** out);
 void vt_destroy(vt_ctx* ctx);
+
+/* Grows the context's scratch to at least `bytes` now (synchronising the
+ * device once), so that later calls that fit never have to grow it, which
+ * would synchronise the device in the middle of queued work.  For serving
+ * loops.  VT_ERR_NOMEM if the allocation fails. */
+vt_status vt_reserve(vt_ctx* ctx, size_t bytes);
 
 /* Plain single-diagram path: bins the sites (counting sort into a uniform
  * bin grid; for Johnson-Mehl also drops the sites that never win, as for

@@ -619,6 +619,14 @@ vt_status vt_profile_read(vt_ctx* ctx, double* bin_ms, double* label_ms, double*
     return VT_OK;
 }
 
+vt_status vt_reserve(vt_ctx* ctx, size_t bytes)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    VT_HIP(hipSetDevice(ctx->device));
+    return ensure_scratch(ctx, bytes);
+}
+
 vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, int32_t* status_dev, void* stream)
 {
     if (!ctx)

@@ -2,16 +2,16 @@
 
 Requests (one diagram each) arrive over time.  The scheduler
   - admits a request as soon as a slot is free and its device memory
-    (labels, sites, bins) fits in the memory budget, in arrival order;
-  - bins every admitted request's sites on a binning stream right away (the
-    bins stay resident on the device);
-  - whenever the labelling stream is idle, labels every admitted request whose
-    bins are ready in one persistent launch (vt_label_batch), so requests that
-    arrived while others were on the GPU join the next batch, and their binning
-    overlaps the running batch;
-  - retires finished requests, releasing their memory and slot.
+    (labels, sites, bins) fits in the memory budget, in arrival order, and
+    starts uploading its sites right away (and, with resident bins, binning
+    them, so the bins stay on the device until the request completes);
+  - whenever a launch lane is free, launches every admitted request whose
+    inputs are ready as one batch (vt_tessellate_batch, or vt_label_batch over
+    resident bins), so requests that arrived while others were on the GPU join
+    the next batch and their uploads overlap the running batches;
+  - retires finished batches, releasing memory and slots.
 Latency is completion time minus arrival time.  The one-by-one baseline runs
-each request alone (vt_tessellate), in arrival order.
+each request alone (vt_tessellate) in arrival order.
 
 The device work sits behind a small executor interface so that the
 scheduling logic can be tested on the CPU with a fake executor.
@@ -34,7 +34,6 @@ class Request:
     digest: int = 0           # hash of the label image
     error: str = ""
     state: dict = field(default_factory=dict)
-    labels: object = None     # device label image kept after completion
 
     @property
     def nvox(self):
@@ -80,47 +79,113 @@ class Executor:
         raise NotImplementedError
 
 
+class PinnedRing:
+    """Host staging for uploads: one pinned buffer used as a ring.  A slice
+    is reused only after the copy that read it has completed (its event)."""
+
+    def __init__(self, torch, nbytes):
+        self.torch = torch
+        self.buf = torch.empty(int(nbytes), dtype=torch.uint8, pin_memory=True)
+        self.np = self.buf.numpy()
+        self.size = int(nbytes)
+        self.head = 0
+        self.inflight = []            # (start, end, event), oldest first
+
+    def _wait_overlap(self, a, b):
+        keep = []
+        for s0, e0, ev in self.inflight:
+            if e0 <= a or s0 >= b:
+                if not ev.query():
+                    keep.append((s0, e0, ev))
+            else:
+                ev.synchronize()
+        self.inflight = keep
+
+    def put(self, arr):
+        """Copies a numpy array into the ring; returns a pinned tensor view."""
+        raw = np.ascontiguousarray(arr).view(np.uint8).reshape(-1)
+        n = (raw.size + 255) // 256 * 256
+        if n > self.size:
+            raise MemoryError("upload larger than the staging ring")
+        if self.head + n > self.size:
+            self.head = 0
+        a, b = self.head, self.head + n
+        self._wait_overlap(a, b)
+        self.np[a:a + raw.size] = raw
+        self.head = b
+        return self.buf[a:a + raw.size], (a, b)
+
+    def mark(self, span, event):
+        self.inflight.append((span[0], span[1], event))
+
+
 class GpuExecutor(Executor):
     """Executor over the device library.
 
-    Uploads run on their own stream.  Labelling launches alternate between
-    `lanes` (context, stream) pairs so that one batch can be binned while the
-    previous one is still labelling.  Two modes:
+    Uploads go through a pinned staging ring on their own stream.  Labelling
+    launches alternate between `lanes` (context, stream) pairs so that one
+    batch can be uploaded and binned while the previous one is still
+    labelling.  Two modes:
       resident_bins=False  each launch is one vt_tessellate_batch call:
                            segmented binning of the batch plus one persistent
-                           labelling launch;
+                           labelling launch per kind/shape group;
       resident_bins=True   every request is binned on arrival (vt_bins_build,
                            bins stay on the device) and a launch is one
                            vt_label_batch over the resident bins.
-    With keep_labels the label images stay on the device after completion so
-    that digest_all() can hash them outside the timed replay.
+    Statuses come back through pinned host memory copied on the lane stream,
+    so retiring a batch never synchronises.  With digest=True every label
+    image is hashed on the device (vt_label_digest) on a separate stream once
+    its batch has completed -- after the completion time is taken -- and the
+    image is released; collect_digests() returns the hashes.
     """
 
-    def __init__(self, ctx, device="cuda:0", lanes=2, resident_bins=False, keep_labels=True):
+    def __init__(self, ctx, device="cuda:0", lanes=2, resident_bins=False, digest=True,
+                 staging_bytes=256 << 20, reserve_bytes=512 << 20, max_batch=256):
         import torch
         from . import vtess
         self.torch = torch
         self.dev = torch.device(device)
         self.ctxs = [ctx] + [vtess.Context(self.dev.index or 0) for _ in range(lanes - 1)]
+        for c in self.ctxs:
+            c.reserve(reserve_bytes)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
         self.s_up = torch.cuda.Stream(device=self.dev)
+        self.s_dig = torch.cuda.Stream(device=self.dev)
+        self.ring = PinnedRing(torch, staging_bytes)
+        self.status_host = [torch.empty(max_batch, dtype=torch.int32, pin_memory=True) for _ in range(lanes)]
+        self.status_dev = [torch.empty(max_batch, dtype=torch.int32, device=self.dev) for _ in range(lanes)]
         self.free_lanes = list(range(lanes))
         self.max_inflight = lanes
+        self.max_batch = max_batch
         self.resident_bins = resident_bins
-        self.keep_labels = keep_labels
+        self.digest = digest
+        self.pending = []             # (request id, accumulator tensor)
+
+    def _upload(self, arr):
+        host, span = self.ring.put(arr)
+        with self.torch.cuda.stream(self.s_up):
+            dev = self.torch.empty(arr.shape, dtype=self.torch.float64, device=self.dev)
+            dev.view(-1).view(self.torch.uint8).copy_(host, non_blocking=True)
+        return dev, span
 
     def _job(self, req):
         from . import vtess
         torch = self.torch
         w = req.workload
         st = req.state
+        st["coords"], span = self._upload(w.coords)
+        spans = [span]
+        st["param"] = None
+        if w.param is not None:
+            st["param"], span = self._upload(w.param)
+            spans.append(span)
         with torch.cuda.stream(self.s_up):
-            st["coords"] = torch.from_numpy(np.ascontiguousarray(w.coords)).pin_memory().to(
-                self.dev, non_blocking=True)
-            st["param"] = None if w.param is None else torch.from_numpy(
-                np.ascontiguousarray(w.param)).pin_memory().to(self.dev, non_blocking=True)
             st["labels"] = torch.empty(w.shape, dtype=torch.int32, device=self.dev)
-            st["status"] = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        ev = torch.cuda.Event()
+        ev.record(self.s_up)
+        for sp in spans:
+            self.ring.mark(sp, ev)
+        st["ev_up"] = ev
         return vtess.Job(n=w.n, L=w.L, kind=w.kind, periodic=w.periodic, growth=w.growth,
                          coords=st["coords"], param=st["param"], labels=st["labels"])
 
@@ -130,7 +195,8 @@ class GpuExecutor(Executor):
     def start_binning(self, req):
         st = req.state
         if self.resident_bins:
-            st["bins"] = self.ctxs[0].bins_build(st["job"], status=st["status"], stream=self.s_up)
+            st["bstat"] = self.torch.empty(1, dtype=self.torch.int32, device=self.dev)
+            st["bins"] = self.ctxs[0].bins_build(st["job"], status=st["bstat"], stream=self.s_up)
         ev = self.torch.cuda.Event()
         ev.record(self.s_up)
         st["ev_ready"] = ev
@@ -140,25 +206,32 @@ class GpuExecutor(Executor):
 
     def start_labelling(self, reqs):
         torch = self.torch
+        if len(reqs) > self.max_batch:
+            raise ValueError("batch larger than max_batch")
         lane = self.free_lanes.pop(0)
         s = self.streams[lane]
         for r in reqs:
             s.wait_event(r.state["ev_ready"])
+        st = self.status_dev[lane][: len(reqs)]
         if self.resident_bins:
-            st = torch.empty(len(reqs), dtype=torch.int32, device=self.dev)
             self.ctxs[lane].label_batch([r.state["bins"] for r in reqs], status=st, stream=s)
         else:
-            with torch.cuda.stream(s):
-                st = torch.empty(len(reqs), dtype=torch.int32, device=self.dev)
             self.ctxs[lane].tessellate_batch([r.state["job"] for r in reqs], status=st, stream=s)
+        with torch.cuda.stream(s):
+            self.status_host[lane][: len(reqs)].copy_(st, non_blocking=True)
         for k, r in enumerate(reqs):
-            r.state["status"] = st[k:k + 1]
+            r.state["lane"], r.state["slot"] = lane, k
         ev = torch.cuda.Event()
         ev.record(s)
         return (lane, ev)
 
     def labelling_done(self, token):
+        # The scheduler retires (finish) every request of a completed launch
+        # before it starts another one, so the lane's status slots are read
+        # before the lane is reused.
         if token[1].query():
+            if self.digest:
+                self.s_dig.wait_event(token[1])
             if token[0] not in self.free_lanes:
                 self.free_lanes.append(token[0])
             return True
@@ -166,45 +239,52 @@ class GpuExecutor(Executor):
 
     def finish(self, req):
         st = req.state
-        req.status = int(st["status"].item())
+        lane = st["lane"]
+        req.status = int(self.status_host[lane][st["slot"]])
         if self.resident_bins:
-            st["bins"].free(stream=self.s_up)
-        if self.keep_labels:
-            req.labels = st["labels"]
+            st["bins"].free(stream=self.streams[lane])
+        self._digest(req, st["labels"])
         req.state = {}
+
+    def _digest(self, req, labels):
+        if not self.digest:
+            return
+        torch = self.torch
+        with torch.cuda.stream(self.s_dig):
+            acc = torch.zeros(1, dtype=torch.int64, device=self.dev)
+        self.ctxs[0].label_digest_async(labels, acc, stream=self.s_dig)
+        labels.record_stream(self.s_dig)
+        self.pending.append((req.rid, acc))
 
     def run_alone(self, req):
         job = self._job(req)
         st = req.state
         s = self.streams[0]
-        s.wait_stream(self.s_up)
-        self.ctxs[0].tessellate(job, status=st["status"], stream=s)
+        s.wait_event(st["ev_up"])
+        status = self.status_dev[0][:1]
+        self.ctxs[0].tessellate(job, status=status, stream=s)
+        with self.torch.cuda.stream(s):
+            self.status_host[0][:1].copy_(status, non_blocking=True)
         s.synchronize()
-        req.status = int(st["status"].item())
-        if self.keep_labels:
-            req.labels = st["labels"]
+        req.status = int(self.status_host[0][0])
+        if self.digest:
+            self.s_dig.wait_stream(s)
+        self._digest(req, st["labels"])
         req.state = {}
 
-    def digest_all(self, reqs):
-        """Hashes the kept label images (after the replay) and drops them."""
-        for r in reqs:
-            if getattr(r, "labels", None) is not None:
-                r.digest = int(digest_device(r.labels).item())
-                r.labels = None
+    def collect_digests(self):
+        """Waits for the digest stream; returns {request id: checksum}."""
+        self.s_dig.synchronize()
+        out = {rid: int(acc.item()) % _P for rid, acc in self.pending}
+        self.pending = []
+        return out
 
 
 # Order-sensitive hash of a label image: sum over voxels i of
-# (label_i + 3) * ((i * 48271 + 97) mod P), mod P, P = 2^31 - 1.  Every term
-# stays below 2^62, so int64 arithmetic is exact on both sides.
+# (label_i + 3) * ((i * 48271 + 97) mod P), mod P, P = 2^31 - 1 (the device
+# library's vt_label_digest computes the same; every term stays below 2^62, so
+# int64 arithmetic is exact).
 _P = 2147483647
-
-
-def digest_device(labels):
-    """Hash of a device label image (torch ops on the current stream)."""
-    import torch
-    flat = labels.reshape(-1).to(torch.int64)
-    w = (torch.arange(flat.numel(), device=labels.device, dtype=torch.int64) * 48271 + 97) % _P
-    return ((flat + 3) * w % _P).sum() % _P
 
 
 def digest_host(labels):
@@ -355,35 +435,42 @@ def make_stream(n_jobs, rate, side_scale=0.25, first_job=0):
             for i in range(n_jobs)]
 
 
-def benchmark(ctx, n_jobs=96, side_scale=0.25, load=0.8, mem_budget=8 << 30, lanes=2):
+def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, lanes=2, calib_jobs=100,
+              max_batch=64, log=None):
     """Replays a request stream twice on the GPU -- continuous batching and one
     by one -- with the same arrival times.  The arrival rate is `load` times
-    the one-by-one service rate, measured on the same jobs run back to back.
-    Returns p50/p99 latency and throughput of both, and whether every job's
-    labels are identical in both modes."""
-    ex = GpuExecutor(ctx, lanes=lanes)
+    the one-by-one service rate, measured on the first `calib_jobs` jobs run
+    back to back.  Returns p50/p99 latency and throughput of both modes, and
+    whether every job's labels (device checksums) are the same in both."""
+    say = log or (lambda msg: None)
+    ex = GpuExecutor(ctx, lanes=lanes, max_batch=max(max_batch, 1))
+    say(f"generating {n_jobs} jobs")
     jobs = make_stream(n_jobs, 1.0, side_scale)
-    # warm-up of both paths, then the one-by-one service time of exactly these
-    # jobs, back to back
-    Server(ex).run_one_by_one([Request(r.rid, r.workload, 0.0) for r in jobs[:16]])
-    Server(ex).run([Request(r.rid, r.workload, 0.0) for r in jobs[:16]])
-    cal = Server(ex).run_one_by_one([Request(r.rid, r.workload, 0.0) for r in jobs])
+    copy = lambda rs, t=None: [Request(r.rid, r.workload, r.arrival if t is None else t) for r in rs]
+    # warm-up of both paths, then the one-by-one service time, back to back
+    Server(ex, mem_budget=mem_budget).run_one_by_one(copy(jobs[:16], 0.0))
+    Server(ex, mem_budget=mem_budget, max_batch=max_batch).run(copy(jobs[:16], 0.0))
+    ex.collect_digests()
+    cal = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(jobs[:calib_jobs], 0.0))
+    ex.collect_digests()
     service = max(r.done for r in cal) / len(cal)
-    for r in cal:
-        r.labels = None
     rate = load / service
     from . import inputs
     t = inputs.arrivals(n_jobs, rate)
     stream = [Request(r.rid, r.workload, float(t[k])) for k, r in enumerate(jobs)]
-    srv = Server(ex, mem_budget=mem_budget)
-    batched = srv.run([Request(r.rid, r.workload, r.arrival) for r in stream])
-    ex.digest_all(batched)
-    alone = Server(ex, mem_budget=mem_budget).run_one_by_one(
-        [Request(r.rid, r.workload, r.arrival) for r in stream])
-    ex.digest_all(alone)
-    same = all(a.digest == b.digest and a.status == b.status for a, b in zip(batched, alone))
-    return {"jobs": n_jobs, "side_scale": side_scale, "rate_per_s": round(rate, 2),
-            "service_ms_alone": round(service * 1e3, 3), "lanes": lanes,
+    say(f"batched replay at {rate:.1f} jobs/s")
+    srv = Server(ex, mem_budget=mem_budget, max_batch=max_batch)
+    batched = srv.run(copy(stream))
+    db = ex.collect_digests()
+    say("one-by-one replay")
+    alone = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(stream))
+    da = ex.collect_digests()
+    same = all(a.status == b.status and db.get(a.rid) == da.get(b.rid) for a, b in zip(batched, alone))
+    nvox = [r.nvox for r in stream]
+    return {"jobs": n_jobs, "side_scale": side_scale, "load": load, "rate_per_s": round(rate, 2),
+            "service_ms_alone": round(service * 1e3, 3), "lanes": lanes, "max_batch": max_batch,
+            "voxels_total": int(sum(nvox)), "voxels_p50": int(np.percentile(nvox, 50)),
             "batched": summarize(batched), "one_by_one": summarize(alone),
             "mean_batch": round(float(np.mean(srv.batches)), 2) if srv.batches else 0,
-            "labels_identical": bool(same)}
+            "peak_mem_gb": round(srv.peak_mem / 2 ** 30, 2),
+            "labels_identical": bool(same), "checked_jobs": len(db)}

@@ -17,7 +17,7 @@ NONPERIODIC, PERIODIC = 0, 1
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BUSY, ERR_INPUT = range(6)
 
 # Symbols declared in include/vtess.h.
-EXPORTS = ["vt_create", "vt_destroy", "vt_tessellate", "vt_tessellate_batch", "vt_bins_build",
+EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessellate_batch", "vt_bins_build",
            "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_load_tuning", "vt_set_params",
            "vt_plan", "vt_numerics_probe", "vt_label_digest", "vt_profile_enable", "vt_profile_read",
            "vt_status_string", "vt_last_error"]
@@ -67,6 +67,7 @@ def lib():
         L.vt_plan.argtypes = [vp, P(VtJob), P(i32), P(i32), P(dbl)]
         L.vt_numerics_probe.argtypes = [vp, vp, vp, vp, vp, i64, vp]
         L.vt_label_digest.argtypes = [vp, vp, i64, vp, vp]
+        L.vt_reserve.argtypes = [vp, ctypes.c_size_t]
         L.vt_profile_enable.argtypes = [vp, i32]
         L.vt_profile_read.argtypes = [vp, P(dbl), P(dbl), P(dbl), P(i64)]
         L.vt_status_string.argtypes = [ctypes.c_int]
@@ -225,6 +226,10 @@ class Context:
         _check(lib().vt_plan(self.handle, ctypes.byref(cj), nb, ctypes.byref(cfg), ctypes.byref(bf)),
                "vt_plan")
         return dict(bins=tuple(nb), tile_cfg=cfg.value, bin_factor=bf.value)
+
+    def reserve(self, nbytes):
+        """Pre-sizes the context's scratch (synchronises the device once)."""
+        _check(lib().vt_reserve(self.handle, int(nbytes)), "vt_reserve")
 
     def label_digest_async(self, labels, acc, stream=None):
         """Adds the checksum terms of a device int32 label image to `acc` (a
