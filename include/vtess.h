@@ -70,7 +70,9 @@ typedef struct {
 } vt_job;
 
 /* Creates a context on HIP device `device`.  Reads a tuning cache from the
- * file named by the environment variable VT_TUNE_CACHE if it is set. */
+ * file named by the environment variable VT_TUNE_CACHE if it is set.  A
+ * context owns one scratch arena that each call reuses: give each context
+ * one stream (or order its calls), and one host thread at a time. */
 vt_status vt_create(int device, vt_ctx** out);
 void vt_destroy(vt_ctx* ctx);
 
@@ -129,7 +131,8 @@ vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path);
 /* Forces the tile configuration and bin-size factor of later calls
  * (tile_cfg < 0 and bin_factor <= 0 restore the tuned/default choice).
  * Tile configurations (voxels, x first): 3D 0 = 8x16x8, 1 = 8x8x8,
- * 2 = 16x16x4; 2D 0 = 32x32, 1 = 32x16, 2 = 16x64. */
+ * 2 = 8x4x4, 3 = 4x4x4; 2D 0 = 32x32, 1 = 32x16, 2 = 16x8, 3 = 8x8.  By default
+ * the tile shrinks as the sites get denser (voxels per site). */
 vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor);
 
 /* Bins per axis and tile configuration the next call would use for job. */
@@ -147,8 +150,8 @@ vt_status vt_numerics_probe(vt_ctx* ctx, const double* x, const double* den, dou
 /* Order-sensitive checksum of a label image, for checking results without
  * copying them to the host (serving, benchmarks).  Adds
  *     sum over i < n of (labels[i] + 3) * ((i * 48271 + 97) mod P),
- * taken mod P = 2^31 - 1 per workgroup, to *acc_dev (a device uint64 that the
- * caller zeroes; fewer than 2^32 workgroups so the total does not wrap).  The
+ * taken mod P = 2^31 - 1 per workgroup (at most 1024 of them), to *acc_dev (a
+ * device uint64 that the caller zeroes).  The
  * checksum is *acc_dev mod P once the stream reaches this point.  labels is a
  * device int32 array of n entries; nothing is allocated.  VT_ERR_INVALID for
  * n < 0 or NULL pointers with n > 0. */

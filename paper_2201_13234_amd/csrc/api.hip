@@ -112,27 +112,38 @@ const TuneEntry* find_tune(const vt_ctx* ctx, const vt_job* j, int64_t nvox)
     return nullptr;
 }
 
-// Tile configuration and bin size: forced, tuned, or default.  The defaults
-// are the fastest measured settings for 3D uniform random sites: Voronoi and
-// Laguerre diagrams gather from bins larger than the mean site spacing (fewer
-// bin visits per region; Laguerre cells vary more in size); a Johnson-Mehl
-// diagram, whose cells reach further, labels best with the smaller 8x8x8
-// tiles.  Batched launches group jobs by configuration, so the same choice
-// holds there.
+// Tile configuration and bin size: forced, tuned, or default.  The default
+// tile shrinks as sites get denser (voxels per site), so that a tile's
+// candidate list stays well under its capacity: thresholds from the candidate
+// counts of uniform random sites, 1.5 times stricter for Laguerre and
+// Johnson-Mehl diagrams, whose weights and times let farther sites compete.
+// Among the sparse settings, the fastest measured for 3D uniform random
+// sites: Voronoi and Laguerre diagrams gather from bins larger than the mean
+// site spacing (fewer bin visits per region; Laguerre cells vary more in
+// size); a Johnson-Mehl diagram, whose cells reach further, labels best with
+// 8x8x8 tiles.  Batched launches group jobs by configuration, so the same
+// choice holds there.
 void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_out, double* bf_out)
 {
-    int cfg = 0;
+    const double vps = (double)nvox / (double)std::max<int64_t>(j->nsites, 1) /
+                       (j->kind == VT_VORONOI ? 1.0 : 1.5);
+    int cfg;
     double bf = 1.0;
     if (j->ndim == 3) {
+        cfg = vps >= 729.0 ? 0 : (vps >= 216.0 ? 1 : (vps >= 91.0 ? 2 : 3));
         if (j->kind == VT_VORONOI) {
             bf = 1.4;
         } else if (j->kind == VT_LAGUERRE) {
             bf = 2.0;
         } else {
-            cfg = 1;
+            cfg = cfg == 0 ? 1 : cfg;
             bf = 1.2;
         }
+    } else {
+        cfg = vps >= 144.0 ? 0 : (vps >= 81.0 ? 1 : (vps >= 20.0 ? 2 : 3));
     }
+    if (cfg >= 2)
+        bf = 1.0;  // small regions: bins of one spacing keep the region list short
     if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
         cfg = t->cfg;
         bf = t->bin_factor;
@@ -141,7 +152,7 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
         cfg = ctx->force_cfg;
     if (ctx->force_bin > 0.0)
         bf = ctx->force_bin;
-    if (cfg < 0 || cfg > 2)
+    if (cfg < 0 || cfg >= vt::kNumCfg)
         cfg = 0;
     *cfg_out = cfg;
     *bf_out = bf;
@@ -517,8 +528,8 @@ vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor)
 {
     if (!ctx)
         return fail(VT_ERR_INVALID, "ctx is NULL");
-    if (tile_cfg > 2)
-        return fail(VT_ERR_INVALID, "tile_cfg must be 0, 1 or 2 (or < 0)");
+    if (tile_cfg >= vt::kNumCfg)
+        return fail(VT_ERR_INVALID, "tile_cfg must be 0, 1, 2 or 3 (or < 0)");
     if (!(bin_factor <= 0.0 || (bin_factor >= 0.125 && bin_factor <= 16.0)))
         return fail(VT_ERR_INVALID, "bin_factor out of range");
     ctx->force_cfg = tile_cfg;
@@ -675,6 +686,8 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     const int64_t pcap = vt::scan_partials_needed(total_bins);
     const size_t o_part = c.take<int32_t>(pcap);
     const size_t o_ovf = c.take<int32_t>(total_tiles * 4);
+    const size_t jb = align_up(host.size() * sizeof(JobDev), 256);
+    const size_t o_tab = c.take<char>((int64_t)(jb + prefix.size() * sizeof(int64_t)), 256);
     vt_status st = ensure_scratch(ctx, align_up(c.off, 256));
     if (st != VT_OK)
         return st;
@@ -693,14 +706,12 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
         d.ovf_count = (int32_t*)(base + o_ovfc) + group_of[k];
         d.ovf_list = (int32_t*)(base + o_ovf) + g.ovf_off;
     }
-    // job table and site prefix in one stream-ordered allocation
-    const size_t jb = align_up(host.size() * sizeof(JobDev), 256);
+    // job table and site prefix, in the scratch arena (stream-ordered like the
+    // rest of it)
     std::vector<char> blob(jb + prefix.size() * sizeof(int64_t));
     std::memcpy(blob.data(), host.data(), host.size() * sizeof(JobDev));
     std::memcpy(blob.data() + jb, prefix.data(), prefix.size() * sizeof(int64_t));
-    void* table = nullptr;
-    if ((st = alloc_table(blob.size(), s, &table)) != VT_OK)
-        return st;
+    void* table = base + o_tab;
     if ((st = stage_copy(ctx, table, blob.data(), blob.size(), s)) != VT_OK)
         return st;
     const JobDev* djobs = (const JobDev*)table;
@@ -715,11 +726,8 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
                            (int32_t*)(base + o_part), pcap, s));
     VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
     VT_HIP(vt::launch_jm_prune(dummy, djobs, njobs, dprefix, total_sites, total_bins, s));
-    if ((st = launch_groups(ctx, djobs, groups, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovfc),
-                            (int32_t*)(base + o_ovf), s)) != VT_OK)
-        return st;
-    VT_HIP(hipFreeAsync(table, s));
-    return VT_OK;
+    return launch_groups(ctx, djobs, groups, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovfc),
+                         (int32_t*)(base + o_ovf), s);
 }
 
 vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out, int32_t* status_dev, void* stream)
@@ -861,8 +869,10 @@ vt_status vt_label_digest(vt_ctx* ctx, const int32_t* labels, int64_t n, unsigne
     if (n == 0)
         return VT_OK;
     VT_HIP(hipSetDevice(ctx->device));
+    // A grid-stride launch of at most 1024 workgroups: each adds one partial
+    // sum, so the accumulator sees few atomics.
     int64_t g = (n + 255) / 256;
-    g = std::min<int64_t>(g, 4 * 1024 * 16);
+    g = std::min<int64_t>(g, 1024);
     k_digest<<<(unsigned)g, 256, 0, (hipStream_t)stream>>>(labels, n, acc_dev);
     VT_HIP(hipGetLastError());
     return VT_OK;
@@ -935,7 +945,7 @@ vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char*
             break;
         TuneEntry best{};
         best.ms = 1e300;
-        for (int cfg = 0; cfg < 3 && result == VT_OK; ++cfg) {
+        for (int cfg = 0; cfg < vt::kNumCfg && result == VT_OK; ++cfg) {
             for (double bf : factors) {
                 ctx->force_cfg = cfg;
                 ctx->force_bin = bf;

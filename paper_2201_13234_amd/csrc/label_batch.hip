@@ -86,7 +86,8 @@ hipError_t launch_group_kind(int cfg, const JobDev* jobs, int njobs, int64_t tot
     switch (cfg) {
     case 0: return launch_group_cfg<KIND, DIM, 0>(jobs, njobs, total, counters, ovf_list, ovf_count, grid, s);
     case 1: return launch_group_cfg<KIND, DIM, 1>(jobs, njobs, total, counters, ovf_list, ovf_count, grid, s);
-    default: return launch_group_cfg<KIND, DIM, 2>(jobs, njobs, total, counters, ovf_list, ovf_count, grid, s);
+    case 2: return launch_group_cfg<KIND, DIM, 2>(jobs, njobs, total, counters, ovf_list, ovf_count, grid, s);
+    default: return launch_group_cfg<KIND, DIM, 3>(jobs, njobs, total, counters, ovf_list, ovf_count, grid, s);
     }
 }
 
@@ -123,7 +124,7 @@ hipError_t launch_label_group(const JobDev* jobs_dev, int njobs, int variant, in
 {
     if (total_regions <= 0 || njobs <= 0)
         return hipSuccess;
-    if (variant < KV || variant > KJD || cfg < 0 || cfg > 2 || (ndim != 2 && ndim != 3))
+    if (variant < KV || variant > KJD || cfg < 0 || cfg >= kNumCfg || (ndim != 2 && ndim != 3))
         return hipErrorInvalidValue;
     if (total_regions < grid)
         grid = (int)total_regions;

@@ -1242,6 +1242,24 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     S.cm[lane] = make_int2(R.ri[e], code | (e << 8));
                 }
             } else {
+                // Images per tile (box_bounds).  The reference test runs for
+                // sites whose wrap code is uniform over the tile, against the
+                // site attaining the tile's upper bound when its own is too.
+                double gb[3] = {0.0, 0.0, 0.0}, eb = 0.0, tb = 0.0, dbmax = 0.0;
+                bool ref_ok = false;
+                if (ubPos >= 0) {
+                    int fb;
+                    double lbb, ubb, dmnb;
+                    double4 g4;
+                    const double4 sb = R.rs[ubPos];
+                    box_bounds<KIND, DIM>(J, C, BT, periodic, sb, fb, lbb, ubb, dmnb, dbmax, g4);
+                    ref_ok = (fb & FL_GENERIC) == 0;
+                    gb[0] = g4.x;
+                    gb[1] = g4.y;
+                    gb[2] = g4.z;
+                    eb = g4.w;
+                    tb = sb.w;
+                }
                 for (int ebase = 0; ebase < nR; ebase += WAVE) {
                     const int e = ebase + lane;
                     int flags = 0;
@@ -1251,7 +1269,11 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                         s = R.rs[e];
                         box_bounds<KIND, DIM>(J, C, BT, periodic, s, flags, lb, ub, dmn, dmx, g);
                     }
-                    const bool keep = e < nR && lb <= thr;
+                    bool keep = e < nR && lb <= thr;
+                    if (keep && ref_ok && (flags & FL_GENERIC) == 0 && e != ubPos) {
+                        const double sg[3] = {g.x, g.y, g.z};
+                        keep = !beaten_by<KIND, DIM>(C, BT, sg, s.w, dmn, gb, eb, tb, dbmax);
+                    }
                     const unsigned long long km = __ballot(keep);
                     if (nc + __popcll(km) > CAP_S) {
                         tile_ovf = true;

@@ -65,13 +65,15 @@ hipError_t launch_single_cfg(const JobDev& job, hipStream_t s, bool fallback)
         switch (job.cfg) {
         case 0: k_label_fallback<KIND, DIM, 0><<<grid, WAVE, 0, s>>>(job); break;
         case 1: k_label_fallback<KIND, DIM, 1><<<grid, WAVE, 0, s>>>(job); break;
-        default: k_label_fallback<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(job); break;
+        case 2: k_label_fallback<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(job); break;
+        default: k_label_fallback<KIND, DIM, 3><<<grid, WAVE, 0, s>>>(job); break;
         }
     } else {
         switch (job.cfg) {
         case 0: k_label_single<KIND, DIM, 0><<<grid, NT, 0, s>>>(job); break;
         case 1: k_label_single<KIND, DIM, 1><<<grid, NT, 0, s>>>(job); break;
-        default: k_label_single<KIND, DIM, 2><<<grid, NT, 0, s>>>(job); break;
+        case 2: k_label_single<KIND, DIM, 2><<<grid, NT, 0, s>>>(job); break;
+        default: k_label_single<KIND, DIM, 3><<<grid, NT, 0, s>>>(job); break;
         }
     }
     return hipGetLastError();

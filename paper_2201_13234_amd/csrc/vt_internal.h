@@ -48,16 +48,22 @@ struct JobDev {
 
 // Tile configurations: a lane labels `rows` runs of `run` voxels along x
 // (consecutive in y); lanes along x, y, z (one wavefront per tile); tiles per
-// region along x, y, z (one workgroup of four wavefronts per region).
+// region along x, y, z (one workgroup of four wavefronts per region).  Denser
+// site sets need smaller tiles so that a tile's candidate list stays short.
 struct TileShape { int run, lx, ly, lz, rows, rx, ry, rz; };
+constexpr int kNumCfg = 4;
 // 3D: 0 = 8x16x8 tiles (two rows per lane) in 16x16x16 regions;
 //     1 = 8x8x8 tiles in 16x16x8 regions;
-//     2 = 16x16x4 tiles (two rows per lane) in 16x16x16 regions.
-constexpr TileShape kShape3[3] = {{8, 1, 8, 8, 2, 2, 1, 2}, {8, 1, 8, 8, 1, 2, 2, 1}, {8, 2, 8, 4, 2, 1, 1, 4}};
+//     2 = 8x4x4 tiles (two voxels per lane) in 8x8x8 regions;
+//     3 = 4x4x4 tiles (one voxel per lane) in 8x8x4 regions.
+constexpr TileShape kShape3[kNumCfg] = {{8, 1, 8, 8, 2, 2, 1, 2}, {8, 1, 8, 8, 1, 2, 2, 1},
+                                        {2, 4, 4, 4, 1, 1, 2, 2}, {1, 4, 4, 4, 1, 2, 2, 1}};
 // 2D: 0 = 32x32 tiles (two rows per lane) in 64x64 regions;
 //     1 = 32x16 tiles in 64x32 regions;
-//     2 = 16x64 tiles (two rows per lane) in 64x64 regions.
-constexpr TileShape kShape2[3] = {{8, 4, 16, 1, 2, 2, 2, 1}, {8, 4, 16, 1, 1, 2, 2, 1}, {8, 2, 32, 1, 2, 4, 1, 1}};
+//     2 = 16x8 tiles (two voxels per lane) in 32x16 regions;
+//     3 = 8x8 tiles (one voxel per lane) in 16x16 regions.
+constexpr TileShape kShape2[kNumCfg] = {{8, 4, 16, 1, 2, 2, 2, 1}, {8, 4, 16, 1, 1, 2, 2, 1},
+                                        {2, 8, 8, 1, 1, 2, 2, 1}, {1, 8, 8, 1, 1, 2, 2, 1}};
 
 inline TileShape shape_of(int ndim, int cfg) { return ndim == 3 ? kShape3[cfg] : kShape2[cfg]; }
 

@@ -128,7 +128,8 @@ class GpuExecutor(Executor):
     labelling.  Two modes:
       resident_bins=False  each launch is one vt_tessellate_batch call:
                            segmented binning of the batch plus one persistent
-                           labelling launch per kind/shape group;
+                           labelling launch per kind/shape group (a launch of
+                           a single request is a plain vt_tessellate call);
       resident_bins=True   every request is binned on arrival (vt_bins_build,
                            bins stay on the device) and a launch is one
                            vt_label_batch over the resident bins.
@@ -215,6 +216,9 @@ class GpuExecutor(Executor):
         st = self.status_dev[lane][: len(reqs)]
         if self.resident_bins:
             self.ctxs[lane].label_batch([r.state["bins"] for r in reqs], status=st, stream=s)
+        elif len(reqs) == 1:
+            # a launch of one request takes the plain path (no job table)
+            self.ctxs[lane].tessellate(reqs[0].state["job"], status=st, stream=s)
         else:
             self.ctxs[lane].tessellate_batch([r.state["job"] for r in reqs], status=st, stream=s)
         with torch.cuda.stream(s):
@@ -391,8 +395,9 @@ class Server:
                 self.batches.append(len(batch))
                 progressed = True
             if not progressed:
-                if queue and not (binning or ready or running) and queue[0].arrival > now():
-                    self.sleep(min(queue[0].arrival - now(), 0.001))
+                wait = queue[0].arrival - now() if queue else 0.0
+                if wait > 0 and not (binning or ready or running):
+                    self.sleep(min(wait, 0.001))
                 else:
                     self.sleep(0)
         return sorted(done, key=lambda r: r.rid)
@@ -402,8 +407,11 @@ class Server:
         reqs = sorted(requests, key=lambda r: r.arrival)
         t0 = self.clock()
         for r in reqs:
-            while self.clock() - t0 < r.arrival:
-                self.sleep(min(r.arrival - (self.clock() - t0), 0.001))
+            while True:
+                wait = r.arrival - (self.clock() - t0)
+                if wait <= 0:
+                    break
+                self.sleep(min(wait, 0.001))
             r.admitted = self.clock() - t0
             if device_bytes(r.workload) > self.mem_budget:
                 r.status, r.error = -2, "request larger than the memory budget"

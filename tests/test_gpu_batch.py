@@ -108,9 +108,10 @@ def test_resident_bins_and_label_batches(ctx):
 def test_serving_mix_equals_alone(ctx, resident):
     from paper_2201_13234_amd import serve as S
     ex = S.GpuExecutor(ctx, resident_bins=resident, staging_bytes=8 << 20, reserve_bytes=64 << 20)
-    reqs = S.make_stream(40, rate=400.0, side_scale=0.12)
+    # a burst (every request at t = 0) so that launches hold several requests
+    reqs = S.make_stream(40, rate=1e9, side_scale=0.12)
     srv = S.Server(ex, mem_budget=1 << 30, max_batch=16)
-    mixed = srv.run([S.Request(r.rid, r.workload, r.arrival) for r in reqs])
+    mixed = srv.run([S.Request(r.rid, r.workload, 0.0) for r in reqs])
     dm = ex.collect_digests()
     alone = S.Server(ex).run_one_by_one([S.Request(r.rid, r.workload, r.arrival) for r in reqs])
     da = ex.collect_digests()
@@ -143,7 +144,7 @@ def test_autotune_roundtrip(ctx, tmp_path):
     c2 = vtess.Context(0)
     c2.load_tuning(path)
     plan = c2.plan(to_dev(w))
-    assert plan["tile_cfg"] in (0, 1, 2)
+    assert plan["tile_cfg"] in (0, 1, 2, 3)
     job = to_dev(w)
     c2.tessellate(job)
     torch.cuda.synchronize()

@@ -74,7 +74,7 @@ def test_random_small_jobs(ctx, seed):
     check(ctx, random_workload(seed))
 
 
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3])
 @pytest.mark.parametrize("bf", [0.7, 1.0, 2.0])
 def test_m1_all_tile_shapes_and_bin_sizes(ctx, cfg, bf):
     check(ctx, I.m1(), cfgs=[(cfg, bf)])
@@ -86,7 +86,7 @@ def test_m1_all_tile_shapes_and_bin_sizes(ctx, cfg, bf):
 def test_every_variant_and_tile_shape(ctx, kind, periodic, d):
     n = (37, 29, 23) if d == 3 else (131, 77)
     w = I.make(n, kind, periodic, 300 if d == 3 else 250, 77 + kind + 3 * d, growth=0.75)
-    check(ctx, w, cfgs=[(0, 0.0), (1, 0.0), (2, 0.0)])
+    check(ctx, w, cfgs=[(0, 0.0), (1, 0.0), (2, 0.0), (3, 0.0)])
 
 
 # ---------------------------------------------------------------- adversarial
@@ -182,6 +182,22 @@ def test_dominant_weight_and_swallowed_sites(ctx):
     for g in (1.0, 3.7, 0.25):
         for periodic in (True, False):
             check(ctx, workload(n, 2, periodic, pts, t, g, name=f"jm_swallow{g}"))
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("d", [2, 3])
+def test_dense_sites_default_tiles(ctx, kind, d):
+    """From sparse to very dense site sets: the planner picks smaller tiles as
+    the voxels per site drop; every choice must equal the oracle."""
+    from gpu_util import to_dev
+    n = (48, 40, 36) if d == 3 else (200, 150)
+    nvox = int(np.prod(n))
+    seen = set()
+    for vps in (1500, 400, 200, 60, 8):
+        w = I.make(n, kind, True, max(1, nvox // vps), 900 + vps + 7 * kind + d, growth=0.9)
+        seen.add(ctx.plan(to_dev(w))["tile_cfg"])
+        check(ctx, w)
+    assert len(seen) >= 3, seen
 
 
 @pytest.mark.parametrize("d", [2, 3])
