@@ -67,6 +67,11 @@ typedef struct {
     const double* coords;/* device, [nsites][ndim] binary64, each in [0, L_a) */
     const double* param; /* device, [nsites]: Laguerre w_s, Johnson-Mehl t_s; NULL for Voronoi */
     int32_t* labels;     /* device, prod(n) int32 written by the call (x fastest) */
+    double*  keys;       /* device, prod(n) binary64 or NULL: the winning key per voxel (the
+                          * distance image: q for Voronoi, q - w for Laguerre, t + sqrt(q)/v
+                          * for Johnson-Mehl; Sec. 3 notes the squared distance map as a
+                          * by-product), bit-identical to the key that chose the label;
+                          * NaN where the job's input is bad */
 } vt_job;
 
 /* Creates a context on HIP device `device`.  Reads a tuning cache from the

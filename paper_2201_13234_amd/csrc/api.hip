@@ -252,6 +252,7 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
     d->coords = j->coords;
     d->param = j->param;
     d->labels = j->labels;
+    d->keys = j->keys;
     return VT_OK;
 }
 

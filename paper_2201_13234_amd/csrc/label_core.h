@@ -723,6 +723,35 @@ __device__ inline void store_runs(const JobDev& J, int mi, int mj, int mk, bool 
     }
 }
 
+// The winning keys of the lane's runs (the distance image), same layout as
+// the labels; NaN for a job with bad input.
+template <int RUN, int ROWS>
+__device__ inline void store_keys(const JobDev& J, int mi, int mj, int mk, bool bad, const double* best)
+{
+    if (mk >= J.n[2] || mi >= J.n[0])
+        return;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        if (mj + r >= J.n[1])
+            break;
+        double* out = J.keys + (int64_t)mi + (int64_t)J.n[0] * ((int64_t)(mj + r) + (int64_t)J.n[1] * mk);
+        double k[RUN];
+#pragma unroll
+        for (int q = 0; q < RUN; ++q)
+            k[q] = bad ? __builtin_nan("") : best[r * RUN + q];
+        if (mi + RUN <= J.n[0] && ((uintptr_t)out & 15) == 0 && RUN % 2 == 0) {
+#pragma unroll
+            for (int q = 0; q < RUN; q += 2)
+                *(double2*)(out + q) = make_double2(k[q], k[q + 1]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < RUN; ++q)
+                if (mi + q < J.n[0])
+                    out[q] = k[q];
+        }
+    }
+}
+
 // ------------------------------------------------ fallback: one tile alone
 
 // Walks the bins around one tile shell by shell, keeps the sites that can
@@ -1308,6 +1337,8 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 for (int q = 0; q < ROWS * RUN; ++q)
                     best[q] = __builtin_inf();
                 evaluate<KIND, DIM, RUN, ROWS, true>(R.rs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
+                if (J.keys)
+                    store_keys<RUN, ROWS>(J, G.mi, G.mj, G.mk, false, best);
             }
         }
     }
@@ -1320,6 +1351,13 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             }
         } else {
             store_runs<RUN, ROWS>(J, G.mi, G.mj, G.mk, bad, lab);
+            if (bad && J.keys) {
+                double none[ROWS * RUN];
+#pragma unroll
+                for (int q = 0; q < ROWS * RUN; ++q)
+                    none[q] = 0.0;
+                store_keys<RUN, ROWS>(J, G.mi, G.mj, G.mk, true, none);
+            }
         }
     }
 }
@@ -1353,6 +1391,8 @@ __device__ void label_tile_alone(const JobDev& J, int64_t r, int w, FallbackLds&
         fallback_tile<KIND, DIM, RUN, LX, LY, LZ, ROWS>(J, C, G.t0, S, lane, xr, yv, zv, best, lab);
     }
     store_runs<RUN, ROWS>(J, G.mi, G.mj, G.mk, bad, lab);
+    if (J.keys)
+        store_keys<RUN, ROWS>(J, G.mi, G.mj, G.mk, bad, best);
 }
 
 // Consecutive regions go to one XCD: workgroups are dispatched to the eight

@@ -34,6 +34,7 @@ struct JobDev {
     const double* coords;          // [nsites][ndim], caller input
     const double* param;           // [nsites] or null
     int32_t* labels;               // caller output
+    double* keys;                  // caller output (winning key per voxel) or null
     int32_t* status;               // one word, written by the kernels
     int32_t* bin_count;            // [nbins] sites per bin (live sites after pruning)
     int32_t* bin_start;            // [nbins + 1], indexes `sites`

@@ -27,7 +27,8 @@ class VtJob(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("kind", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("L", ctypes.c_double * 3),
                 ("growth", ctypes.c_double), ("nsites", ctypes.c_int64),
-                ("coords", ctypes.c_void_p), ("param", ctypes.c_void_p), ("labels", ctypes.c_void_p)]
+                ("coords", ctypes.c_void_p), ("param", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("keys", ctypes.c_void_p)]
 
 
 class VtError(RuntimeError):
@@ -114,6 +115,7 @@ class Job:
     param: object = None      # torch float64 [nsites] or None
     growth: float = 1.0
     labels: object = None     # torch int32 with prod(n) elements, allocated if None
+    keys: object = None       # torch float64 with prod(n) elements for the distance image, or None
 
     def to_c(self):
         import torch
@@ -122,13 +124,15 @@ class Job:
             self.labels = torch.empty(tuple(reversed(self.n)), dtype=torch.int32,
                                       device=self.coords.device)
         for name, t, dt in (("coords", self.coords, torch.float64), ("param", self.param, torch.float64),
-                            ("labels", self.labels, torch.int32)):
+                            ("labels", self.labels, torch.int32), ("keys", self.keys, torch.float64)):
             if t is not None and (t.dtype != dt or not t.is_cuda or not t.is_contiguous()):
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor")
         if self.coords.dim() != 2 or self.coords.shape[1] != d:
             raise ValueError("coords must be [nsites, ndim]")
         if self.labels.numel() != int(_prod(self.n)):
             raise ValueError("labels must hold prod(n) elements")
+        if self.keys is not None and self.keys.numel() != int(_prod(self.n)):
+            raise ValueError("keys must hold prod(n) elements")
         j = VtJob()
         j.ndim = d
         j.kind = int(self.kind)
@@ -142,6 +146,7 @@ class Job:
         j.coords = self.coords.data_ptr()
         j.param = self.param.data_ptr() if self.param is not None else None
         j.labels = self.labels.data_ptr()
+        j.keys = self.keys.data_ptr() if self.keys is not None else None
         return j
 
 

@@ -43,7 +43,8 @@ def test_job_struct_matches_header_layout():
     import ctypes
     from paper_2201_13234_amd import vtess
     # 4 int32, 3 int64, 3 double, double, int64, 3 pointers
-    assert ctypes.sizeof(vtess.VtJob) == 16 + 24 + 24 + 8 + 8 + 24
+    assert ctypes.sizeof(vtess.VtJob) == 16 + 24 + 24 + 8 + 8 + 32
+    assert vtess.VtJob.keys.offset == 104
     assert vtess.VtJob.coords.offset == 80
 
 

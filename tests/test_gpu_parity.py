@@ -311,3 +311,47 @@ def test_full_size_config(ctx, name):
     print(f"[{name}] oracle run", flush=True)
     ref = run_oracle(w)
     assert np.array_equal(got, ref), describe_mismatch(got, ref)
+
+
+# ------------------------------------------------------ distance image (keys)
+
+def run_keys(ctx, w, batch=False):
+    import torch
+    from gpu_util import to_dev
+    job = to_dev(w)
+    job.keys = torch.full(tuple(reversed(w.n)), -7.0, dtype=torch.float64, device="cuda:0")
+    if batch:
+        ctx.tessellate_batch([job])
+    else:
+        ctx.tessellate(job)
+    torch.cuda.synchronize()
+    return job.labels.cpu().numpy(), job.keys.cpu().numpy()
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("periodic", [True, False])
+def test_keys_bitexact(ctx, kind, d, periodic):
+    """The winning key per voxel equals the oracle's minimum key bit for bit,
+    on the plain and the batched path and for every tile configuration."""
+    n = (40, 33, 27) if d == 3 else (150, 97)
+    w = I.make(n, kind, periodic, 350, 1234 + kind + 5 * d + int(periodic), growth=0.7)
+    p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+    lab_ref, key_ref, _ = oracle.tessellate(p, w.coords, w.param, want_keys=True)
+    for cfg in (0, 1, 2, 3):
+        ctx.set_params(cfg, 0.0)
+        try:
+            for batch in (False, True):
+                lab, key = run_keys(ctx, w, batch)
+                assert np.array_equal(lab, lab_ref), f"cfg {cfg} batch {batch}: " + describe_mismatch(lab, lab_ref)
+                assert np.array_equal(key.view(np.int64), key_ref.view(np.int64)), f"cfg {cfg} batch {batch} keys"
+        finally:
+            ctx.set_params(-1, 0.0)
+
+
+def test_keys_nan_for_bad_input(ctx):
+    w = I.make((20, 20, 20), 0, True, 50, 5)
+    w.coords = w.coords.copy()
+    w.coords[3, 1] = 20.0          # outside [0, L)
+    lab, key = run_keys(ctx, w)
+    assert np.all(lab == -1) and np.all(np.isnan(key))
