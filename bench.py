@@ -29,7 +29,9 @@ FP64_PEAK_TFLOPS = 78.6
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per
 # second (a wavefront-64 instruction occupies a SIMD for four cycles).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-LABEL_KERNEL_SRC = os.path.join(ROOT, "paper_2201_13234_amd", "csrc", "label_kernel.hip")
+# the sources of the labelling kernel (device code, launch code, shared types)
+LABEL_KERNEL_SRC = [os.path.join(ROOT, "paper_2201_13234_amd", "csrc", f)
+                    for f in ("label_core.h", "label_kernel.hip", "vt_internal.h")]
 
 
 def counters_path(workload):
@@ -38,7 +40,10 @@ def counters_path(workload):
 
 def source_digest():
     import hashlib
-    return hashlib.sha256(open(LABEL_KERNEL_SRC, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for f in LABEL_KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def load_counters(workload):
@@ -79,14 +84,14 @@ def _per_dispatch(path, counter, match):
 
 def summarize_counters(args):
     """Turns three rocprofv3 --pmc runs of `bench.py --copy-probe-mib M`
-    (the probe is the run's only two-operand elementwise kernel)
+    (the probe is torch's int32 -> float32 direct copy kernel)
     (FETCH_SIZE, WRITE_SIZE, SQ instruction counters) into the committed
     counter summary.  FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled
     by what they read for the plain copy of known size in the same run."""
     fetch_csv, write_csv, sq_csv = args.summarize
     copy_bytes = args.copy_probe_mib * 2 ** 20
     is_label = lambda k: "k_label_single" in k
-    is_copy = lambda k: "elementwise_kernel" in k and "array<char*, 2" in k
+    is_copy = lambda k: "direct_copy_kernel" in k
     lf, n_lf, names = _per_dispatch(fetch_csv, "FETCH_SIZE", is_label)
     cf, n_cf, cnames = _per_dispatch(fetch_csv, "FETCH_SIZE", is_copy)
     lw, _, _ = _per_dispatch(write_csv, "WRITE_SIZE", is_label)
@@ -97,7 +102,7 @@ def summarize_counters(args):
         "workload": args.workload_name,
         "label_kernel_sha256": source_digest(),
         "kernel": names[0],
-        "copy_probe": {"kernel": cnames[0], "bytes_read": copy_bytes, "bytes_written": copy_bytes,
+        "copy_probe": {"kernel": cnames[0][:96] + "...", "bytes_read": copy_bytes, "bytes_written": copy_bytes,
                        "fetch_kib": round(cf, 1), "write_kib": round(cw, 1),
                        "fetch_scale": round(fetch_scale, 4), "write_scale": round(write_scale, 4)},
         "label_fetch_kib": round(lf, 1),
