@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const Job
 // distance obeys too) t_r + d(x, r) / v <= t_r + d(r, s) / v + d(x, s) / v <
 // t_s + d(x, s) / v - M for every x, and M (2^-36 of the key scale) is far
 // above the rounding error of any computed key.  The paper notes that such
-// nucleation sites are ineffective (Sec. 4); dropping them from the bins leaves
+// nucleation sites are ineffective (Sec. 3.3); dropping them from the bins leaves
 // the labels unchanged and shortens every candidate list.  A swallowing site
 // lies within (t_s - min t) * v of s, so the search only visits bins that
 // close; a site whose search box exceeds kPruneMaxBins bins is kept.
