@@ -35,6 +35,18 @@ struct TileLds {
     };
 };
 
+// After pruning, tiles whose lanes all cover the same 8 x positions keep
+// their survivors as evaluation records, written over the (then dead) list
+// arrays: the squared x differences are the same for every lane, so they are
+// computed once per survivor instead of once per lane.
+constexpr int XRUN = 8;
+struct EvalRec {
+    double dx2[XRUN];  // squared x difference at the 8 x positions (wrap code applied)
+    double y, z, p;    // site y, z and parameter
+    int idx, flags;    // site index, flags (wrap codes of y and z are used)
+};
+constexpr int CAP_E = (int)(sizeof(TileLds) / sizeof(EvalRec));
+
 struct RegionLds {
     double4 rs[CAP_R];
     int ri[CAP_R];
@@ -694,6 +706,104 @@ __device__ inline void evaluate(const double4* base, const int2* cm, int nc, boo
     }
 }
 
+// Writes the evaluation records of the nc sorted list entries (cm, sites in
+// the region list `base`) for a tile whose lanes share the x positions xr.
+// The records overlay the list arrays, so every lane reads its entry first.
+template <int DIM>
+__device__ inline void write_records(TileLds& S, const double4* base, int nc, int lane, const JobDev& J,
+                                     bool periodic, const double* xr)
+{
+    int2 m = make_int2(0, 0);
+    double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (lane < nc) {
+        m = S.cm[lane];
+        s = base[m.y >> 8];
+    }
+    const int fl = m.y & 0xff;
+    double d2[XRUN];
+    if (!(fl & FL_GENERIC)) {
+        const double ox = code_off(fl & 3, J.L[0]);
+#pragma unroll
+        for (int q = 0; q < XRUN; ++q) {
+            const double dx = fl == 0 ? s.x - xr[q] : (s.x - xr[q]) + ox;
+            d2[q] = dx * dx;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < XRUN; ++q) {
+            const double dx = periodic ? min_image(s.x - xr[q], J.H[0], J.L[0]) : s.x - xr[q];
+            d2[q] = dx * dx;
+        }
+    }
+    wave_sync();
+    if (lane < nc) {
+        EvalRec* R = reinterpret_cast<EvalRec*>(&S);
+        EvalRec& E = R[lane];
+#pragma unroll
+        for (int q = 0; q < XRUN; ++q)
+            E.dx2[q] = d2[q];
+        E.y = s.y;
+        E.z = s.z;
+        E.p = s.w;
+        E.idx = m.x;
+        E.flags = fl;
+    }
+    wave_sync();
+}
+
+// evaluate() over evaluation records: the x terms come from LDS.
+template <int KIND, int DIM, int ROWS>
+__device__ inline void evaluate_rec(const TileLds& S, int nc, const JobDev& J, const JobConst& C, bool periodic,
+                                    const double* yv, double zv, double* best, int* lab)
+{
+    const EvalRec* R = reinterpret_cast<const EvalRec*>(&S);
+    for (int k = 0; k < nc; ++k) {
+        const EvalRec& E = R[k];
+        const int idx = __builtin_amdgcn_readfirstlane(E.idx), fl = __builtin_amdgcn_readfirstlane(E.flags);
+        double dx2[XRUN];
+#pragma unroll
+        for (int q = 0; q < XRUN; ++q)
+            dx2[q] = E.dx2[q];
+        const double sy = E.y, sz = E.z, sp = E.p;
+        double c[ROWS];
+        if ((fl & (FL_GENERIC | 0x3c)) == 0) {  // no wrap in y and z
+            const double dz = (DIM == 3) ? sz - zv : 0.0;
+            const double dz2 = dz * dz;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double dy = sy - yv[r];
+                c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
+            }
+        } else if (!(fl & FL_GENERIC)) {
+            const double dz = (DIM == 3) ? (sz - zv) + code_off((fl >> 4) & 3, J.L[2]) : 0.0;
+            const double dz2 = dz * dz;
+            const double oy = code_off((fl >> 2) & 3, J.L[1]);
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double dy = (sy - yv[r]) + oy;
+                c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
+            }
+        } else {
+            const double dz = (DIM == 3) ? (periodic ? min_image(sz - zv, J.H[2], J.L[2]) : sz - zv) : 0.0;
+            const double dz2 = dz * dz;
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const double dy = periodic ? min_image(sy - yv[r], J.H[1], J.L[1]) : sy - yv[r];
+                c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+            for (int q = 0; q < XRUN; ++q) {
+                const double key = dist_key<KIND>(dx2[q] + c[r], sp, C.v, C.rv);
+                lab[r * XRUN + q] = key < best[r * XRUN + q] ? idx : lab[r * XRUN + q];
+                best[r * XRUN + q] = fmin(best[r * XRUN + q], key);
+            }
+        }
+    }
+}
+
 template <int RUN, int ROWS>
 __device__ inline void store_runs(const JobDev& J, int mi, int mj, int mk, bool bad, int* lab)
 {
@@ -1336,7 +1446,12 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
 #pragma unroll
                 for (int q = 0; q < ROWS * RUN; ++q)
                     best[q] = __builtin_inf();
-                evaluate<KIND, DIM, RUN, ROWS, true>(R.rs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
+                if (RUN == XRUN && LX == 1 && nc <= CAP_E) {
+                    write_records<DIM>(S, R.rs, nc, lane, J, periodic, xr);
+                    evaluate_rec<KIND, DIM, ROWS>(S, nc, J, C, periodic, yv, zv, best, lab);
+                } else {
+                    evaluate<KIND, DIM, RUN, ROWS, true>(R.rs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);
+                }
                 if (J.keys)
                     store_keys<RUN, ROWS>(J, G.mi, G.mj, G.mk, false, best);
             }
