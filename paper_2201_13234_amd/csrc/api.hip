@@ -130,11 +130,13 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
     int cfg;
     double bf = 1.0;
     if (j->ndim == 3) {
-        cfg = vps >= 729.0 ? 0 : (vps >= 216.0 ? 1 : (vps >= 91.0 ? 2 : 3));
+        cfg = vps >= 1100.0 ? 0 : (vps >= 216.0 ? 1 : (vps >= 91.0 ? 2 : 3));
         if (j->kind == VT_VORONOI) {
             bf = 1.4;
         } else if (j->kind == VT_LAGUERRE) {
-            bf = 2.0;
+            // large bins only where sites are sparse: denser jobs would gather
+            // many more sites than their tiles need
+            bf = vps >= 2000.0 ? 2.0 : 1.2;
         } else {
             cfg = cfg == 0 ? 1 : cfg;
             bf = 1.2;

@@ -280,8 +280,15 @@ __device__ inline void box_bounds(const JobDev& J, const JobConst& C, const Tile
             }
         }
         if (gen) {
+            // The wrap flips inside the box: it contains the point half a
+            // period from the site, where the periodic distance peaks at
+            // L/2, so over the box the distance is smallest at an end (unless
+            // the box spans half a period itself).
             flags |= FL_GENERIC;
             dmin = 0.0;
+            if (B.hi[a] - B.lo[a] < J.H[a])
+                dmin = fmin(fabs(min_image(sc[a] - B.lo[a], J.H[a], J.L[a])),
+                            fabs(min_image(sc[a] - B.hi[a], J.H[a], J.L[a])));
             dmax = J.H[a];
         } else {
             dmin = fmax(0.0, fmax(B.lo[a] - sg, sg - B.hi[a]));

@@ -200,6 +200,17 @@ def test_dense_sites_default_tiles(ctx, kind, d):
     assert len(seen) >= 3, seen
 
 
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_thin_periodic_axis(ctx, kind):
+    """A periodic axis shorter than the gather box: sites whose wrap flips
+    inside a tile take the generic bounds."""
+    for n in ((96, 40, 70), (30, 90, 50), (64, 64, 22)):
+        nvox = int(np.prod(n))
+        w = I.make(n, kind, True, max(2, nvox // 900), 4321 + kind + n[2], growth=1.3)
+        check(ctx, w)
+        check(ctx, w, cfgs=[(0, 2.0), (1, 0.5)])
+
+
 @pytest.mark.parametrize("d", [2, 3])
 def test_jm_ineffective_sites(ctx, d):
     """Johnson-Mehl sites that a neighbour's grain reaches before they
