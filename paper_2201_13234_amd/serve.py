@@ -303,16 +303,20 @@ class Server:
 
     mem_budget: bytes of device memory the in-flight requests may hold;
     max_slots: requests in flight at once; max_batch: requests per labelling
-    launch.  A request larger than the whole budget is rejected (status -2)
-    without blocking the others.
+    launch; batch_voxels: a launch takes ready requests in arrival order until
+    their voxels would exceed this (a larger request goes alone), so that a
+    burst of arrivals drains as a sequence of short launches rather than one
+    long one that every request in it has to wait for.  A request larger than
+    the whole budget is rejected (status -2) without blocking the others.
     """
 
-    def __init__(self, executor, mem_budget=8 << 30, max_slots=64, max_batch=64,
+    def __init__(self, executor, mem_budget=8 << 30, max_slots=64, max_batch=64, batch_voxels=24 << 20,
                  clock=time.perf_counter, sleep=time.sleep):
         self.ex = executor
         self.mem_budget = int(mem_budget)
         self.max_slots = int(max_slots)
         self.max_batch = int(max_batch)
+        self.batch_voxels = int(batch_voxels)
         self.clock = clock
         self.sleep = sleep
         self.mem_in_use = 0
@@ -390,7 +394,11 @@ class Server:
             running = keep
             # launch what is ready while a lane is free
             if ready and len(running) < self.ex.max_inflight:
-                batch, ready = ready[: self.max_batch], ready[self.max_batch:]
+                k, vox = 0, 0
+                while k < len(ready) and k < self.max_batch and (k == 0 or vox + ready[k].nvox <= self.batch_voxels):
+                    vox += ready[k].nvox
+                    k += 1
+                batch, ready = ready[:k], ready[k:]
                 running.append((self.ex.start_labelling(batch), batch))
                 self.batches.append(len(batch))
                 progressed = True
@@ -443,13 +451,15 @@ def make_stream(n_jobs, rate, side_scale=0.25, first_job=0):
             for i in range(n_jobs)]
 
 
-def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, lanes=2, calib_jobs=100,
-              max_batch=64, log=None):
+def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, lanes=2, calib_jobs=0,
+              max_batch=64, extra_loads=(0.95,), log=None):
     """Replays a request stream twice on the GPU -- continuous batching and one
     by one -- with the same arrival times.  The arrival rate is `load` times
-    the one-by-one service rate, measured on the first `calib_jobs` jobs run
-    back to back.  Returns p50/p99 latency and throughput of both modes, and
-    whether every job's labels (device checksums) are the same in both."""
+    the one-by-one service rate, measured on all jobs (or the first
+    `calib_jobs`) run back to back.  Returns p50/p99 latency and throughput of both modes, and
+    whether every job's labels (device checksums) are the same in both.  Each
+    of `extra_loads` repeats the comparison at that load (reported under
+    "other_loads")."""
     say = log or (lambda msg: None)
     ex = GpuExecutor(ctx, lanes=lanes, max_batch=max(max_batch, 1))
     say(f"generating {n_jobs} jobs")
@@ -459,26 +469,35 @@ def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, l
     Server(ex, mem_budget=mem_budget).run_one_by_one(copy(jobs[:16], 0.0))
     Server(ex, mem_budget=mem_budget, max_batch=max_batch).run(copy(jobs[:16], 0.0))
     ex.collect_digests()
-    cal = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(jobs[:calib_jobs], 0.0))
+    # every job once, back to back: the one-by-one service rate, and warm
+    # device allocations for every label size before either measured replay
+    cal = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(jobs[:calib_jobs] if calib_jobs else jobs, 0.0))
     ex.collect_digests()
     service = max(r.done for r in cal) / len(cal)
-    rate = load / service
     from . import inputs
-    t = inputs.arrivals(n_jobs, rate)
-    stream = [Request(r.rid, r.workload, float(t[k])) for k, r in enumerate(jobs)]
-    say(f"batched replay at {rate:.1f} jobs/s")
-    srv = Server(ex, mem_budget=mem_budget, max_batch=max_batch)
-    batched = srv.run(copy(stream))
-    db = ex.collect_digests()
-    say("one-by-one replay")
-    alone = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(stream))
-    da = ex.collect_digests()
-    same = all(a.status == b.status and db.get(a.rid) == da.get(b.rid) for a, b in zip(batched, alone))
-    nvox = [r.nvox for r in stream]
-    return {"jobs": n_jobs, "side_scale": side_scale, "load": load, "rate_per_s": round(rate, 2),
-            "service_ms_alone": round(service * 1e3, 3), "lanes": lanes, "max_batch": max_batch,
-            "voxels_total": int(sum(nvox)), "voxels_p50": int(np.percentile(nvox, 50)),
-            "batched": summarize(batched), "one_by_one": summarize(alone),
-            "mean_batch": round(float(np.mean(srv.batches)), 2) if srv.batches else 0,
-            "peak_mem_gb": round(srv.peak_mem / 2 ** 30, 2),
-            "labels_identical": bool(same), "checked_jobs": len(db)}
+
+    def replay(ld):
+        rate = ld / service
+        t = inputs.arrivals(n_jobs, rate)
+        stream = [Request(r.rid, r.workload, float(t[k])) for k, r in enumerate(jobs)]
+        say(f"load {ld}: batched replay at {rate:.1f} jobs/s")
+        srv = Server(ex, mem_budget=mem_budget, max_batch=max_batch)
+        batched = srv.run(copy(stream))
+        db = ex.collect_digests()
+        say(f"load {ld}: one-by-one replay")
+        alone = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(stream))
+        da = ex.collect_digests()
+        same = all(a.status == b.status and db.get(a.rid) == da.get(b.rid) for a, b in zip(batched, alone))
+        return {"load": ld, "rate_per_s": round(rate, 2), "batched": summarize(batched),
+                "one_by_one": summarize(alone),
+                "mean_batch": round(float(np.mean(srv.batches)), 2) if srv.batches else 0,
+                "peak_mem_gb": round(srv.peak_mem / 2 ** 30, 2),
+                "labels_identical": bool(same), "checked_jobs": len(db)}
+
+    out = replay(load)
+    nvox = [r.nvox for r in jobs]
+    out.update({"jobs": n_jobs, "side_scale": side_scale, "service_ms_alone": round(service * 1e3, 3),
+                "lanes": lanes, "max_batch": max_batch, "voxels_total": int(sum(nvox)),
+                "voxels_p50": int(np.percentile(nvox, 50))})
+    out["other_loads"] = [replay(ld) for ld in extra_loads]
+    return out

@@ -144,3 +144,28 @@ def test_digest_host_matches_definition():
     P = 2147483647
     want = sum((int(v) + 3) * ((i * 48271 + 97) % P) for i, v in enumerate(lab.reshape(-1))) % P
     assert S.digest_host(lab) == want
+
+
+def test_batches_capped_by_voxels():
+    """A burst is cut into launches of at most batch_voxels (in arrival
+    order); a request larger than the cap goes alone."""
+    clock = SimClock()
+    reqs = small_stream(30, rate=1e9, seed=7)       # everything arrives at once
+    big = S.Request(rid=99, workload=I.make((60, 60, 60), 0, True, 20, seed=5), arrival=0.0)
+    cap = 4000
+    srv = S.Server(FakeExecutor(clock), max_batch=64, batch_voxels=cap, clock=clock, sleep=clock.sleep)
+    launched = []
+    orig = srv.ex.start_labelling
+
+    def spy(batch):
+        launched.append([r.rid for r in batch])
+        return orig(batch)
+    srv.ex.start_labelling = spy
+    done = srv.run(copy(reqs) + [big])
+    assert all(r.status == 0 for r in done)
+    sizes = {r.rid: r.nvox for r in reqs + [big]}
+    for b in launched:
+        assert len(b) == 1 or sum(sizes[i] for i in b) <= cap
+    assert [99] in launched
+    order = [i for b in launched for i in b]
+    assert sorted(order) == sorted(sizes)
