@@ -376,7 +376,7 @@ __global__ void k_probe(const double* x, const double* den, double* so, double* 
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) {
-        so[i] = sqrt(x[i]);
+        so[i] = vt::key_sqrt(x[i]);  // the square root the Johnson-Mehl keys use
         dq[i] = x[i] / den[i];
     }
 }

@@ -20,6 +20,9 @@ constexpr int R_DOM = 8;       // dominance references: the candidates with the 
 // flags: wrap code per axis in bits 2a..2a+1 (0 none, 1 subtract L, 2 add L),
 // bit 6 = some axis needs a per-voxel minimum-image test.
 constexpr int FL_GENERIC = 64;
+// Evaluation records: every squared distance of the site to the tile's voxel
+// centres is at least 2^-500, so the Johnson-Mehl keys may use sqrt_refined.
+constexpr int FL_SQRT_FAST = 256;
 
 enum { KV = 0, KL = 1, KJM = 2, KJD = 3 };  // Johnson-Mehl: multiply by exact 1/v, or divide
 
@@ -201,6 +204,15 @@ __device__ inline double block_max(double v, double* wred, int tid)
         r = fmax(r, wred[k]);
     __syncthreads();
     return r;
+}
+
+// dist_key with sqrt_refined (for q >= 2^-500 only).
+template <int KIND>
+__device__ inline double dist_key_fast(double q, double p, double v, double rv)
+{
+    if (KIND == KJM)
+        return p + sqrt_refined(q) * rv;
+    return p + sqrt_refined(q) / v;
 }
 
 template <int KIND>
@@ -716,7 +728,7 @@ __device__ inline void evaluate(const double4* base, const int2* cm, int nc, boo
 // Writes the evaluation records of the nc sorted list entries (cm, sites in
 // the region list `base`) for a tile whose lanes share the x positions xr.
 // The records overlay the list arrays, so every lane reads its entry first.
-template <int DIM>
+template <int KIND, int DIM>
 __device__ inline void write_records(TileLds& S, const double4* base, int nc, int lane, const JobDev& J,
                                      bool periodic, const double* xr)
 {
@@ -726,7 +738,23 @@ __device__ inline void write_records(TileLds& S, const double4* base, int nc, in
         m = S.cm[lane];
         s = base[m.y >> 8];
     }
-    const int fl = m.y & 0xff;
+    int fl = m.y & 0xff;
+    if (KIND == KJM || KIND == KJD) {
+        // A site off the lattice of voxel centres by at least 2^-24 of a
+        // voxel on some axis is that far from every voxel centre (images
+        // shift by whole periods); with n < 2^20 the lattice coordinate's
+        // rounding error stays below 2^-32.
+        const double sc[3] = {s.x, s.y, s.z};
+        bool off = false, ok = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const double u = sc[a] / J.h[a] - 0.5;
+            off = off || fabs(u - rint(u)) > 0x1p-24;
+            ok = ok && J.n[a] < (1 << 20) && J.h[a] > 0x1p-200;
+        }
+        if (off && ok)
+            fl |= FL_SQRT_FAST;
+    }
     double d2[XRUN];
     if (!(fl & FL_GENERIC)) {
         const double ox = code_off(fl & 3, J.L[0]);
@@ -799,13 +827,25 @@ __device__ inline void evaluate_rec(const TileLds& S, int nc, const JobDev& J, c
                 c[r] = (DIM == 3) ? dy * dy + dz2 : dy * dy;
             }
         }
+        if ((KIND == KJM || KIND == KJD) && (fl & FL_SQRT_FAST)) {
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
+            for (int r = 0; r < ROWS; ++r) {
 #pragma unroll
-            for (int q = 0; q < XRUN; ++q) {
-                const double key = dist_key<KIND>(dx2[q] + c[r], sp, C.v, C.rv);
-                lab[r * XRUN + q] = key < best[r * XRUN + q] ? idx : lab[r * XRUN + q];
-                best[r * XRUN + q] = fmin(best[r * XRUN + q], key);
+                for (int q = 0; q < XRUN; ++q) {
+                    const double key = dist_key_fast<KIND>(dx2[q] + c[r], sp, C.v, C.rv);
+                    lab[r * XRUN + q] = key < best[r * XRUN + q] ? idx : lab[r * XRUN + q];
+                    best[r * XRUN + q] = fmin(best[r * XRUN + q], key);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+                for (int q = 0; q < XRUN; ++q) {
+                    const double key = dist_key<KIND>(dx2[q] + c[r], sp, C.v, C.rv);
+                    lab[r * XRUN + q] = key < best[r * XRUN + q] ? idx : lab[r * XRUN + q];
+                    best[r * XRUN + q] = fmin(best[r * XRUN + q], key);
+                }
             }
         }
     }
@@ -1454,7 +1494,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 for (int q = 0; q < ROWS * RUN; ++q)
                     best[q] = __builtin_inf();
                 if (RUN == XRUN && LX == 1 && nc <= CAP_E) {
-                    write_records<DIM>(S, R.rs, nc, lane, J, periodic, xr);
+                    write_records<KIND, DIM>(S, R.rs, nc, lane, J, periodic, xr);
                     evaluate_rec<KIND, DIM, ROWS>(S, nc, J, C, periodic, yv, zv, best, lab);
                 } else {
                     evaluate<KIND, DIM, RUN, ROWS, true>(R.rs, S.cm, nc, false, J, C, periodic, xr, yv, zv, best, lab);

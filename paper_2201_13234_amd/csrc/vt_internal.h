@@ -68,6 +68,31 @@ constexpr TileShape kShape2[kNumCfg] = {{8, 4, 16, 1, 2, 2, 2, 1}, {8, 4, 16, 1,
 
 inline TileShape shape_of(int ndim, int cfg) { return ndim == 3 ? kShape3[cfg] : kShape2[cfg]; }
 
+// Square root with IEEE rounding, for q >= 2^-500: the hardware reciprocal
+// square root refined by the same fused multiply-add steps as the compiler's
+// correctly rounded sqrt, without its rescaling of tiny inputs and its
+// fix-up for zero and infinity (neither is reachable above 2^-500), so the
+// result is the same bit for bit.
+__device__ inline double sqrt_refined(double q)
+{
+    const double y = __builtin_amdgcn_rsq(q);
+    double g = q * y;
+    double h = y * 0.5;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, q);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, q);
+    return __builtin_fma(d, h, g);
+}
+
+// sqrt(q) for q >= 0, IEEE rounded, through sqrt_refined where it applies.
+__device__ inline double key_sqrt(double q)
+{
+    return q >= 0x1p-500 ? sqrt_refined(q) : sqrt(q);
+}
+
 // ---- launchers (defined in the .hip files) ----
 // Binning over one job (jobs_dev == nullptr, `single` used) or over njobs jobs
 // whose sites are enumerated by site_prefix_dev ([njobs + 1], device).

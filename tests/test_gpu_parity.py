@@ -299,6 +299,11 @@ def test_numerics_probe_is_ieee(ctx):
     rng = np.random.default_rng(15)
     x = np.concatenate([rng.uniform(0, 1e6, 400_000), rng.uniform(0, 4, 400_000),
                         np.exp(rng.uniform(-700, 700, 200_000)),
+                        # random bit patterns of positive finite doubles
+                        (rng.integers(1, 0x7FF0000000000000, 200_000, dtype=np.int64)).view(np.float64),
+                        # both sides of the switch to the short square root at 2^-500
+                        np.nextafter(2.0 ** -500, np.inf) * rng.uniform(0.5, 2.0, 1000),
+                        np.array([2.0 ** -500, np.nextafter(2.0 ** -500, 0), np.nextafter(2.0 ** -500, np.inf)]),
                         np.array([0.0, 1.0, 2.0, 4.0, 0.25, 5e-324, 2.2250738585072014e-308,
                                   1.7976931348623157e308, 3.0, 1e-300])])
     den = np.concatenate([rng.uniform(0.1, 10, x.size - 10), np.array([1.0, 3.0, 0.7, 1.3, 7.0, 1.0,
@@ -349,6 +354,41 @@ def test_keys_bitexact(ctx, kind, d, periodic):
     w = I.make(n, kind, periodic, 350, 1234 + kind + 5 * d + int(periodic), growth=0.7)
     p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
     lab_ref, key_ref, _ = oracle.tessellate(p, w.coords, w.param, want_keys=True)
+    for cfg in (0, 1, 2, 3):
+        ctx.set_params(cfg, 0.0)
+        try:
+            for batch in (False, True):
+                lab, key = run_keys(ctx, w, batch)
+                assert np.array_equal(lab, lab_ref), f"cfg {cfg} batch {batch}: " + describe_mismatch(lab, lab_ref)
+                assert np.array_equal(key.view(np.int64), key_ref.view(np.int64)), f"cfg {cfg} batch {batch} keys"
+        finally:
+            ctx.set_params(-1, 0.0)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_jm_keys_sites_on_voxel_centres(ctx, d):
+    """Johnson-Mehl keys at zero and tiny distances: sites exactly on voxel
+    centres (sqrt(0)), a hair off them, and at ordinary positions, on a grid
+    whose voxel size is not a power of two.  Keys and labels equal the
+    oracle's bit for bit on every tile configuration."""
+    rng = np.random.default_rng(77 + d)
+    n = (36, 29, 23) if d == 3 else (130, 91)
+    L = tuple(0.37 * v for v in n)
+    h = np.array(L) / np.array(n)
+    ns = 300
+    idx = np.stack([rng.integers(0, v, ns) for v in n], axis=1)
+    coords = (idx + 0.5) * h
+    off = np.array([0.0, 2.0 ** -30, 2.0 ** -24, 1.5 * 2.0 ** -24, 1e-6, 1e-3, 0.3])
+    pick = np.where(rng.random((ns, d)) < 0.5, 0, rng.integers(1, off.size, (ns, d)))
+    coords = coords + off[pick] * h * rng.choice([-1.0, 1.0], (ns, d))
+    coords = np.mod(coords, np.array(L))
+    coords = np.where(coords >= np.array(L), 0.0, coords)
+    t = rng.uniform(0.0, 2.0 * float(np.prod(L) / ns) ** (1 / d), ns)
+    w = I.Workload(name=f"jm_on_centres_{d}d", n=n, L=L, kind=2, periodic=True, coords=coords,
+                   param=t, growth=0.9, meta={})
+    p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+    lab_ref, key_ref, _ = oracle.tessellate(p, w.coords, w.param, want_keys=True)
+    assert np.any(key_ref == t[lab_ref])       # some voxels do sit on their site
     for cfg in (0, 1, 2, 3):
         ctx.set_params(cfg, 0.0)
         try:
