@@ -16,12 +16,13 @@ from .build import LIB
 
 VORONOI, LAGUERRE, JOHNSON_MEHL = 0, 1, 2
 OK, ERR_INVALID, ERR_NOMEM, ERR_INPUT = 0, 1, 2, 5
+MAX_DIM = 6
 
 
 class Problem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("kind", ctypes.c_int32),
                 ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("n", ctypes.c_int64 * 3), ("L", ctypes.c_double * 3),
+                ("n", ctypes.c_int64 * MAX_DIM), ("L", ctypes.c_double * MAX_DIM),
                 ("growth", ctypes.c_double)]
 
 
@@ -61,16 +62,16 @@ def lib():
 
 
 def problem(n, L, kind=VORONOI, periodic=True, growth=1.0):
-    """Problem statement: n voxels and lengths L per axis (2 or 3 entries)."""
+    """Problem statement: n voxels and lengths L per axis (1 to 6 entries)."""
     n = list(n)
     L = list(L)
-    if len(n) != len(L) or len(n) not in (2, 3):
-        raise ValueError("n and L must both have 2 or 3 entries")
+    if len(n) != len(L) or not 1 <= len(n) <= MAX_DIM:
+        raise ValueError(f"n and L must both have 1 to {MAX_DIM} entries")
     p = Problem()
     p.ndim = len(n)
     p.kind = int(kind)
     p.periodic = 1 if periodic else 0
-    for a in range(3):
+    for a in range(MAX_DIM):
         p.n[a] = int(n[a]) if a < len(n) else 1
         p.L[a] = float(L[a]) if a < len(L) else 1.0
     p.growth = float(growth)
@@ -156,10 +157,10 @@ def brute(p, coords, param=None, nthreads=0, want_keys=False):
 
 
 def label_points(p, coords, param, vox, nthreads=0):
-    """Brute force at voxel indices vox [npts, ndim or 3]; returns (labels, keys)."""
+    """Brute force at voxel indices vox [npts, ndim]; returns (labels, keys)."""
     coords, param = _prep(p, coords, param)
     vox = np.asarray(vox, dtype=np.int64)
-    v3 = np.zeros((vox.shape[0], 3), dtype=np.int64)
+    v3 = np.zeros((vox.shape[0], MAX_DIM), dtype=np.int64)
     v3[:, :vox.shape[1]] = vox
     labels = np.empty(vox.shape[0], dtype=np.int32)
     keys = np.empty(vox.shape[0], dtype=np.float64)

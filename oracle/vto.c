@@ -30,13 +30,15 @@
 /* Geometry shared by every routine of this file                             */
 /* ------------------------------------------------------------------------ */
 
+#define MAXD VTO_MAX_DIM
+
 typedef struct {
     int ndim, kind, periodic;
-    int64_t n[3];
-    double L[3];
-    double h[3];  /* voxel size L_a / n_a */
-    double H[3];  /* half period L_a / 2 */
-    double G;     /* Johnson-Mehl growth rate */
+    int64_t n[MAXD];
+    double L[MAXD];
+    double h[MAXD];  /* voxel size L_a / n_a */
+    double H[MAXD];  /* half period L_a / 2 */
+    double G;        /* Johnson-Mehl growth rate */
     int64_t nvox;
 } geo_t;
 
@@ -49,7 +51,7 @@ static void geo_init(geo_t* g, const vto_problem* p)
     g->periodic = p->periodic ? 1 : 0;
     g->G = p->growth;
     g->nvox = 1;
-    for (a = 0; a < 3; ++a) {
+    for (a = 0; a < MAXD; ++a) {
         if (a < p->ndim) {
             g->n[a] = p->n[a];
             g->L[a] = p->L[a];
@@ -89,8 +91,49 @@ static double axis_delta(const geo_t* g, int a, double s, double x)
     return d;
 }
 
+/* A periodic site coordinate brought into the unit cell [0, L): the
+ * L-periodic distance of App. A (eq. L-distance_def) does not change when a
+ * point moves by a whole period.  fmod is exact; the one rounding is r + L
+ * for r < 0, and a sum that rounds up to L is the point 0 of the next
+ * period. */
+static double cell_coord(double c, double L)
+{
+    double r = fmod(c, L);
+    if (r < 0.0) {
+        r = r + L;
+        if (r >= L)
+            r = 0.0;
+    }
+    return r + 0.0; /* -0.0 -> +0.0 */
+}
+
+/* The sites the routines below work on: the caller's array, or for periodic
+ * boundaries a copy with every coordinate brought into the unit cell.
+ * Returns NULL when the copy cannot be allocated; release with
+ * release_sites. */
+static const double* prepare_sites(const geo_t* g, int64_t nsites, const double* coords)
+{
+    double* c;
+    int64_t i;
+    if (!g->periodic)
+        return coords;
+    c = (double*)malloc((size_t)nsites * (size_t)g->ndim * sizeof(double));
+    if (!c)
+        return NULL;
+    for (i = 0; i < nsites * g->ndim; ++i)
+        c[i] = cell_coord(coords[i], g->L[i % g->ndim]);
+    return c;
+}
+
+static void release_sites(const double* sites, const double* coords)
+{
+    if (sites != coords)
+        free((void*)sites);
+}
+
 /* The key the diagram minimises at point x for site s (Sec. 2):
- *   squared distance q = d0^2 + (d1^2 + d2^2)    (eq. de / eq. dL, squared)
+ *   squared distance q = d0^2 + T, T = d1^2 then T + d2^2, ... (eq. de /
+ *                    eq. dL, squared; in 3D q = d0^2 + (d1^2 + d2^2))
  *   Voronoi:      q                              (eq. Voronoi_Cell; the
  *                                                 squared distance is allowed
  *                                                 by the remark of Sec. 3.1)
@@ -100,12 +143,17 @@ static double site_key(const geo_t* g, const double* s, double prm, const double
 {
     double q;
     double d0 = axis_delta(g, 0, s[0], x[0]);
-    double d1 = axis_delta(g, 1, s[1], x[1]);
-    if (g->ndim == 3) {
-        double d2 = axis_delta(g, 2, s[2], x[2]);
-        q = d0 * d0 + (d1 * d1 + d2 * d2);
+    if (g->ndim == 1) {
+        q = d0 * d0;
     } else {
-        q = d0 * d0 + d1 * d1;
+        double d1 = axis_delta(g, 1, s[1], x[1]);
+        double T = d1 * d1;
+        int a;
+        for (a = 2; a < g->ndim; ++a) {
+            double da = axis_delta(g, a, s[a], x[a]);
+            T = T + da * da;
+        }
+        q = d0 * d0 + T;
     }
     if (g->kind == VTO_LAGUERRE)
         return q - prm;
@@ -136,7 +184,7 @@ int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
 {
     int a;
     int64_t s;
-    if (!p || (p->ndim != 2 && p->ndim != 3))
+    if (!p || p->ndim < 1 || p->ndim > MAXD)
         return VTO_ERR_INVALID;
     if (p->kind < VTO_VORONOI || p->kind > VTO_JOHNSON_MEHL)
         return VTO_ERR_INVALID;
@@ -155,7 +203,7 @@ int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
     for (s = 0; s < nsites; ++s) {
         for (a = 0; a < p->ndim; ++a) {
             double c = coords[s * p->ndim + a];
-            if (!(c >= 0.0 && c < p->L[a]))
+            if (p->periodic ? !isfinite(c) : !(c >= 0.0 && c < p->L[a]))
                 return VTO_ERR_INPUT;
         }
         if (p->kind != VTO_VORONOI && !isfinite(param[s]))
@@ -341,13 +389,11 @@ static void brute_voxel(const geo_t* g, int64_t nsites, const double* coords,
 
 static void voxel_point(const geo_t* g, int64_t lin, double* x)
 {
-    int64_t i0 = lin % g->n[0];
-    int64_t r = lin / g->n[0];
-    int64_t i1 = r % g->n[1];
-    int64_t i2 = r / g->n[1];
-    x[0] = voxel_centre(g, 0, i0);
-    x[1] = voxel_centre(g, 1, i1);
-    x[2] = (g->ndim == 3) ? voxel_centre(g, 2, i2) : 0.0;
+    int a;
+    for (a = 0; a < g->ndim; ++a) {
+        x[a] = voxel_centre(g, a, lin % g->n[a]);
+        lin /= g->n[a];
+    }
 }
 
 int vto_brute(const vto_problem* p, int64_t nsites, const double* coords,
@@ -355,23 +401,28 @@ int vto_brute(const vto_problem* p, int64_t nsites, const double* coords,
 {
     geo_t g;
     int64_t v;
+    const double* sites;
     int rc = vto_validate(p, nsites, coords, param);
     if (rc != VTO_OK)
         return rc;
     if (!labels)
         return VTO_ERR_INVALID;
     geo_init(&g, p);
+    sites = prepare_sites(&g, nsites, coords);
+    if (!sites)
+        return VTO_ERR_NOMEM;
     nthreads = resolve_threads(nthreads);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (v = 0; v < g.nvox; ++v) {
-        double x[3], k;
+        double x[MAXD], k;
         int32_t l;
         voxel_point(&g, v, x);
-        brute_voxel(&g, nsites, coords, param, x, &l, &k);
+        brute_voxel(&g, nsites, sites, param, x, &l, &k);
         labels[v] = l;
         if (keys_out)
             keys_out[v] = k;
     }
+    release_sites(sites, coords);
     return VTO_OK;
 }
 
@@ -381,6 +432,7 @@ int vto_label_points(const vto_problem* p, int64_t nsites, const double* coords,
 {
     geo_t g;
     int64_t i;
+    const double* sites;
     int rc = vto_validate(p, nsites, coords, param);
     if (rc != VTO_OK)
         return rc;
@@ -390,22 +442,26 @@ int vto_label_points(const vto_problem* p, int64_t nsites, const double* coords,
     for (i = 0; i < npts; ++i) {
         int a;
         for (a = 0; a < p->ndim; ++a)
-            if (vox[3 * i + a] < 0 || vox[3 * i + a] >= g.n[a])
+            if (vox[MAXD * i + a] < 0 || vox[MAXD * i + a] >= g.n[a])
                 return VTO_ERR_INVALID;
     }
+    sites = prepare_sites(&g, nsites, coords);
+    if (!sites)
+        return VTO_ERR_NOMEM;
     nthreads = resolve_threads(nthreads);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (i = 0; i < npts; ++i) {
-        double x[3], k;
+        double x[MAXD], k;
         int32_t l;
-        x[0] = voxel_centre(&g, 0, vox[3 * i + 0]);
-        x[1] = voxel_centre(&g, 1, vox[3 * i + 1]);
-        x[2] = (g.ndim == 3) ? voxel_centre(&g, 2, vox[3 * i + 2]) : 0.0;
-        brute_voxel(&g, nsites, coords, param, x, &l, &k);
+        int a;
+        for (a = 0; a < g.ndim; ++a)
+            x[a] = voxel_centre(&g, a, vox[MAXD * i + a]);
+        brute_voxel(&g, nsites, sites, param, x, &l, &k);
         labels[i] = l;
         if (keys_out)
             keys_out[i] = k;
     }
+    release_sites(sites, coords);
     return VTO_OK;
 }
 
@@ -421,10 +477,6 @@ int vto_label_points(const vto_problem* p, int64_t nsites, const double* coords,
 static int64_t axis_box(const geo_t* g, int a, double s, double R, int64_t* out)
 {
     int64_t n = g->n[a], lo, hi, i, cnt = 0;
-    if (a >= g->ndim) {
-        out[0] = 0;
-        return 1;
-    }
     if (!(R < 2.0 * g->L[a])) {
         for (i = 0; i < n; ++i)
             out[i] = i;
@@ -457,8 +509,9 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
 {
     geo_t g;
     double* D;
-    int64_t n_step1 = 0, n_box = 0, n_out = 0;
-    int outer, rc, failed = 0;
+    const double* sites;
+    int64_t n_step1 = 0, n_box = 0, n_out = 0, nidx = 0;
+    int outer, rc, failed = 0, a;
     rc = vto_validate(p, nsites, coords, param);
     if (rc != VTO_OK)
         return rc;
@@ -467,33 +520,40 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
     geo_init(&g, p);
     outer = g.ndim - 1; /* threads own slabs along the slowest axis */
     nthreads = resolve_threads(nthreads);
+    for (a = 0; a < g.ndim; ++a)
+        nidx += g.n[a];
 
     /* Initialisation: the level tau (eq. v0_3d or the t0 search), D = inf. */
     if (isnan(tau))
         tau = vto_choose_tau(p, nsites, param);
-    D = keys_out ? keys_out : (double*)malloc((size_t)g.nvox * sizeof(double));
-    if (!D)
+    sites = prepare_sites(&g, nsites, coords);
+    if (!sites)
         return VTO_ERR_NOMEM;
+    D = keys_out ? keys_out : (double*)malloc((size_t)g.nvox * sizeof(double));
+    if (!D) {
+        release_sites(sites, coords);
+        return VTO_ERR_NOMEM;
+    }
 
 #pragma omp parallel num_threads(nthreads) reduction(+ : n_step1, n_box, n_out)
     {
         int T = 1, t = 0;
-        int64_t o0, o1, v, s;
-        int64_t *ix, *iy, *iz;
+        int64_t o0, o1, v, s, plane = 1;
+        int64_t* idx;
 #ifdef _OPENMP
         T = omp_get_num_threads();
         t = omp_get_thread_num();
 #endif
+        int ax;
         o0 = g.n[outer] * t / T;
         o1 = g.n[outer] * (t + 1) / T;
-        ix = (int64_t*)malloc((size_t)(g.n[0] + g.n[1] + g.n[2]) * sizeof(int64_t));
-        if (!ix) {
+        for (ax = 0; ax < outer; ++ax)
+            plane *= g.n[ax];
+        idx = (int64_t*)malloc((size_t)nidx * sizeof(int64_t));
+        if (!idx) {
 #pragma omp atomic write
             failed = 1;
         } else {
-            int64_t plane = g.n[0] * (outer == 2 ? g.n[1] : 1);
-            iy = ix + g.n[0];
-            iz = iy + g.n[1];
             for (v = o0 * plane; v < o1 * plane; ++v) {
                 D[v] = INFINITY;
                 labels[v] = -1;
@@ -502,10 +562,13 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
             /* Step 1: for s = 1..N_s, every voxel of the ball of s takes s if
              * its key is strictly below D. */
             for (s = 0; s < nsites; ++s) {
-                const double* sp = coords + s * g.ndim;
+                const double* sp = sites + s * g.ndim;
                 double prm = param ? param[s] : 0.0;
                 double R = ball_radius(p, prm, tau);
-                int64_t nx, ny, nz, a, b, c;
+                int64_t* box[MAXD];
+                int64_t cnt[MAXD], pos[MAXD];
+                int64_t off = 0, c;
+                int b, empty = 0;
                 if (tau == -INFINITY)
                     break;
                 if (p->kind == VTO_VORONOI && !(tau >= 0.0))
@@ -514,21 +577,36 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
                     continue;
                 if (p->kind == VTO_JOHNSON_MEHL && !(tau >= prm))
                     continue;
-                nx = axis_box(&g, 0, sp[0], R, ix);
-                ny = axis_box(&g, 1, sp[1], R, iy);
-                nz = axis_box(&g, 2, g.ndim == 3 ? sp[2] : 0.0, R, iz);
-                for (c = 0; c < nz; ++c) {
-                    for (b = 0; b < ny; ++b) {
-                        int64_t jo = (outer == 2) ? iz[c] : iy[b];
-                        double x[3];
-                        if (jo < o0 || jo >= o1)
-                            continue;
-                        x[1] = voxel_centre(&g, 1, iy[b]);
-                        x[2] = (g.ndim == 3) ? voxel_centre(&g, 2, iz[c]) : 0.0;
-                        for (a = 0; a < nx; ++a) {
-                            int64_t lin = ix[a] + g.n[0] * (iy[b] + g.n[1] * iz[c]);
+                /* the index box of the ball, axis by axis */
+                for (b = 0; b < g.ndim; ++b) {
+                    box[b] = idx + off;
+                    cnt[b] = axis_box(&g, b, sp[b], R, box[b]);
+                    off += g.n[b];
+                    pos[b] = 0;
+                    if (cnt[b] == 0)
+                        empty = 1;
+                }
+                if (empty)
+                    continue;
+                /* every voxel of the box: axis 0 innermost, the others by an
+                 * odometer over their index lists */
+                for (;;) {
+                    int64_t jo = box[outer][pos[outer]];
+                    if (g.ndim == 1 || (jo >= o0 && jo < o1)) {
+                        double x[MAXD];
+                        int64_t base = 0, stride = 1;
+                        for (b = 0; b < g.ndim; ++b) {
+                            if (b > 0)
+                                base += box[b][pos[b]] * stride;
+                            x[b] = voxel_centre(&g, b, box[b][pos[b]]);
+                            stride *= g.n[b];
+                        }
+                        for (c = 0; c < cnt[0]; ++c) {
+                            int64_t lin = base + box[0][c];
                             double k;
-                            x[0] = voxel_centre(&g, 0, ix[a]);
+                            if (g.ndim == 1 && (box[0][c] < o0 || box[0][c] >= o1))
+                                continue;
+                            x[0] = voxel_centre(&g, 0, box[0][c]);
                             k = site_key(&g, sp, prm, x);
                             ++n_box;
                             if (k <= tau) { /* the voxel is inside the ball */
@@ -540,6 +618,13 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
                             }
                         }
                     }
+                    for (b = 1; b < g.ndim; ++b) {
+                        if (++pos[b] < cnt[b])
+                            break;
+                        pos[b] = 0;
+                    }
+                    if (b >= g.ndim)
+                        break;
                 }
             }
 
@@ -547,15 +632,16 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
              * loop. */
             for (v = o0 * plane; v < o1 * plane; ++v) {
                 if (labels[v] == -1) {
-                    double x[3];
+                    double x[MAXD];
                     ++n_out;
                     voxel_point(&g, v, x);
-                    brute_voxel(&g, nsites, coords, param, x, &labels[v], &D[v]);
+                    brute_voxel(&g, nsites, sites, param, x, &labels[v], &D[v]);
                 }
             }
-            free(ix);
+            free(idx);
         }
     }
+    release_sites(sites, coords);
     if (!keys_out)
         free(D);
     if (failed)

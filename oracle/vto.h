@@ -9,8 +9,9 @@
  * table or constant with the device library.
  *
  * What it computes (paper Sec. 2 and Sec. 3):
- *   For every voxel k of an n_0 x n_1 [x n_2] grid on the box
- *   Omega = [0,L_0) x [0,L_1) [x [0,L_2)], the label I(k) is the index of the
+ *   For every voxel k of an n_0 x ... x n_{d-1} grid (1 <= d <= 6; the paper
+ *   states the method for any dimension, Sec. 3) on the box
+ *   Omega = [0,L_0) x ... x [0,L_{d-1}), the label I(k) is the index of the
  *   site that minimises the diagram's key at the voxel centre x(k):
  *     Voronoi      key = q                      (squared distance, Sec. 3.1)
  *     Laguerre     key = q - w_s                (power distance, Sec. 2.3)
@@ -27,8 +28,14 @@
  *     if delta < -L_a/2 add L_a.  This is the paper's nearest-integer
  *     function N(y) = floor(y + 1/2) applied to the exact quotient
  *     delta / L_a (never to a rounded one);
- *   - q = d0*d0 + (d1*d1 + d2*d2) in 3D and d0*d0 + d1*d1 in 2D, each
- *     operation rounded once in IEEE binary64 (build with -ffp-contract=off);
+ *   - q = d0*d0 + T with T = d1*d1, then T = T + d2*d2, ... over the
+ *     remaining axes in order (3D: d0*d0 + (d1*d1 + d2*d2); 2D: d0*d0 + d1*d1;
+ *     1D: d0*d0), each operation rounded once in IEEE binary64 (build with
+ *     -ffp-contract=off);
+ *   - periodic boundaries: a site coordinate may be any finite number (App. A
+ *     defines the L-periodic distance for points outside the unit cell); it
+ *     is first brought into [0, L_a) by r = fmod(c, L_a), which is exact,
+ *     then r + L_a if r < 0, and 0 if that sum rounds up to L_a;
  *   - labels are 0-based.
  *
  * Precision: all arithmetic is IEEE binary64 with round-to-nearest, no
@@ -44,18 +51,19 @@ extern "C" {
 #endif
 
 enum { VTO_VORONOI = 0, VTO_LAGUERRE = 1, VTO_JOHNSON_MEHL = 2 };
+enum { VTO_MAX_DIM = 6 };
 
 /* Return codes (same numeric values as the device library's codes). */
 enum { VTO_OK = 0, VTO_ERR_INVALID = 1, VTO_ERR_NOMEM = 2, VTO_ERR_INPUT = 5 };
 
 /* Problem statement of Sec. 3 (list at the top of the section). */
 typedef struct {
-    int32_t ndim;      /* 2 or 3 */
+    int32_t ndim;      /* 1 .. VTO_MAX_DIM */
     int32_t kind;      /* VTO_VORONOI, VTO_LAGUERRE or VTO_JOHNSON_MEHL */
     int32_t periodic;  /* 1: L-periodic distance (App. A); 0: Euclidean */
     int32_t reserved;
-    int64_t n[3];      /* voxels per axis; axis 0 fastest in memory; n[2] ignored in 2D */
-    double  L[3];      /* domain lengths; L[2] ignored in 2D */
+    int64_t n[VTO_MAX_DIM]; /* voxels per axis; axis 0 fastest in memory; entries >= ndim ignored */
+    double  L[VTO_MAX_DIM]; /* domain lengths; entries >= ndim ignored */
     double  growth;    /* Johnson-Mehl growth rate G (= v) > 0; ignored otherwise */
 } vto_problem;
 
@@ -68,9 +76,9 @@ typedef struct {
     int64_t n_step2;   /* keys evaluated in step 2 (= n_out * N_s) */
 } vto_stats;
 
-/* Checks the problem scalars and every site (finite, inside [0,L_a); finite
- * parameter).  Returns VTO_OK, VTO_ERR_INVALID (bad scalars) or VTO_ERR_INPUT
- * (bad site data). */
+/* Checks the problem scalars and every site (finite; inside [0,L_a) unless
+ * the boundaries are periodic; finite parameter).  Returns VTO_OK,
+ * VTO_ERR_INVALID (bad scalars) or VTO_ERR_INPUT (bad site data). */
 int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
                  const double* param);
 
@@ -114,8 +122,8 @@ int vto_brute(const vto_problem* p, int64_t nsites, const double* coords,
               const double* param, int nthreads, int32_t* labels,
               double* keys_out);
 
-/* Brute force at selected voxels only: vox is [npts][3] voxel indices
- * (third entry ignored in 2D); writes label and minimum key per point. */
+/* Brute force at selected voxels only: vox is [npts][VTO_MAX_DIM] voxel
+ * indices (entries >= ndim ignored); writes label and minimum key per point. */
 int vto_label_points(const vto_problem* p, int64_t nsites, const double* coords,
                      const double* param, int64_t npts, const int64_t* vox,
                      int nthreads, int32_t* labels, double* keys_out);

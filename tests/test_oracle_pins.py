@@ -439,16 +439,23 @@ def test_single_site_takes_everything():
 # --------------------------------------------------------------------------
 
 def test_validation_errors():
-    p = prob((8, 8, 8))
+    p = prob((8, 8, 8), periodic=False)
+    pp = prob((8, 8, 8), periodic=True)
     good = np.full((3, 3), 1.0)
     assert O.validate(p, good) == O.OK
     for bad in (8.0, -1e-300, float("nan"), float("inf")):
         c = good.copy()
         c[1, 2] = bad
         assert O.validate(p, c) == O.ERR_INPUT
+        # periodic boundaries accept any finite coordinate (App. A)
+        assert O.validate(pp, c) == (O.OK if math.isfinite(bad) else O.ERR_INPUT)
     pj = prob((8, 8, 8), O.JOHNSON_MEHL, growth=0.0)
     assert O.validate(pj, good, np.zeros(3)) == O.ERR_INVALID
     pl = prob((8, 8, 8), O.LAGUERRE)
     assert O.validate(pl, good, np.array([0.0, float("nan"), 1.0])) == O.ERR_INPUT
     with pytest.raises(O.OracleError):
         O.tessellate(p, np.full((2, 3), 8.5))
+    with pytest.raises(O.OracleError):
+        O.tessellate(pp, np.full((2, 3), float("inf")))
+    with pytest.raises(ValueError):
+        O.problem([4] * 7, [4.0] * 7)
