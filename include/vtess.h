@@ -64,7 +64,11 @@ typedef struct {
     double  L[3];        /* domain lengths > 0; L[2] ignored in 2D */
     double  growth;      /* Johnson-Mehl growth rate v > 0 (G of eq. JMAK2); ignored otherwise */
     int64_t nsites;      /* 1 .. 2^31 - 1 */
-    const double* coords;/* device, [nsites][ndim] binary64, each in [0, L_a) */
+    const double* coords;/* device, [nsites][ndim] binary64: in [0, L_a) for non-periodic
+                          * boundaries; any finite value for periodic ones (brought into
+                          * [0, L_a) by an exact fmod, then + L_a if negative, 0 if that
+                          * sum rounds to L_a: App. A defines the L-periodic distance for
+                          * points outside the unit cell) */
     const double* param; /* device, [nsites]: Laguerre w_s, Johnson-Mehl t_s; NULL for Voronoi */
     int32_t* labels;     /* device, prod(n) int32 written by the call (x fastest) */
     double*  keys;       /* device, prod(n) binary64 or NULL: the winning key per voxel (the
@@ -73,6 +77,28 @@ typedef struct {
                           * by-product), bit-identical to the key that chose the label;
                           * NaN where the job's input is bad */
 } vt_job;
+
+/* General dimension (1 .. VT_MAX_DIM axes; the method is stated for any
+ * dimension in Sec. 3).  Fields as in vt_job, with
+ *   q = d0*d0 + T,  T = d1*d1, then T = T + d2*d2, ... over the remaining
+ *   axes in order (3D: d0*d0 + (d1*d1 + d2*d2); 2D: d0*d0 + d1*d1; 1D:
+ *   d0*d0), each operation rounded once. */
+#define VT_MAX_DIM 6
+enum { VT_ND_GENERIC = 1 }; /* flags: use the general kernel for 2 and 3 axes as well */
+typedef struct {
+    int32_t ndim;        /* 1 .. VT_MAX_DIM */
+    int32_t kind;        /* vt_kind */
+    int32_t bc;          /* vt_bc */
+    int32_t flags;       /* 0 or VT_ND_GENERIC */
+    int64_t n[VT_MAX_DIM]; /* voxels per axis, axis 0 fastest in memory; entries >= ndim ignored */
+    double  L[VT_MAX_DIM]; /* domain lengths > 0; entries >= ndim ignored */
+    double  growth;      /* Johnson-Mehl growth rate v > 0; ignored otherwise */
+    int64_t nsites;      /* 1 .. 2^31 - 1 */
+    const double* coords;/* device, [nsites][ndim], as for vt_job */
+    const double* param; /* device, [nsites] or NULL for Voronoi */
+    int32_t* labels;     /* device, prod(n) int32 */
+    double*  keys;       /* device, prod(n) binary64 or NULL: the winning key per voxel */
+} vt_job_nd;
 
 /* Creates a context on HIP device `device`.  Reads a tuning cache from the
  * file named by the environment variable VT_TUNE_CACHE if it is set.  A
@@ -93,6 +119,16 @@ vt_status vt_reserve(vt_ctx* ctx, size_t bytes);
  * device int32, set to VT_OK or VT_ERR_INPUT by the kernels.  May grow the
  * context's scratch, which synchronises the device. */
 vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
+
+/* Any dimension from 1 to VT_MAX_DIM.  Jobs with 2 or 3 axes go through
+ * vt_tessellate unless flags holds VT_ND_GENERIC; the others (and those
+ * with the flag) run the general kernel: a counting sort of the sites into a
+ * d-dimensional bin grid, then per tile of at most 256 voxels a search over
+ * rings of bins until the sites beyond them provably lose, and a
+ * lexicographic (key, index) minimum over the remaining candidates.  Same
+ * results, status word, errors and scratch behaviour as vt_tessellate
+ * (n_a in [1, 2^30], at most 2^40 voxels, else VT_ERR_INVALID). */
+vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_dev, void* stream);
 
 /* Many diagrams, of any sizes, kinds and boundaries: one segmented binning
  * pass over all of them, then one persistent labelling launch per group of

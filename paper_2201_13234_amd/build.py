@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvtess.so")
-SOURCES = ["label_batch.hip", "label_kernel.hip", "bin_kernels.hip", "api.hip"]
+SOURCES = ["label_batch.hip", "label_kernel.hip", "bin_kernels.hip", "nd_kernels.hip", "api.hip"]
 # The labelling kernel never sees a NaN (sites are checked by the binning
 # pass and a job with bad input is skipped), so min/max need no quieting;
 # infinities stay honoured.

@@ -600,6 +600,180 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     return VT_OK;
 }
 
+// ---- general dimension ----
+
+namespace {
+
+// Tile shape of the general kernel: powers of two per axis, at most 256
+// voxels, grown along the axis with the most voxels per tile side.
+void nd_tile_shape(const vt_job_nd* j, int32_t* T)
+{
+    int prod = 1;
+    for (int a = 0; a < j->ndim; ++a)
+        T[a] = 1;
+    while (prod * 2 <= 256) {
+        int best = -1;
+        double ratio = 1.0;
+        for (int a = 0; a < j->ndim; ++a) {
+            const double r = (double)j->n[a] / (double)T[a];
+            if (T[a] < j->n[a] && r > ratio) {
+                ratio = r;
+                best = a;
+            }
+        }
+        if (best < 0)
+            break;
+        T[best] *= 2;
+        prod *= 2;
+    }
+}
+
+vt_status plan_nd(const vt_job_nd* j, vt::NdDev* d)
+{
+    if (!j)
+        return fail(VT_ERR_INVALID, "job is NULL");
+    if (j->ndim < 1 || j->ndim > VT_MAX_DIM)
+        return fail(VT_ERR_INVALID, "ndim must be in [1, 6]");
+    if (j->kind < VT_VORONOI || j->kind > VT_JOHNSON_MEHL)
+        return fail(VT_ERR_INVALID, "unknown diagram kind");
+    if (j->bc != VT_NONPERIODIC && j->bc != VT_PERIODIC)
+        return fail(VT_ERR_INVALID, "unknown boundary mode");
+    if (j->flags & ~VT_ND_GENERIC)
+        return fail(VT_ERR_INVALID, "unknown flags");
+    if (j->nsites < 1 || j->nsites > 0x7fffffffLL)
+        return fail(VT_ERR_INVALID, "nsites must be in [1, 2^31-1]");
+    if (!j->coords || !j->labels)
+        return fail(VT_ERR_INVALID, "coords and labels must be device pointers");
+    if (j->kind != VT_VORONOI && !j->param)
+        return fail(VT_ERR_INVALID, "param is required for Laguerre and Johnson-Mehl");
+    if (j->kind == VT_JOHNSON_MEHL && !(std::isfinite(j->growth) && j->growth > 0.0))
+        return fail(VT_ERR_INVALID, "growth rate must be finite and > 0");
+    std::memset(d, 0, sizeof *d);
+    d->ndim = j->ndim;
+    d->kind = j->kind;
+    d->bc = j->bc ? 1 : 0;
+    double nvox = 1.0, V = 1.0;
+    for (int a = 0; a < j->ndim; ++a) {
+        if (j->n[a] < 1 || j->n[a] > (1 << 30))
+            return fail(VT_ERR_INVALID, "n[a] must be in [1, 2^30]");
+        if (!(std::isfinite(j->L[a]) && j->L[a] > 0.0))
+            return fail(VT_ERR_INVALID, "L[a] must be finite and > 0");
+        d->n[a] = j->n[a];
+        d->L[a] = j->L[a];
+        d->h[a] = j->L[a] / (double)j->n[a];
+        d->H[a] = 0.5 * j->L[a];
+        nvox *= (double)j->n[a];
+        V *= j->L[a];
+    }
+    if (nvox > 1099511627776.0)
+        return fail(VT_ERR_INVALID, "more than 2^40 voxels");
+    d->nsites = (int32_t)j->nsites;
+    d->growth = j->kind == VT_JOHNSON_MEHL ? j->growth : 1.0;
+    d->rgrowth = 1.0 / d->growth;
+    d->jm_div = (j->kind == VT_JOHNSON_MEHL && !is_pow2_scale(d->growth)) ? 1 : 0;
+
+    // Bins: side ~ the mean site spacing (V / N)^(1/d), at most 2^20 per axis
+    // and about 4 N + 64 in total.
+    const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim);
+    int64_t nbins = 1;
+    for (int a = 0; a < j->ndim; ++a) {
+        const double f = std::floor(j->L[a] / spacing + 0.5);
+        d->nb[a] = (int)std::min(std::max(f, 1.0), (double)(1 << 20));
+        nbins *= d->nb[a];
+    }
+    const int64_t cap = std::min<int64_t>(4 * (int64_t)j->nsites + 64, (int64_t)1 << 28);
+    while (nbins > cap) {
+        nbins = 1;
+        for (int a = 0; a < j->ndim; ++a) {
+            d->nb[a] = std::max(1, d->nb[a] * 3 / 4);
+            nbins *= d->nb[a];
+        }
+    }
+    d->nbins = (int32_t)nbins;
+    for (int a = 0; a < j->ndim; ++a) {
+        d->bs[a] = j->L[a] / (double)d->nb[a];
+        d->inv_bs[a] = (double)d->nb[a] / j->L[a];
+    }
+    nd_tile_shape(j, d->T);
+    d->ntiles = 1;
+    for (int a = 0; a < j->ndim; ++a) {
+        d->nt[a] = (j->n[a] + d->T[a] - 1) / d->T[a];
+        d->ntiles *= d->nt[a];
+    }
+    d->coords = j->coords;
+    d->param = j->param;
+    d->labels = j->labels;
+    d->keys = j->keys;
+    return VT_OK;
+}
+
+}  // namespace
+
+vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_dev, void* stream)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    if (job && (job->ndim == 2 || job->ndim == 3) && !(job->flags & VT_ND_GENERIC)) {
+        if (job->flags & ~VT_ND_GENERIC)
+            return fail(VT_ERR_INVALID, "unknown flags");
+        vt_job j;
+        std::memset(&j, 0, sizeof j);
+        j.ndim = job->ndim;
+        j.kind = job->kind;
+        j.bc = job->bc;
+        for (int a = 0; a < job->ndim; ++a) {
+            j.n[a] = job->n[a];
+            j.L[a] = job->L[a];
+        }
+        j.growth = job->growth;
+        j.nsites = job->nsites;
+        j.coords = job->coords;
+        j.param = job->param;
+        j.labels = job->labels;
+        j.keys = job->keys;
+        return vt_tessellate(ctx, &j, status_dev, stream);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    vt::NdDev d;
+    vt_status st = plan_nd(job, &d);
+    if (st != VT_OK)
+        return st;
+    VT_HIP(hipSetDevice(ctx->device));
+    Carver c;
+    const size_t o_pbound = c.take<unsigned long long>(2);
+    const size_t o_status = c.take<int32_t>(1, 4);
+    const size_t o_count = c.take<int32_t>(d.nbins, 4);
+    const size_t o_start = c.take<int32_t>((int64_t)d.nbins + 1);
+    const size_t o_bin = c.take<int32_t>(d.nsites);
+    const size_t o_rank = c.take<int32_t>(d.nsites);
+    const size_t o_sc = c.take<double>((int64_t)d.nsites * d.ndim);
+    const size_t o_sp = c.take<double>(d.nsites);
+    const size_t o_sidx = c.take<int32_t>(d.nsites);
+    const int64_t partial_cap = vt::scan_partials_needed((int64_t)d.nbins);
+    const size_t o_partial = c.take<int32_t>(partial_cap);
+    if ((st = ensure_scratch(ctx, align_up(c.off, 256))) != VT_OK)
+        return st;
+    char* base = (char*)ctx->scratch;
+    d.pbound = (unsigned long long*)(base + o_pbound);
+    d.status = status_dev ? status_dev : (int32_t*)(base + o_status);
+    d.bin_count = (int32_t*)(base + o_count);
+    d.bin_start = (int32_t*)(base + o_start);
+    d.site_bin = (int32_t*)(base + o_bin);
+    d.site_rank = (int32_t*)(base + o_rank);
+    d.sc = (double*)(base + o_sc);
+    d.sp = (double*)(base + o_sp);
+    d.sidx = (int32_t*)(base + o_sidx);
+    // pbound, internal status and bin counts are contiguous: zero them
+    // together (and the caller's status word)
+    const int64_t words = (int64_t)((o_count - o_pbound) / 4) + d.nbins;
+    VT_HIP(launch_prepare((int32_t*)(base + o_pbound), words, status_dev, s));
+    VT_HIP(vt::launch_nd_bin_count(d, s));
+    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (int32_t*)(base + o_partial), partial_cap, s));
+    VT_HIP(vt::launch_nd_bin_scatter(d, s));
+    VT_HIP(vt::launch_nd_label(d, s));
+    return VT_OK;
+}
+
 vt_status vt_profile_enable(vt_ctx* ctx, int32_t enable)
 {
     if (!ctx)

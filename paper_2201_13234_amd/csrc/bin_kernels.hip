@@ -5,9 +5,11 @@
 //
 // One thread per site.  In a batch, a thread finds its job by binary search
 // over the per-job site offsets.  The count pass also checks every site
-// (finite coordinates inside [0, L_a), finite parameter; problem statement of
-// Sec. 3) and records max(param) and max(-param) for the labelling kernel's
-// lower bounds.
+// (finite coordinates, inside [0, L_a) unless the boundaries are periodic;
+// finite parameter; problem statement of Sec. 3) and records max(param) and
+// max(-param) for the labelling kernel's lower bounds.  Periodic coordinates
+// are brought into the unit cell (cell_coord) by both passes, so the sorted
+// sites always lie in [0, L_a).
 #include "vt_internal.h"
 
 namespace vt {
@@ -76,6 +78,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDe
         for (int a = 0; a < 3; ++a) {
             if (a < nd) {
                 double c = J.coords[i * nd + a];
+                if (J.bc && isfinite(c))
+                    c = cell_coord(c, J.L[a]);
                 if (!(c >= 0.0 && c < J.L[a])) {
                     ok = false;
                 } else {
@@ -148,9 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const Job
     int pos = J.bin_start[lin] + J.site_rank[i];
     const double* c = J.coords + i * nd;
     double4 rec;
-    rec.x = c[0];
-    rec.y = c[1];
-    rec.z = nd == 3 ? c[2] : 0.0;
+    rec.x = J.bc ? cell_coord(c[0], J.L[0]) : c[0];
+    rec.y = J.bc ? cell_coord(c[1], J.L[1]) : c[1];
+    rec.z = nd == 3 ? (J.bc ? cell_coord(c[2], J.L[2]) : c[2]) : 0.0;
     rec.w = J.kind != KIND_VORONOI ? J.param[i] : 0.0;
     J.sites[pos] = rec;
     J.sidx[pos] = (int32_t)i;

@@ -93,6 +93,55 @@ __device__ inline double key_sqrt(double q)
     return q >= 0x1p-500 ? sqrt_refined(q) : sqrt(q);
 }
 
+// A periodic site coordinate brought into the unit cell [0, L): the
+// L-periodic distance (App. A, eq. L-distance_def) is unchanged when a point
+// moves by whole periods.  fmod is exact; r + L for r < 0 is the one rounding,
+// and a sum that rounds up to L is the origin of the next period.
+__device__ inline double cell_coord(double c, double L)
+{
+    double r = fmod(c, L);
+    if (r < 0.0) {
+        r = r + L;
+        if (r >= L)
+            r = 0.0;
+    }
+    return r + 0.0;  // -0.0 -> +0.0
+}
+
+// ---- any dimension (1 .. kMaxDim): the general path ----
+constexpr int kMaxDim = 6;
+
+// Device-side description of one diagram of the general path.
+struct NdDev {
+    int32_t ndim, kind, bc, jm_div;
+    int32_t nsites, nbins;
+    int32_t T[kMaxDim];            // tile voxels per axis (powers of two, product <= 256)
+    int32_t nb[kMaxDim];           // bins per axis
+    int64_t n[kMaxDim];            // voxels per axis
+    int64_t nt[kMaxDim];           // tiles per axis
+    int64_t ntiles;
+    double L[kMaxDim], h[kMaxDim], H[kMaxDim];
+    double bs[kMaxDim], inv_bs[kMaxDim];
+    double growth, rgrowth;
+    const double* coords;          // [nsites][ndim], caller input
+    const double* param;           // [nsites] or null
+    int32_t* labels;               // caller output
+    double* keys;                  // caller output or null
+    int32_t* status;               // one word, written by the kernels
+    int32_t* bin_count;            // [nbins]
+    int32_t* bin_start;            // [nbins + 1]
+    int32_t* site_bin;             // [nsites]
+    int32_t* site_rank;            // [nsites]
+    double* sc;                    // [nsites][ndim] sorted coordinates, inside the cell
+    double* sp;                    // [nsites] sorted parameters
+    int32_t* sidx;                 // sorted -> input index
+    unsigned long long* pbound;    // [2]: ordered bits of max(param), max(-param)
+};
+
+hipError_t launch_nd_bin_count(const NdDev& J, hipStream_t s);
+hipError_t launch_nd_bin_scatter(const NdDev& J, hipStream_t s);
+hipError_t launch_nd_label(const NdDev& J, hipStream_t s);
+
 // ---- launchers (defined in the .hip files) ----
 // Binning over one job (jobs_dev == nullptr, `single` used) or over njobs jobs
 // whose sites are enumerated by site_prefix_dev ([njobs + 1], device).

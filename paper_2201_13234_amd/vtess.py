@@ -17,7 +17,8 @@ NONPERIODIC, PERIODIC = 0, 1
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BUSY, ERR_INPUT = range(6)
 
 # Symbols declared in include/vtess.h.
-EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessellate_batch", "vt_bins_build",
+EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessellate_nd", "vt_tessellate_batch",
+           "vt_bins_build",
            "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_load_tuning", "vt_set_params",
            "vt_plan", "vt_numerics_probe", "vt_label_digest", "vt_profile_enable", "vt_profile_read",
            "vt_status_string", "vt_last_error"]
@@ -26,6 +27,18 @@ EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessell
 class VtJob(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("kind", ctypes.c_int32), ("bc", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("n", ctypes.c_int64 * 3), ("L", ctypes.c_double * 3),
+                ("growth", ctypes.c_double), ("nsites", ctypes.c_int64),
+                ("coords", ctypes.c_void_p), ("param", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("keys", ctypes.c_void_p)]
+
+
+MAX_DIM = 6
+ND_GENERIC = 1
+
+
+class VtJobNd(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("kind", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("n", ctypes.c_int64 * MAX_DIM), ("L", ctypes.c_double * MAX_DIM),
                 ("growth", ctypes.c_double), ("nsites", ctypes.c_int64),
                 ("coords", ctypes.c_void_p), ("param", ctypes.c_void_p), ("labels", ctypes.c_void_p),
                 ("keys", ctypes.c_void_p)]
@@ -58,6 +71,7 @@ def lib():
         L.vt_destroy.argtypes = [vp]
         L.vt_destroy.restype = None
         L.vt_tessellate.argtypes = [vp, P(VtJob), vp, vp]
+        L.vt_tessellate_nd.argtypes = [vp, P(VtJobNd), vp, vp]
         L.vt_tessellate_batch.argtypes = [vp, P(VtJob), i32, vp, vp]
         L.vt_bins_build.argtypes = [vp, P(VtJob), P(vp), vp, vp]
         L.vt_label_batch.argtypes = [vp, P(vp), i32, vp, vp]
@@ -117,7 +131,7 @@ class Job:
     labels: object = None     # torch int32 with prod(n) elements, allocated if None
     keys: object = None       # torch float64 with prod(n) elements for the distance image, or None
 
-    def to_c(self):
+    def _check_tensors(self):
         import torch
         d = len(self.n)
         if self.labels is None:
@@ -133,12 +147,39 @@ class Job:
             raise ValueError("labels must hold prod(n) elements")
         if self.keys is not None and self.keys.numel() != int(_prod(self.n)):
             raise ValueError("keys must hold prod(n) elements")
+
+    def to_c(self):
+        d = len(self.n)
+        if d not in (2, 3):
+            raise ValueError("vt_job holds 2 or 3 axes; use Context.tessellate_nd")
+        self._check_tensors()
         j = VtJob()
         j.ndim = d
         j.kind = int(self.kind)
         j.bc = PERIODIC if self.periodic else NONPERIODIC
         j.reserved = 0
         for a in range(3):
+            j.n[a] = int(self.n[a]) if a < d else 1
+            j.L[a] = float(self.L[a]) if a < d else 1.0
+        j.growth = float(self.growth)
+        j.nsites = int(self.coords.shape[0])
+        j.coords = self.coords.data_ptr()
+        j.param = self.param.data_ptr() if self.param is not None else None
+        j.labels = self.labels.data_ptr()
+        j.keys = self.keys.data_ptr() if self.keys is not None else None
+        return j
+
+    def to_c_nd(self, generic=False):
+        d = len(self.n)
+        if not 1 <= d <= MAX_DIM:
+            raise ValueError(f"1 to {MAX_DIM} axes")
+        self._check_tensors()
+        j = VtJobNd()
+        j.ndim = d
+        j.kind = int(self.kind)
+        j.bc = PERIODIC if self.periodic else NONPERIODIC
+        j.flags = ND_GENERIC if generic else 0
+        for a in range(MAX_DIM):
             j.n[a] = int(self.n[a]) if a < d else 1
             j.L[a] = float(self.L[a]) if a < d else 1.0
         j.growth = float(self.growth)
@@ -192,6 +233,14 @@ class Context:
         cj = job.to_c()
         _check(lib().vt_tessellate(self.handle, ctypes.byref(cj), _ptr(status), _stream(stream)),
                "vt_tessellate")
+        return job.labels
+
+    def tessellate_nd(self, job, status=None, stream=None, generic=False):
+        """Any number of axes from 1 to 6 (vt_tessellate_nd); generic=True
+        runs the general kernel also for 2 and 3 axes."""
+        cj = job.to_c_nd(generic)
+        _check(lib().vt_tessellate_nd(self.handle, ctypes.byref(cj), _ptr(status), _stream(stream)),
+               "vt_tessellate_nd")
         return job.labels
 
     def tessellate_batch(self, jobs, status=None, stream=None):

@@ -48,6 +48,35 @@ def test_job_struct_matches_header_layout():
     assert vtess.VtJob.coords.offset == 80
 
 
+def test_job_structs_match_the_c_compiler(tmp_path):
+    # Layout as the C compiler sees include/vtess.h, against the ctypes mirrors.
+    import ctypes
+    import subprocess
+    from paper_2201_13234_amd import vtess
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "vtess.h"
+int main(void) {
+    printf("%zu %zu %zu %zu\\n", sizeof(vt_job), offsetof(vt_job, coords), offsetof(vt_job, keys),
+           offsetof(vt_job, growth));
+    printf("%zu %zu %zu %zu\\n", sizeof(vt_job_nd), offsetof(vt_job_nd, coords), offsetof(vt_job_nd, keys),
+           offsetof(vt_job_nd, growth));
+    return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    rows = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for row, S in zip(rows, (vtess.VtJob, vtess.VtJobNd)):
+        size, coords, keys, growth = (int(v) for v in row.split())
+        assert (size, coords, keys, growth) == (ctypes.sizeof(S), S.coords.offset, S.keys.offset,
+                                                S.growth.offset)
+    assert ctypes.sizeof(vtess.VtJobNd) == 16 + 48 + 48 + 8 + 8 + 32
+
+
 def test_product_code_never_imports_the_oracle():
     for dirpath, _, files in os.walk(PKG):
         for f in files:

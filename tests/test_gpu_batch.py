@@ -68,7 +68,7 @@ def test_one_bad_job_fails_alone(ctx):
     ws = mixed_jobs(8, 2)
     bad = ws[3]
     bad.coords = bad.coords.copy()
-    bad.coords[0, 0] = -1.0
+    bad.coords[0, 0] = float("nan")
     jobs = [to_dev(w) for w in ws]
     status = torch.zeros(len(jobs), dtype=torch.int32, device="cuda:0")
     ctx.tessellate_batch(jobs, status=status)

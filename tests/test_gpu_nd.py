@@ -1,0 +1,239 @@
+"""Parity of the general path (vt_tessellate_nd: 1 to 6 axes) and of periodic
+sites outside the unit cell with the oracle, voxel by voxel, bit for bit:
+labels and the winning keys.
+
+Sizes span several tiles with ragged tails on every axis; the edge cases are
+one site, duplicates, sites on voxel centres, axes of one voxel, more sites
+than voxels, clusters that overflow one staging round of the kernel, and bad
+input.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_13234_amd import inputs as I
+from gpu_util import describe_mismatch, run_device, to_dev, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2201_13234_amd import vtess
+    assert torch.cuda.is_available()
+    c = vtess.Context(0)
+    yield c
+    c.close()
+
+
+def run_nd(ctx, w, generic=False, keys=True):
+    import torch
+    job = to_dev(w)
+    if keys:
+        job.keys = torch.full(tuple(reversed(w.n)), -7.0, dtype=torch.float64, device="cuda:0")
+    st = torch.full((1,), 99, dtype=torch.int32, device="cuda:0")
+    print(f"[nd] {w.name} n={w.n} ns={len(w.coords)} kind={w.kind} periodic={w.periodic} "
+          f"generic={generic}", flush=True)
+    ctx.tessellate_nd(job, status=st, generic=generic)
+    torch.cuda.synchronize()
+    return job.labels.cpu().numpy(), (job.keys.cpu().numpy() if keys else None), int(st.item())
+
+
+def oracle_keys(w):
+    p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+    lab, key, _ = oracle.tessellate(p, w.coords, w.param, want_keys=True)
+    return lab, key
+
+
+def check(ctx, w, generic=False):
+    lab_ref, key_ref = oracle_keys(w)
+    lab, key, st = run_nd(ctx, w, generic)
+    assert st == 0
+    assert np.array_equal(lab, lab_ref), f"{w.name}: " + describe_mismatch(lab, lab_ref)
+    assert np.array_equal(key.view(np.int64), key_ref.view(np.int64)), f"{w.name}: keys differ"
+
+
+def random_nd(seed, d, kind=None, periodic=None, outside=False):
+    rng = np.random.default_rng(3000 + seed)
+    top = {1: 3000, 2: 90, 3: 30, 4: 14, 5: 9, 6: 6}[d]
+    n = tuple(int(v) for v in rng.integers(1, top, d))
+    if np.prod(n) < 64:
+        n = tuple(max(v, 3) for v in n)
+    L = tuple(float(v) * float(rng.uniform(0.5, 2.0)) for v in n)
+    kind = int(rng.integers(0, 3)) if kind is None else kind
+    periodic = bool(rng.integers(0, 2)) if periodic is None else periodic
+    ns = int(rng.integers(1, 300))
+    coords = I.uniform_sites(rng, ns, L)
+    if outside and periodic:
+        coords = coords + rng.integers(-3, 4, coords.shape) * np.array(L)
+    sp = (np.prod(L) / ns) ** (1.0 / d)
+    param = None
+    if kind == I.LAGUERRE:
+        param = I.lognormal_weights(rng, ns, 0.5 * sp, 0.3)
+    elif kind == I.JOHNSON_MEHL:
+        param = rng.uniform(0.0, 1.92 * sp, ns)
+    growth = float(rng.choice([1.0, 0.5, 0.7, 2.0]))
+    return workload(n, kind, periodic, coords, param, growth, L=L, name=f"nd{d}_{seed}")
+
+
+# ------------------------------------------------------------- other dimensions
+
+@pytest.mark.parametrize("seed", range(24))
+def test_nd_random(ctx, seed):
+    d = (1, 4, 5, 6)[seed % 4]
+    check(ctx, random_nd(seed, d, kind=(seed // 4) % 3, periodic=seed % 8 < 4))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_general_kernel_in_2d_and_3d(ctx, seed):
+    # the general kernel on 2 and 3 axes must give the tuned path's results
+    d = 2 + seed % 2
+    w = random_nd(100 + seed, d, kind=(seed // 2) % 3, periodic=seed % 4 < 2)
+    check(ctx, w, generic=True)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_nd_entry_routes_2d_3d_to_the_tuned_path(ctx, d):
+    w = random_nd(200 + d, d, kind=0, periodic=True)
+    lab_ref, key_ref = oracle_keys(w)
+    lab, key, st = run_nd(ctx, w, generic=False)
+    assert st == 0 and np.array_equal(lab, lab_ref)
+    assert np.array_equal(key.view(np.int64), key_ref.view(np.int64))
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_nd_1d_long_line(ctx, kind):
+    # 1D: many tiles of 256 voxels, ragged end
+    rng = np.random.default_rng(40 + kind)
+    n = (200_003,)
+    L = (1000.0,)
+    ns = 5000
+    coords = I.uniform_sites(rng, ns, L)
+    param = None if kind == 0 else rng.uniform(0, 0.3, ns)
+    check(ctx, workload(n, kind, kind != 1, coords, param, 0.9, L=L, name=f"line{kind}"))
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_nd_4d_several_thousand_sites(ctx, kind):
+    rng = np.random.default_rng(50 + kind)
+    n = (21, 18, 17, 13)
+    L = tuple(float(v) for v in n)
+    ns = 4000
+    coords = I.uniform_sites(rng, ns, L)
+    sp = (np.prod(L) / ns) ** 0.25
+    param = None
+    if kind == 1:
+        param = I.lognormal_weights(rng, ns, 0.5 * sp, 0.3)
+    elif kind == 2:
+        param = rng.uniform(0, 1.92 * sp, ns)
+    check(ctx, workload(n, kind, True, coords, param, 1.0, L=L, name=f"4d{kind}"))
+
+
+# --------------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("d", [1, 4, 6])
+def test_nd_single_site(ctx, d):
+    n = {1: (77,), 4: (5, 6, 7, 3), 6: (3, 4, 2, 3, 2, 3)}[d]
+    w = workload(n, 2, False, np.full((1, d), 0.37), np.array([1.5]), 0.8, name=f"one{d}")
+    check(ctx, w)
+
+
+@pytest.mark.parametrize("d", [1, 4, 5])
+def test_nd_duplicates_and_voxel_centres(ctx, d):
+    rng = np.random.default_rng(60 + d)
+    n = {1: (300,), 4: (9, 8, 7, 6), 5: (6, 5, 7, 4, 5)}[d]
+    ns = 120
+    idx = np.stack([rng.integers(0, v, ns) for v in n], axis=1)
+    coords = idx + 0.5                                   # on voxel centres (L = n)
+    coords[ns // 2:] = coords[: ns - ns // 2]            # duplicates: lower index wins
+    for periodic in (True, False):
+        check(ctx, workload(n, 0, periodic, coords, name=f"dup{d}{periodic}"))
+
+
+def test_nd_axes_of_one_voxel(ctx):
+    rng = np.random.default_rng(7)
+    n = (1, 13, 1, 9, 1)
+    L = (0.7, 13.0, 2.0, 9.0, 1.0)
+    coords = I.uniform_sites(rng, 40, L)
+    for kind in (0, 1, 2):
+        param = None if kind == 0 else rng.uniform(0, 2, 40)
+        check(ctx, workload(n, kind, kind != 2, coords, param, 1.3, L=L, name=f"flat{kind}"))
+
+
+def test_nd_more_sites_than_voxels(ctx):
+    rng = np.random.default_rng(8)
+    n = (4, 5, 3, 4)
+    L = tuple(float(v) for v in n)
+    coords = I.uniform_sites(rng, 2000, L)
+    check(ctx, workload(n, 0, True, coords, L=L, name="dense4d"))
+
+
+@pytest.mark.parametrize("kind", [0, 2])
+def test_nd_cluster_overflows_staging(ctx, kind):
+    # 3000 sites inside one small region: a tile's candidates exceed one LDS
+    # staging round (512) several times over.
+    rng = np.random.default_rng(9 + kind)
+    n = (12, 12, 10, 10)
+    L = tuple(float(v) for v in n)
+    coords = 5.0 + rng.random((3000, 4)) * 0.8
+    param = None if kind == 0 else rng.uniform(0, 0.01, 3000)
+    check(ctx, workload(n, kind, False, coords, param, 1.0, L=L, name=f"cluster{kind}"))
+
+
+def test_nd_bad_input(ctx):
+    rng = np.random.default_rng(10)
+    n = (7, 6, 5, 4)
+    L = tuple(float(v) for v in n)
+    coords = I.uniform_sites(rng, 30, L)
+    for periodic, bad in ((False, 7.0), (False, -0.5), (True, np.nan), (True, np.inf)):
+        c = coords.copy()
+        c[11, 0] = bad
+        lab, key, st = run_nd(ctx, workload(n, 0, periodic, c, L=L, name="bad"))
+        assert st == 5 and np.all(lab == -1) and np.all(np.isnan(key))
+    # a bad parameter
+    lab, key, st = run_nd(ctx, workload(n, 1, True, coords, np.where(np.arange(30) == 3, np.nan, 1.0),
+                                        L=L, name="badw"))
+    assert st == 5 and np.all(lab == -1)
+
+
+def test_nd_scalar_errors(ctx):
+    import torch
+    from paper_2201_13234_amd import vtess
+    w = random_nd(300, 4, kind=0)
+    job = to_dev(w)
+    job.n = (3,) * 7
+    with pytest.raises(ValueError):
+        ctx.tessellate_nd(job)
+    job = to_dev(w)
+    job.L = (1.0, -1.0, 1.0, 1.0)
+    with pytest.raises(vtess.VtError) as e:
+        ctx.tessellate_nd(job)
+    assert e.value.code == vtess.ERR_INVALID
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------- periodic sites outside the cell
+
+@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_tuned_path_sites_outside_the_cell(ctx, d, kind):
+    w = random_nd(400 + 3 * d + kind, d, kind=kind, periodic=True, outside=True)
+    w.coords[0, 0] = -1e-300
+    lab_ref, key_ref = oracle_keys(w)
+    lab, st = run_device(ctx, w, status=True)
+    assert st == 0 and np.array_equal(lab, lab_ref), describe_mismatch(lab, lab_ref)
+    # the batch path bins with the same kernels
+    import torch
+    job = to_dev(w)
+    job.keys = torch.zeros(tuple(reversed(w.n)), dtype=torch.float64, device="cuda:0")
+    ctx.tessellate_batch([job])
+    torch.cuda.synchronize()
+    assert np.array_equal(job.labels.cpu().numpy(), lab_ref)
+    assert np.array_equal(job.keys.cpu().numpy().view(np.int64), key_ref.view(np.int64))
+
+
+@pytest.mark.parametrize("d", [1, 4, 5])
+def test_nd_sites_outside_the_cell(ctx, d):
+    for kind in (0, 1, 2):
+        check(ctx, random_nd(500 + 3 * d + kind, d, kind=kind, periodic=True, outside=True))

@@ -258,7 +258,8 @@ def test_invalid_sites_give_minus_one(ctx):
     for bad in (20.0, -0.5, float("nan"), float("inf")):
         pts = I.uniform_sites(rng, 30, [20.0] * 3)
         pts[11, 1] = bad
-        w = workload(n, 0, True, pts)
+        # periodic boundaries accept any finite coordinate (brought into the cell)
+        w = workload(n, 0, not np.isfinite(bad), pts)
         lab, st = run_device(ctx, w, status=True)
         assert st == 5
         assert np.all(lab == -1)
@@ -403,6 +404,6 @@ def test_jm_keys_sites_on_voxel_centres(ctx, d):
 def test_keys_nan_for_bad_input(ctx):
     w = I.make((20, 20, 20), 0, True, 50, 5)
     w.coords = w.coords.copy()
-    w.coords[3, 1] = 20.0          # outside [0, L)
+    w.coords[3, 1] = float("nan")
     lab, key = run_keys(ctx, w)
     assert np.all(lab == -1) and np.all(np.isnan(key))
