@@ -11,7 +11,10 @@ in HBM.  The line printed at the end also carries
     (committed counter summary, used only while it matches the kernel
     source);
   - cpu_baseline: the CPU oracle (paper's two-step ball algorithm) timed on
-    the host's cores on the same workload;
+    the host's cores on the same workload, and the device labels of the timed
+    configuration checked against the oracle at sampled voxels;
+  - general_path (with --nd): the general-dimension kernel on a 4D Voronoi
+    diagram, 64^4 voxels and 16,384 sites;
   - serving: a short request stream replayed through the continuous-batching
     loop and one job at a time (p50/p99 latency), unless --no-serving.
 """
@@ -126,16 +129,75 @@ def summarize_counters(args):
     print(json.dumps(rec, indent=1))
 
 
-def cpu_baseline(w):
+def cpu_baseline(w, labels):
+    """The oracle on the host cores (one full diagram), and the device labels
+    `labels` of the same workload checked at 2,000 sampled voxels."""
+    import numpy as np
     import oracle
     p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     oracle.tessellate(p, w.coords, w.param, nthreads=threads)
     dt = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    vox = np.stack([rng.integers(0, n, 2000) for n in w.n], axis=1)
+    ref, _ = oracle.label_points(p, w.coords, w.param, vox)
+    got = labels[tuple(vox[:, a] for a in reversed(range(len(w.n))))]
     return {"value": round(w.nvox / dt / 1e9, 6), "unit": "Gvoxels/s", "cores": threads,
             "kind": "oracle", "seconds": round(dt, 3),
-            "sample": f"one full diagram of the benchmark workload ({w.name}), two-step ball algorithm"}
+            "sample": f"one full diagram of the benchmark workload ({w.name}), two-step ball algorithm",
+            "sampled_parity": {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}}
+
+
+def nd_workload():
+    """4D Voronoi, 64^4 voxels, 16,384 uniform periodic sites (about M2's
+    voxels per site), seed 6."""
+    import numpy as np
+    from paper_2201_13234_amd import inputs
+    n = (64, 64, 64, 64)
+    L = tuple(float(v) for v in n)
+    rng = np.random.default_rng(6)
+    return n, L, inputs.uniform_sites(rng, 16384, L)
+
+
+def nd_sampled_parity(labels):
+    """Part of the CPU leg: the general kernel's labels at sampled voxels
+    against the oracle."""
+    import numpy as np
+    import oracle
+    n, L, coords = nd_workload()
+    rng = np.random.default_rng(1)
+    vox = np.stack([rng.integers(0, v, 2000) for v in n], axis=1)
+    ref, _ = oracle.label_points(oracle.problem(n, L, oracle.VORONOI, True), coords, None, vox)
+    got = labels[tuple(vox[:, a] for a in reversed(range(len(n))))]
+    return {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}
+
+
+def general_path(ctx, steps, warmup):
+    """The general-dimension kernel (vt_tessellate_nd) on nd_workload(),
+    timed with events on the stream the kernels run on."""
+    import numpy as np
+    import torch
+    from paper_2201_13234_amd import inputs, vtess
+    n, L, coords = nd_workload()
+    dev = torch.device("cuda:0")
+    job = vtess.Job(n=n, L=L, kind=inputs.VORONOI, periodic=True,
+                    coords=torch.from_numpy(coords).to(dev))
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.tessellate_nd(job, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.tessellate_nd(job, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nvox = int(np.prod(n))
+    return {"workload": "4D Voronoi 64^4, 16,384 sites, periodic, seed 6", "ms_per_call": round(ms, 4),
+            "value": round(nvox / (ms * 1e-3) / 1e9, 3), "unit": "Gvoxels/s",
+            "hbm_write_frac": round(4.0 * nvox / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "labels": job.labels.cpu().numpy()}
 
 
 def main():
@@ -146,6 +208,7 @@ def main():
     ap.add_argument("--config", default="M2", help="M1..M4 (default M2, the headline workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream replay")
+    ap.add_argument("--nd", action="store_true", help="also time the general-dimension kernel (4D)")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="request-stream length (the stream of 2,000 seeded jobs by default)")
     ap.add_argument("--serving-scale", type=float, default=1.0,
@@ -259,16 +322,12 @@ def main():
                       "overflow": round(ovf_avg_ms, 4)},
         "roofline": roofline,
     }
-    # correctness of the timed configuration: sampled voxels against the oracle
-    import oracle
-    rng = np.random.default_rng(0)
-    vox = np.stack([rng.integers(0, n, 2000) for n in w.n], axis=1)
     lab = job.labels.cpu().numpy()
-    ref, _ = oracle.label_points(oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth),
-                                 w.coords, w.param, vox)
-    got = lab[tuple(vox[:, a] for a in reversed(range(len(w.n))))]
-    out["sampled_parity"] = {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}
-
+    if args.nd:
+        print("[bench] general-dimension kernel (4D)", file=sys.stderr, flush=True)
+        g = general_path(ctx, max(args.steps // 4, 2), 1)
+        nd_labels = g.pop("labels")
+        out["general_path"] = g
     if not args.no_serving:
         from paper_2201_13234_amd import serve
         print(f"[bench] serving replay ({args.serving_jobs} jobs)", file=sys.stderr, flush=True)
@@ -277,7 +336,9 @@ def main():
                                                              flush=True))
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, lab)
+        if args.nd:
+            out["cpu_baseline"]["general_path_sampled_parity"] = nd_sampled_parity(nd_labels)
     ctx.close()
     print(json.dumps(out), flush=True)
 
