@@ -21,9 +21,9 @@ MAX_DIM = 6
 
 class Problem(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("kind", ctypes.c_int32),
-                ("periodic", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("lattice", ctypes.c_int32),
                 ("n", ctypes.c_int64 * MAX_DIM), ("L", ctypes.c_double * MAX_DIM),
-                ("growth", ctypes.c_double)]
+                ("growth", ctypes.c_double), ("periods", ctypes.c_double * (MAX_DIM * MAX_DIM))]
 
 
 class Stats(ctypes.Structure):
@@ -61,8 +61,10 @@ def lib():
     return _lib
 
 
-def problem(n, L, kind=VORONOI, periodic=True, growth=1.0):
-    """Problem statement: n voxels and lengths L per axis (1 to 6 entries)."""
+def problem(n, L, kind=VORONOI, periodic=True, growth=1.0, periods=None):
+    """Problem statement: n voxels and lengths L per axis (1 to 6 entries).
+    periods (optional, d x d, row i = period vector L_i): general periodic
+    cell (App. A); L is then ignored and the boundaries are periodic."""
     n = list(n)
     L = list(L)
     if len(n) != len(L) or not 1 <= len(n) <= MAX_DIM:
@@ -75,6 +77,14 @@ def problem(n, L, kind=VORONOI, periodic=True, growth=1.0):
         p.n[a] = int(n[a]) if a < len(n) else 1
         p.L[a] = float(L[a]) if a < len(L) else 1.0
     p.growth = float(growth)
+    if periods is not None:
+        P = np.asarray(periods, dtype=np.float64)
+        if P.shape != (len(n), len(n)):
+            raise ValueError("periods must be ndim x ndim")
+        p.lattice = 1
+        p.periodic = 1
+        for k, v in enumerate(P.ravel()):
+            p.periods[k] = float(v)
     return p
 
 

@@ -33,14 +33,67 @@
 #define MAXD VTO_MAX_DIM
 
 typedef struct {
-    int ndim, kind, periodic;
+    int ndim, kind, periodic, lattice;
     int64_t n[MAXD];
     double L[MAXD];
     double h[MAXD];  /* voxel size L_a / n_a */
     double H[MAXD];  /* half period L_a / 2 */
     double G;        /* Johnson-Mehl growth rate */
     int64_t nvox;
+    /* general periods: P[i][a] component a of period vector i; hv[i][a] =
+     * P[i][a] / n_i; Pinv the inverse of the matrix with columns P[i] (used
+     * only to find which translations can be nearest); rown[i] the norm of
+     * row i of Pinv */
+    double P[MAXD][MAXD], hv[MAXD][MAXD], Pinv[MAXD][MAXD], rown[MAXD];
 } geo_t;
+
+/* Inverse of the d x d matrix M (M[a][i] = component a of column i) by
+ * Gauss-Jordan elimination with partial pivoting.  Returns 0 when the matrix
+ * is singular to working precision. */
+static int invert(int d, double M[MAXD][MAXD], double R[MAXD][MAXD])
+{
+    double A[MAXD][2 * MAXD];
+    int r, c, k;
+    double scale = 0.0;
+    for (r = 0; r < d; ++r)
+        for (c = 0; c < d; ++c) {
+            A[r][c] = M[r][c];
+            A[r][d + c] = (r == c) ? 1.0 : 0.0;
+            if (fabs(M[r][c]) > scale)
+                scale = fabs(M[r][c]);
+        }
+    if (!(scale > 0.0) || !isfinite(scale))
+        return 0;
+    for (c = 0; c < d; ++c) {
+        int piv = c;
+        double f;
+        for (r = c + 1; r < d; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c]))
+                piv = r;
+        if (!(fabs(A[piv][c]) > 1e-12 * scale))
+            return 0;
+        if (piv != c)
+            for (k = 0; k < 2 * d; ++k) {
+                double t = A[c][k];
+                A[c][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        f = A[c][c];
+        for (k = 0; k < 2 * d; ++k)
+            A[c][k] /= f;
+        for (r = 0; r < d; ++r) {
+            if (r == c)
+                continue;
+            f = A[r][c];
+            for (k = 0; k < 2 * d; ++k)
+                A[r][k] -= f * A[c][k];
+        }
+    }
+    for (r = 0; r < d; ++r)
+        for (c = 0; c < d; ++c)
+            R[r][c] = A[r][d + c];
+    return 1;
+}
 
 static void geo_init(geo_t* g, const vto_problem* p)
 {
@@ -50,7 +103,25 @@ static void geo_init(geo_t* g, const vto_problem* p)
     g->kind = p->kind;
     g->periodic = p->periodic ? 1 : 0;
     g->G = p->growth;
+    g->lattice = p->lattice ? 1 : 0;
     g->nvox = 1;
+    if (g->lattice) {
+        int i, b;
+        double M[MAXD][MAXD];
+        for (i = 0; i < p->ndim; ++i)
+            for (b = 0; b < p->ndim; ++b) {
+                g->P[i][b] = p->periods[i * p->ndim + b];
+                g->hv[i][b] = g->P[i][b] / (double)p->n[i];
+                M[b][i] = g->P[i][b];
+            }
+        if (invert(p->ndim, M, g->Pinv))
+            for (i = 0; i < p->ndim; ++i) {
+                double r2 = 0.0;
+                for (b = 0; b < p->ndim; ++b)
+                    r2 += g->Pinv[i][b] * g->Pinv[i][b];
+                g->rown[i] = sqrt(r2);
+            }
+    }
     for (a = 0; a < MAXD; ++a) {
         if (a < p->ndim) {
             g->n[a] = p->n[a];
@@ -115,7 +186,7 @@ static const double* prepare_sites(const geo_t* g, int64_t nsites, const double*
 {
     double* c;
     int64_t i;
-    if (!g->periodic)
+    if (!g->periodic || g->lattice)
         return coords;
     c = (double*)malloc((size_t)nsites * (size_t)g->ndim * sizeof(double));
     if (!c)
@@ -139,9 +210,84 @@ static void release_sites(const double* sites, const double* coords)
  *                                                 by the remark of Sec. 3.1)
  *   Laguerre:     q - w_s                        (power distance, Sec. 2.3)
  *   Johnson-Mehl: t_s + sqrt(q) / G              (eq. JMAK2)              */
+/* Squared distance between e = s - x shifted by the translation k (the
+ * definition of eq. L-distance_def for one k), summed as in site_key. */
+static double lattice_q(const geo_t* g, const double* e, const int64_t* k)
+{
+    double d[MAXD] = {0.0}, T, q;
+    int a, i;
+    for (a = 0; a < g->ndim; ++a) {
+        double o = (double)k[0] * g->P[0][a];
+        for (i = 1; i < g->ndim; ++i)
+            o = o + (double)k[i] * g->P[i][a];
+        d[a] = e[a] + o;
+    }
+    if (g->ndim == 1)
+        return d[0] * d[0];
+    T = d[1] * d[1];
+    for (a = 2; a < g->ndim; ++a)
+        T = T + d[a] * d[a];
+    q = d[0] * d[0] + T;
+    return q;
+}
+
+/* General periods: the minimum of lattice_q over every translation k.  Any
+ * k that can reach the minimum satisfies |k_i - g_i| <= |row i of Pinv| *
+ * |d(k0)| with g = Pinv (x - s) and k0 = rint(g), so only the box of those k
+ * (widened for rounding) is searched. */
+static double lattice_min_q(const geo_t* g, const double* s, const double* x)
+{
+    double e[MAXD], gv[MAXD], q0, D0, best;
+    int64_t k0[MAXD], lo[MAXD], hi[MAXD], k[MAXD];
+    int a, i;
+    for (a = 0; a < g->ndim; ++a)
+        e[a] = s[a] - x[a];
+    for (i = 0; i < g->ndim; ++i) {
+        double acc = 0.0;
+        for (a = 0; a < g->ndim; ++a)
+            acc -= g->Pinv[i][a] * e[a];
+        gv[i] = acc;
+        k0[i] = (int64_t)rint(acc);
+    }
+    q0 = lattice_q(g, e, k0);
+    D0 = sqrt(q0);
+    for (i = 0; i < g->ndim; ++i) {
+        double r = g->rown[i] * D0 * (1.0 + 0x1p-20) + 0x1p-30 * (1.0 + fabs(gv[i]));
+        lo[i] = (int64_t)ceil(gv[i] - r);
+        hi[i] = (int64_t)floor(gv[i] + r);
+        if (lo[i] > k0[i])
+            lo[i] = k0[i];
+        if (hi[i] < k0[i])
+            hi[i] = k0[i];
+        k[i] = lo[i];
+    }
+    best = q0;
+    for (;;) {
+        double q = lattice_q(g, e, k);
+        if (q < best)
+            best = q;
+        for (i = 0; i < g->ndim; ++i) {
+            if (++k[i] <= hi[i])
+                break;
+            k[i] = lo[i];
+        }
+        if (i == g->ndim)
+            break;
+    }
+    return best;
+}
+
 static double site_key(const geo_t* g, const double* s, double prm, const double* x)
 {
     double q;
+    if (g->lattice) {
+        q = lattice_min_q(g, s, x);
+        if (g->kind == VTO_LAGUERRE)
+            return q - prm;
+        if (g->kind == VTO_JOHNSON_MEHL)
+            return prm + sqrt(q) / g->G;
+        return q;
+    }
     double d0 = axis_delta(g, 0, s[0], x[0]);
     if (g->ndim == 1) {
         q = d0 * d0;
@@ -194,6 +340,21 @@ int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
         return VTO_ERR_INVALID;
     if (p->kind == VTO_JOHNSON_MEHL && !(isfinite(p->growth) && p->growth > 0.0))
         return VTO_ERR_INVALID;
+    if (p->lattice) {
+        geo_t g;
+        if (!p->periodic)
+            return VTO_ERR_INVALID;
+        for (a = 0; a < p->ndim * p->ndim; ++a)
+            if (!isfinite(p->periods[a]))
+                return VTO_ERR_INVALID;
+        for (a = 0; a < p->ndim; ++a)
+            if (p->n[a] < 1 || p->n[a] > 2147483647LL)
+                return VTO_ERR_INVALID;
+        geo_init(&g, p);
+        for (a = 0; a < p->ndim; ++a)
+            if (!(g.rown[a] > 0.0))
+                return VTO_ERR_INVALID; /* singular period matrix */
+    }
     for (a = 0; a < p->ndim; ++a) {
         if (p->n[a] < 1 || p->n[a] > 2147483647LL)
             return VTO_ERR_INVALID;
@@ -203,6 +364,11 @@ int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
     for (s = 0; s < nsites; ++s) {
         for (a = 0; a < p->ndim; ++a) {
             double c = coords[s * p->ndim + a];
+            if (p->lattice) {
+                if (!isfinite(c))
+                    return VTO_ERR_INPUT;
+                continue;
+            }
             if (p->periodic ? !isfinite(c) : !(c >= 0.0 && c < p->L[a]))
                 return VTO_ERR_INPUT;
         }
@@ -387,13 +553,33 @@ static void brute_voxel(const geo_t* g, int64_t nsites, const double* coords,
     *key = D;
 }
 
+/* Centre of the voxel with index vector k: the orthogonal reading per axis,
+ * or for general periods x_a = sum_i (k_i + 1/2) (L_ia / n_i) in order. */
+static void voxel_at(const geo_t* g, const int64_t* k, double* x)
+{
+    int a, i;
+    if (!g->lattice) {
+        for (a = 0; a < g->ndim; ++a)
+            x[a] = voxel_centre(g, a, k[a]);
+        return;
+    }
+    for (a = 0; a < g->ndim; ++a) {
+        double acc = ((double)k[0] + 0.5) * g->hv[0][a];
+        for (i = 1; i < g->ndim; ++i)
+            acc = acc + ((double)k[i] + 0.5) * g->hv[i][a];
+        x[a] = acc;
+    }
+}
+
 static void voxel_point(const geo_t* g, int64_t lin, double* x)
 {
+    int64_t k[MAXD];
     int a;
     for (a = 0; a < g->ndim; ++a) {
-        x[a] = voxel_centre(g, a, lin % g->n[a]);
+        k[a] = lin % g->n[a];
         lin /= g->n[a];
     }
+    voxel_at(g, k, x);
 }
 
 int vto_brute(const vto_problem* p, int64_t nsites, const double* coords,
@@ -453,9 +639,7 @@ int vto_label_points(const vto_problem* p, int64_t nsites, const double* coords,
     for (i = 0; i < npts; ++i) {
         double x[MAXD], k;
         int32_t l;
-        int a;
-        for (a = 0; a < g.ndim; ++a)
-            x[a] = voxel_centre(&g, a, vox[MAXD * i + a]);
+        voxel_at(&g, vox + MAXD * i, x);
         brute_voxel(&g, nsites, sites, param, x, &l, &k);
         labels[i] = l;
         if (keys_out)
@@ -518,6 +702,19 @@ int vto_tessellate(const vto_problem* p, int64_t nsites, const double* coords,
     if (!labels)
         return VTO_ERR_INVALID;
     geo_init(&g, p);
+    if (g.lattice) {
+        /* general periods: the brute-force definition (the index boxes of
+         * step 1 assume orthogonal periods) */
+        rc = vto_brute(p, nsites, coords, param, nthreads, labels, keys_out);
+        if (rc == VTO_OK && stats) {
+            stats->tau = NAN;
+            stats->n_step1 = 0;
+            stats->n_box = 0;
+            stats->n_out = g.nvox;
+            stats->n_step2 = g.nvox * nsites;
+        }
+        return rc;
+    }
     outer = g.ndim - 1; /* threads own slabs along the slowest axis */
     nthreads = resolve_threads(nthreads);
     for (a = 0; a < g.ndim; ++a)

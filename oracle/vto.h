@@ -36,6 +36,16 @@
  *     defines the L-periodic distance for points outside the unit cell); it
  *     is first brought into [0, L_a) by r = fmod(c, L_a), which is exact,
  *     then r + L_a if r < 0, and 0 if that sum rounds up to L_a;
+ *   - general period vectors L_i (App. A, eq. L-distance_def; lattice = 1):
+ *     the grid covers the cell {sum_i alpha_i L_i, alpha in [0,1)^d}; voxel k
+ *     is centred at x_a = sum_i ((double)k_i + 0.5) * (L_ia / n_i), summed
+ *     over i in order; the squared distance to site s is the minimum over
+ *     all integer k of the folded sum of d_a^2 with
+ *     d_a = (s_a - x_a) + (k_0 L_0a + k_1 L_1a + ...), summed in order.
+ *     Sites are Cartesian, any finite value, not reduced.  With a diagonal
+ *     matrix and sites inside the cell this equals the orthogonal reading
+ *     bit for bit.  Only the brute-force definition is used (the two-step
+ *     algorithm's index boxes assume orthogonal periods);
  *   - labels are 0-based.
  *
  * Precision: all arithmetic is IEEE binary64 with round-to-nearest, no
@@ -61,10 +71,12 @@ typedef struct {
     int32_t ndim;      /* 1 .. VTO_MAX_DIM */
     int32_t kind;      /* VTO_VORONOI, VTO_LAGUERRE or VTO_JOHNSON_MEHL */
     int32_t periodic;  /* 1: L-periodic distance (App. A); 0: Euclidean */
-    int32_t reserved;
+    int32_t lattice;   /* 1: general period vectors in `periods` (needs periodic = 1) */
     int64_t n[VTO_MAX_DIM]; /* voxels per axis; axis 0 fastest in memory; entries >= ndim ignored */
     double  L[VTO_MAX_DIM]; /* domain lengths; entries >= ndim ignored */
     double  growth;    /* Johnson-Mehl growth rate G (= v) > 0; ignored otherwise */
+    double  periods[VTO_MAX_DIM * VTO_MAX_DIM]; /* lattice = 1: periods[i*ndim + a] is
+                                                   component a of period vector L_i */
 } vto_problem;
 
 /* Operation counters of the two-step algorithm (Sec. 3.2.3, Figs. voro4/fdl). */
