@@ -98,6 +98,17 @@ typedef struct {
     const double* param; /* device, [nsites] or NULL for Voronoi */
     int32_t* labels;     /* device, prod(n) int32 */
     double*  keys;       /* device, prod(n) binary64 or NULL: the winning key per voxel */
+    const double* periods; /* host, NULL or [ndim][ndim]: periods[i*ndim + a] is component a of
+                          * period vector L_i (App. A, eq. L-distance_def; needs bc =
+                          * VT_PERIODIC, L is then ignored).  The grid covers the cell
+                          * {sum_i alpha_i L_i, alpha in [0,1)^d}: voxel k is centred at
+                          * x_a = sum_i ((double)k_i + 0.5) * (L_ia / n_i), summed over i in
+                          * order, and q is the minimum over integer translations k of the
+                          * folded sum of d_a^2 with d_a = (s_a - x_a) + (k_0 L_0a + k_1 L_1a
+                          * + ...), summed in order.  Sites are Cartesian, any finite value.
+                          * A diagonal matrix and sites inside the cell give the orthogonal
+                          * result bit for bit.  VT_ERR_INVALID for a singular or non-finite
+                          * matrix.  Always runs the general kernel. */
 } vt_job_nd;
 
 /* Creates a context on HIP device `device`.  Reads a tuning cache from the
@@ -120,9 +131,9 @@ vt_status vt_reserve(vt_ctx* ctx, size_t bytes);
  * context's scratch, which synchronises the device. */
 vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
 
-/* Any dimension from 1 to VT_MAX_DIM.  Jobs with 2 or 3 axes go through
- * vt_tessellate unless flags holds VT_ND_GENERIC; the others (and those
- * with the flag) run the general kernel: a counting sort of the sites into a
+/* Any dimension from 1 to VT_MAX_DIM.  Jobs with 2 or 3 axes and no period
+ * vectors go through vt_tessellate unless flags holds VT_ND_GENERIC; the
+ * others (and those with the flag) run the general kernel: a counting sort of the sites into a
  * d-dimensional bin grid, then per tile of at most 256 voxels a search over
  * rings of bins until the sites beyond them provably lose, and a
  * lexicographic (key, index) minimum over the remaining candidates.  Same

@@ -604,6 +604,54 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
 
 namespace {
 
+// Inverse of the period matrix (columns = period vectors; Pinv[i][a] is
+// fractional coordinate i per Cartesian axis a) by Gauss-Jordan elimination
+// with partial pivoting; *det gets the determinant.  Used only for binning
+// and bounds, so its rounding never reaches a key.  False when singular.
+bool invert_periods(int d, const double* periods, double Pinv[vt::kMaxDim][vt::kMaxDim], double* det)
+{
+    double A[vt::kMaxDim][2 * vt::kMaxDim];
+    double scale = 0.0;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            A[r][c] = periods[c * d + r];  // row r = Cartesian axis, column c = period vector
+            A[r][d + c] = r == c ? 1.0 : 0.0;
+            scale = std::max(scale, std::fabs(A[r][c]));
+        }
+    if (!(scale > 0.0))
+        return false;
+    double dt = 1.0;
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < d; ++r)
+            if (std::fabs(A[r][c]) > std::fabs(A[piv][c]))
+                piv = r;
+        if (!(std::fabs(A[piv][c]) > 1e-12 * scale))
+            return false;
+        if (piv != c) {
+            for (int k = 0; k < 2 * d; ++k)
+                std::swap(A[c][k], A[piv][k]);
+            dt = -dt;
+        }
+        const double f = A[c][c];
+        dt *= f;
+        for (int k = 0; k < 2 * d; ++k)
+            A[c][k] /= f;
+        for (int r = 0; r < d; ++r) {
+            if (r == c)
+                continue;
+            const double g = A[r][c];
+            for (int k = 0; k < 2 * d; ++k)
+                A[r][k] -= g * A[c][k];
+        }
+    }
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c)
+            Pinv[r][c] = A[r][d + c];
+    *det = dt;
+    return true;
+}
+
 // Tile shape of the general kernel: powers of two per axis, at most 256
 // voxels, grown along the axis with the most voxels per tile side.
 void nd_tile_shape(const vt_job_nd* j, int32_t* T)
@@ -656,7 +704,7 @@ vt_status plan_nd(const vt_job_nd* j, vt::NdDev* d)
     for (int a = 0; a < j->ndim; ++a) {
         if (j->n[a] < 1 || j->n[a] > (1 << 30))
             return fail(VT_ERR_INVALID, "n[a] must be in [1, 2^30]");
-        if (!(std::isfinite(j->L[a]) && j->L[a] > 0.0))
+        if (!j->periods && !(std::isfinite(j->L[a]) && j->L[a] > 0.0))
             return fail(VT_ERR_INVALID, "L[a] must be finite and > 0");
         d->n[a] = j->n[a];
         d->L[a] = j->L[a];
@@ -672,12 +720,47 @@ vt_status plan_nd(const vt_job_nd* j, vt::NdDev* d)
     d->rgrowth = 1.0 / d->growth;
     d->jm_div = (j->kind == VT_JOHNSON_MEHL && !is_pow2_scale(d->growth)) ? 1 : 0;
 
+    // General period vectors: bins and tile bounds in fractional
+    // coordinates (period 1 per axis).
+    double extent[VT_MAX_DIM];
+    for (int a = 0; a < j->ndim; ++a)
+        extent[a] = j->L[a];
+    if (j->periods) {
+        const int nd = j->ndim;
+        if (!j->bc)
+            return fail(VT_ERR_INVALID, "period vectors need periodic boundaries");
+        for (int k = 0; k < nd * nd; ++k)
+            if (!std::isfinite(j->periods[k]))
+                return fail(VT_ERR_INVALID, "period vectors must be finite");
+        double det = 0.0;
+        if (!invert_periods(nd, j->periods, d->Pinv, &det))
+            return fail(VT_ERR_INVALID, "period vectors are linearly dependent");
+        d->lattice = 1;
+        d->cell_d = 0.0;
+        for (int i = 0; i < nd; ++i) {
+            double n2 = 0.0, r2 = 0.0;
+            for (int a = 0; a < nd; ++a) {
+                d->P[i][a] = j->periods[i * nd + a];
+                d->hv[i][a] = d->P[i][a] / (double)j->n[i];
+                n2 += d->P[i][a] * d->P[i][a];
+                r2 += d->Pinv[i][a] * d->Pinv[i][a];
+            }
+            d->rown[i] = std::sqrt(r2);
+            d->cell_d += std::sqrt(n2);
+            extent[i] = std::sqrt(n2);
+            d->L[i] = 1.0;
+            d->H[i] = 0.5;
+            d->h[i] = 1.0 / (double)j->n[i];
+        }
+        V = std::fabs(det);
+    }
+
     // Bins: side ~ the mean site spacing (V / N)^(1/d), at most 2^20 per axis
     // and about 4 N + 64 in total.
     const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim);
     int64_t nbins = 1;
     for (int a = 0; a < j->ndim; ++a) {
-        const double f = std::floor(j->L[a] / spacing + 0.5);
+        const double f = std::floor(extent[a] / spacing + 0.5);
         d->nb[a] = (int)std::min(std::max(f, 1.0), (double)(1 << 20));
         nbins *= d->nb[a];
     }
@@ -691,8 +774,8 @@ vt_status plan_nd(const vt_job_nd* j, vt::NdDev* d)
     }
     d->nbins = (int32_t)nbins;
     for (int a = 0; a < j->ndim; ++a) {
-        d->bs[a] = j->L[a] / (double)d->nb[a];
-        d->inv_bs[a] = (double)d->nb[a] / j->L[a];
+        d->bs[a] = d->L[a] / (double)d->nb[a];
+        d->inv_bs[a] = (double)d->nb[a] / d->L[a];
     }
     nd_tile_shape(j, d->T);
     d->ntiles = 1;
@@ -713,7 +796,7 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
 {
     if (!ctx)
         return fail(VT_ERR_INVALID, "ctx is NULL");
-    if (job && (job->ndim == 2 || job->ndim == 3) && !(job->flags & VT_ND_GENERIC)) {
+    if (job && (job->ndim == 2 || job->ndim == 3) && !(job->flags & VT_ND_GENERIC) && !job->periods) {
         if (job->flags & ~VT_ND_GENERIC)
             return fail(VT_ERR_INVALID, "unknown flags");
         vt_job j;
@@ -740,13 +823,14 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
         return st;
     VT_HIP(hipSetDevice(ctx->device));
     Carver c;
-    const size_t o_pbound = c.take<unsigned long long>(2);
+    const size_t o_pbound = c.take<unsigned long long>(3);
     const size_t o_status = c.take<int32_t>(1, 4);
     const size_t o_count = c.take<int32_t>(d.nbins, 4);
     const size_t o_start = c.take<int32_t>((int64_t)d.nbins + 1);
     const size_t o_bin = c.take<int32_t>(d.nsites);
     const size_t o_rank = c.take<int32_t>(d.nsites);
     const size_t o_sc = c.take<double>((int64_t)d.nsites * d.ndim);
+    const size_t o_sf = c.take<double>(d.lattice ? (int64_t)d.nsites * d.ndim : 0);
     const size_t o_sp = c.take<double>(d.nsites);
     const size_t o_sidx = c.take<int32_t>(d.nsites);
     const int64_t partial_cap = vt::scan_partials_needed((int64_t)d.nbins);
@@ -761,6 +845,7 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     d.site_bin = (int32_t*)(base + o_bin);
     d.site_rank = (int32_t*)(base + o_rank);
     d.sc = (double*)(base + o_sc);
+    d.sf = d.lattice ? (double*)(base + o_sf) : nullptr;
     d.sp = (double*)(base + o_sp);
     d.sidx = (int32_t*)(base + o_sidx);
     // pbound, internal status and bin counts are contiguous: zero them

@@ -3,26 +3,34 @@
 // with anisotropic voxels and the same keys as the 2D/3D path:
 //     Voronoi q,  Laguerre q - w_s,  Johnson-Mehl t_s + sqrt(q) / v,
 // q = d0*d0 + T, T = d1*d1, then T + d2*d2, ... over the remaining axes (the
-// 2D and 3D forms are its first cases), minimum-image differences for
-// periodic boundaries (App. A, eq. dL), each operation rounded once.
+// 2D and 3D forms are its first cases), each operation rounded once.
 //
-// Binning: a counting sort into a uniform d-dimensional bin grid (periodic
-// coordinates brought into the unit cell first).
+// Periodic boundaries come in two forms (App. A):
+//   - orthogonal periods L_a: minimum-image differences (eq. dL), sites
+//     brought into the cell first;
+//   - general period vectors L_i (eq. L-distance_def, "lattice"): voxel k is
+//     centred at x_a = sum_i (k_i + 1/2) (L_ia / n_i), and q is the minimum
+//     over integer translations k of the folded sum of d_a^2 with
+//     d_a = (s_a - x_a) + (k_0 L_0a + k_1 L_1a + ...).
+//
+// Binning: a counting sort into a uniform d-dimensional bin grid (in
+// fractional coordinates for general periods).
 //
 // Labelling: one workgroup of 256 threads per tile of at most 256 voxels
 // (powers of two per axis), one voxel per thread.
 //   1. Rings of bins around the tile are visited until every site beyond them
 //      provably loses: UB = the smallest upper bound of a visited site's key
-//      over the tile's box of voxel centres, and the sites outside the visited
-//      box are at least `gap` away along some axis, so their keys exceed
-//      gap^2 (Voronoi), gap^2 - max w (Laguerre), min t + gap / v
-//      (Johnson-Mehl).
+//      over the tile's voxel centres, and the sites outside the visited box
+//      are at least `gap` away, so their keys exceed gap^2 (Voronoi),
+//      gap^2 - max w (Laguerre), min t + gap / v (Johnson-Mehl).
 //   2. The visited sites whose lower bound over the tile is <= UB + M are
-//      staged in LDS and every thread takes the lexicographic minimum of
-//      (key, site index) over them: the brute-force result with ties to the
-//      lowest index, whatever the order of the candidates.
+//      staged in LDS (for general periods with the box of translations that
+//      can bring them within reach) and every thread takes the lexicographic
+//      minimum of (key, site index) over them: the brute-force result with
+//      ties to the lowest index, whatever the order of the candidates.
 // M = 2^-36 of the key scale, far above the rounding error of any bound or
-// key, so a dropped site's computed key is strictly above the winner's.
+// key, so a dropped site's (or translation's) computed key is strictly
+// above the winner's.
 #include "vt_internal.h"
 
 namespace vt {
@@ -45,27 +53,61 @@ __device__ inline double nd_from_ordered(unsigned long long u)
     return __longlong_as_double((long long)b);
 }
 
+__device__ inline unsigned long long wave_max_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Fractional coordinate i of Cartesian point s (general periods).
+__device__ inline double frac_coord(const NdDev& J, int nd, const double* s, int i)
+{
+    double f = 0.0;
+    for (int a = 0; a < nd; ++a)
+        f += J.Pinv[i][a] * s[a];
+    return f;
+}
+
 // ------------------------------------------------------------------ binning
 
 __global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
 {
     const int64_t i = blockIdx.x * (int64_t)NDT + threadIdx.x;
     const bool live = i < J.nsites;
-    unsigned long long hi = 0ull, lo = 0ull;
+    unsigned long long hi = 0ull, lo = 0ull, mag = 0ull;
     if (live) {
         const int nd = J.ndim;
         bool ok = true;
         int64_t lin = 0, stride = 1;
+        double s[kMaxDim];
         for (int a = 0; a < nd; ++a) {
-            double c = J.coords[i * nd + a];
-            if (J.bc && isfinite(c))
-                c = cell_coord(c, J.L[a]);
+            s[a] = J.coords[i * nd + a];
+            ok = ok && isfinite(s[a]);
+        }
+        for (int a = 0; a < nd; ++a) {
             int b = 0;
-            if (!(c >= 0.0 && c < J.L[a])) {
-                ok = false;
+            if (J.lattice) {
+                if (ok) {
+                    const double f = frac_coord(J, nd, s, a);
+                    const double r = f - floor(f);
+                    const int v = (int)(r * J.inv_bs[a]);
+                    b = v < 0 ? 0 : (v >= J.nb[a] ? J.nb[a] - 1 : v);
+                    const unsigned long long m = nd_ordered(fabs(s[a]));
+                    mag = m > mag ? m : mag;
+                }
             } else {
-                const int v = (int)(c * J.inv_bs[a]);
-                b = v < 0 ? 0 : (v >= J.nb[a] ? J.nb[a] - 1 : v);
+                double c = s[a];
+                if (J.bc && isfinite(c))
+                    c = cell_coord(c, J.L[a]);
+                if (!(c >= 0.0 && c < J.L[a])) {
+                    ok = false;
+                } else {
+                    const int v = (int)(c * J.inv_bs[a]);
+                    b = v < 0 ? 0 : (v >= J.nb[a] ? J.nb[a] - 1 : v);
+                }
             }
             lin += b * stride;
             stride *= J.nb[a];
@@ -81,25 +123,23 @@ __global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
         }
         if (!ok) {
             lin = 0;
-            hi = lo = 0ull;
+            hi = lo = mag = 0ull;
             atomicOr(J.status, ST_INPUT);
         }
         J.site_bin[i] = (int32_t)lin;
         J.site_rank[i] = atomicAdd(&J.bin_count[lin], 1);
     }
-    if (J.kind == KIND_VORONOI)
-        return;
-    // parameter bounds: reduce over the wavefront, one atomic per wavefront
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
-        hi = h2 > hi ? h2 : hi;
-        lo = l2 > lo ? l2 : lo;
-    }
+    // parameter and coordinate bounds: one atomic per wavefront
+    hi = wave_max_u64(hi);
+    lo = wave_max_u64(lo);
+    mag = wave_max_u64(mag);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         if (hi)
             atomicMax(&J.pbound[0], hi);
         if (lo)
             atomicMax(&J.pbound[1], lo);
+        if (mag)
+            atomicMax(&J.pbound[2], mag);
     }
 }
 
@@ -110,9 +150,16 @@ __global__ __launch_bounds__(NDT) void k_nd_scatter(NdDev J)
         return;
     const int nd = J.ndim;
     const int64_t pos = J.bin_start[J.site_bin[i]] + J.site_rank[i];
+    double s[kMaxDim];
+    for (int a = 0; a < nd; ++a)
+        s[a] = J.coords[i * nd + a];
     for (int a = 0; a < nd; ++a) {
-        const double c = J.coords[i * nd + a];
-        J.sc[pos * nd + a] = J.bc ? cell_coord(c, J.L[a]) : c;
+        if (J.lattice) {
+            J.sc[pos * nd + a] = s[a];
+            J.sf[pos * nd + a] = frac_coord(J, nd, s, a);
+        } else {
+            J.sc[pos * nd + a] = J.bc ? cell_coord(s[a], J.L[a]) : s[a];
+        }
     }
     J.sp[pos] = J.kind != KIND_VORONOI ? J.param[i] : 0.0;
     J.sidx[pos] = (int32_t)i;
@@ -126,8 +173,13 @@ struct NdConst {
     double rv;         // 1 / v
 };
 
+// Staged candidates.  For general periods each carries the box of
+// translations k (first value and count per axis) to evaluate.
+template <int D, bool LAT>
 struct NdLds {
-    double c[kMaxDim][ND_CAP];
+    double c[D][ND_CAP];
+    double klo[LAT ? D : 1][LAT ? ND_CAP : 1];
+    int32_t kn[LAT ? D : 1][LAT ? ND_CAP : 1];
     double p[ND_CAP];
     int32_t idx[ND_CAP];
     int32_t count;
@@ -135,7 +187,8 @@ struct NdLds {
     int32_t ired[NDT / WAVE];
 };
 
-__device__ inline double block_min(double v, NdLds& S)
+template <class L>
+__device__ inline double block_min(double v, L& S)
 {
     for (int o = 32; o > 0; o >>= 1)
         v = fmin(v, __shfl_xor(v, o));
@@ -149,7 +202,8 @@ __device__ inline double block_min(double v, NdLds& S)
     return r;
 }
 
-__device__ inline int block_max_int(int v, NdLds& S)
+template <class L>
+__device__ inline int block_max_int(int v, L& S)
 {
     for (int o = 32; o > 0; o >>= 1)
         v = max(v, __shfl_xor(v, o));
@@ -163,30 +217,48 @@ __device__ inline int block_max_int(int v, NdLds& S)
     return r;
 }
 
-// Bounds of the key of the sorted site `pos` over the tile's box of voxel
-// centres [lo, hi]: per axis the smallest and largest (minimum-image)
-// distance to the box, then the key of the kind.
-template <int KIND, int DIM>
-__device__ inline void site_bounds(const NdDev& J, const NdConst& C, int64_t pos, const double* lo,
-                                   const double* hi, double& kl, double& ku)
+// Key of a squared distance q (bounds only: Johnson-Mehl through 1/v).
+template <int KIND>
+__device__ inline double key_of_q(double q, double p, const NdConst& C)
 {
-    const int nd = DIM;
+    if (KIND == KIND_VORONOI)
+        return q;
+    if (KIND == KIND_LAGUERRE)
+        return q - p;
+    return p + sqrt(q) * C.rv;
+}
+
+// What the bounds need of a tile.
+template <int D>
+struct NdTile {
+    double lo[D], hi[D];     // orthogonal: box of voxel centres; lattice: fractional box
+    double blo[D], bhi[D];   // lattice: Cartesian bounding box of the voxel centres
+    double cen[D];           // lattice: fractional centre
+};
+
+// Bounds of the key of the sorted site `pos` over the tile (orthogonal
+// periods or none): per axis the smallest and largest (minimum-image)
+// distance to the box of voxel centres, then the key of the kind.
+template <int KIND, int DIM>
+__device__ inline void site_bounds(const NdDev& J, const NdConst& C, int64_t pos, const NdTile<DIM>& G,
+                                   double& kl, double& ku)
+{
     double lq = 0.0, uq = 0.0;
 #pragma unroll
-    for (int a = 0; a < nd; ++a) {
-        const double s = J.sc[pos * nd + a];
+    for (int a = 0; a < DIM; ++a) {
+        const double s = J.sc[pos * DIM + a];
         double dmin, dmax;
         if (!J.bc) {
-            dmin = fmax(0.0, fmax(lo[a] - s, s - hi[a]));
-            dmax = fmax(fabs(s - lo[a]), fabs(s - hi[a]));
+            dmin = fmax(0.0, fmax(G.lo[a] - s, s - G.hi[a]));
+            dmax = fmax(fabs(s - G.lo[a]), fabs(s - G.hi[a]));
         } else {
             // images s - L, s, s + L cover every voxel centre of the cell
             dmin = __builtin_inf();
             dmax = __builtin_inf();
             for (int k = -1; k <= 1; ++k) {
                 const double sk = s + (double)k * J.L[a];
-                dmin = fmin(dmin, fmax(0.0, fmax(lo[a] - sk, sk - hi[a])));
-                dmax = fmin(dmax, fmax(fabs(sk - lo[a]), fabs(sk - hi[a])));
+                dmin = fmin(dmin, fmax(0.0, fmax(G.lo[a] - sk, sk - G.hi[a])));
+                dmax = fmin(dmax, fmax(fabs(sk - G.lo[a]), fabs(sk - G.hi[a])));
             }
             dmax = fmin(dmax, J.H[a]);
         }
@@ -194,16 +266,52 @@ __device__ inline void site_bounds(const NdDev& J, const NdConst& C, int64_t pos
         uq += dmax * dmax;
     }
     const double p = J.sp[pos];
-    if (KIND == KIND_VORONOI) {
-        kl = lq;
-        ku = uq;
-    } else if (KIND == KIND_LAGUERRE) {
-        kl = lq - p;
-        ku = uq - p;
-    } else {
-        kl = p + sqrt(lq) * C.rv;
-        ku = p + sqrt(uq) * C.rv;
+    kl = key_of_q<KIND>(lq, p, C);
+    ku = key_of_q<KIND>(uq, p, C);
+}
+
+// Cartesian image of sorted site `pos` under translation k (approximate:
+// bounds only).
+template <int DIM>
+__device__ inline void lattice_image(const NdDev& J, int64_t pos, const double* k, double* img)
+{
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double o = 0.0;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+            o += k[i] * J.P[i][a];
+        img[a] = J.sc[pos * DIM + a] + o;
     }
+}
+
+// Squared distance bounds between a point and the tile's Cartesian box.
+template <int DIM>
+__device__ inline void box_q(const NdTile<DIM>& G, const double* y, double& lq, double& uq)
+{
+    lq = 0.0;
+    uq = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double dmin = fmax(0.0, fmax(G.blo[a] - y[a], y[a] - G.bhi[a]));
+        const double dmax = fmax(fabs(y[a] - G.blo[a]), fabs(y[a] - G.bhi[a]));
+        lq += dmin * dmin;
+        uq += dmax * dmax;
+    }
+}
+
+// General periods: upper bound of the key of sorted site `pos` over the tile,
+// through the translation that brings it nearest the tile's centre.
+template <int KIND, int DIM>
+__device__ inline double lattice_upper(const NdDev& J, const NdConst& C, int64_t pos, const NdTile<DIM>& G)
+{
+    double k[DIM], img[DIM], lq, uq;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+        k[i] = rint(G.cen[i] - J.sf[pos * DIM + i]);
+    lattice_image<DIM>(J, pos, k, img);
+    box_q<DIM>(G, img, lq, uq);
+    return key_of_q<KIND>(uq, J.sp[pos], C);
 }
 
 // The visited bin box of ring r around the tile's bins [bl, bh]: per axis the
@@ -267,10 +375,12 @@ __device__ inline int64_t box_bin(const NdDev& J, const NdBox& B, int64_t j, con
     return lin;
 }
 
-// Smallest distance from the tile's box to a site outside the visited box
-// (infinite once every site has been visited).
-template <int DIM>
-__device__ inline double outside_gap(const NdDev& J, const NdBox& B, const double* lo, const double* hi)
+// Smallest distance from the tile to a site outside the visited box
+// (infinite once every site has been visited).  General periods: a
+// fractional gap gamma along axis i is at least gamma / |row i of Pinv| in
+// Cartesian distance.
+template <int DIM, bool LAT>
+__device__ inline double outside_gap(const NdDev& J, const NdBox& B, const NdTile<DIM>& G)
 {
     double g = __builtin_inf();
 #pragma unroll
@@ -278,42 +388,85 @@ __device__ inline double outside_gap(const NdDev& J, const NdBox& B, const doubl
         if (J.bc) {
             if (B.full[a])
                 continue;
-            const double low = lo[a] - (double)B.first[a] * J.bs[a];
-            const double high = (double)(B.first[a] + B.width[a]) * J.bs[a] - hi[a];
-            g = fmin(g, fmin(low, high));
+            const double low = G.lo[a] - (double)B.first[a] * J.bs[a];
+            const double high = (double)(B.first[a] + B.width[a]) * J.bs[a] - G.hi[a];
+            const double ga = fmax(fmin(low, high), 0.0);
+            g = fmin(g, LAT ? ga / J.rown[a] : ga);
         } else {
             if (B.first[a] > 0)
-                g = fmin(g, lo[a] - (double)B.first[a] * J.bs[a]);
+                g = fmin(g, G.lo[a] - (double)B.first[a] * J.bs[a]);
             if (B.first[a] + B.width[a] < J.nb[a])
-                g = fmin(g, (double)(B.first[a] + B.width[a]) * J.bs[a] - hi[a]);
+                g = fmin(g, (double)(B.first[a] + B.width[a]) * J.bs[a] - G.hi[a]);
         }
     }
     return fmax(g, 0.0);
 }
 
-// The exact key of a staged candidate at voxel centre x (same operations as
-// the problem's definition; see the file comment).
-template <int KIND, int DIM>
-__device__ inline double nd_key(const NdDev& J, const NdLds& S, int k, const double* x)
+// The exact key of staged candidate k at voxel centre x (the operations of
+// the definition in the file comment).
+template <int KIND, int DIM, bool LAT>
+__device__ inline double nd_key(const NdDev& J, const NdLds<DIM, LAT>& S, int k, const double* x)
 {
-    const int nd = DIM;
-    double d = S.c[0][k] - x[0];
-    if (J.bc)
-        d = d >= J.H[0] ? d - J.L[0] : (d < -J.H[0] ? d + J.L[0] : d);
-    double q = d * d;
-    if (nd > 1) {
-        double e = S.c[1][k] - x[1];
-        if (J.bc)
-            e = e >= J.H[1] ? e - J.L[1] : (e < -J.H[1] ? e + J.L[1] : e);
-        double T = e * e;
+    double q;
+    if (!LAT) {
+        double d[DIM];
 #pragma unroll
-        for (int a = 2; a < nd; ++a) {
-            double f = S.c[a][k] - x[a];
+        for (int a = 0; a < DIM; ++a) {
+            double e = S.c[a][k] - x[a];
             if (J.bc)
-                f = f >= J.H[a] ? f - J.L[a] : (f < -J.H[a] ? f + J.L[a] : f);
-            T = T + f * f;
+                e = e >= J.H[a] ? e - J.L[a] : (e < -J.H[a] ? e + J.L[a] : e);
+            d[a] = e;
         }
-        q = q + T;
+        q = d[0] * d[0];
+        if (DIM > 1) {
+            double T = d[1] * d[1];
+#pragma unroll
+            for (int a = 2; a < DIM; ++a)
+                T = T + d[a] * d[a];
+            q = q + T;
+        }
+    } else {
+        double e[DIM], kk[DIM];
+        int cnt[DIM];
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            e[a] = S.c[a][k] - x[a];
+            kk[a] = S.klo[LAT ? a : 0][LAT ? k : 0];
+            cnt[a] = 0;
+        }
+        q = __builtin_inf();
+        for (;;) {
+            double d[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                double o = kk[0] * J.P[0][a];
+#pragma unroll
+                for (int i = 1; i < DIM; ++i)
+                    o = o + kk[i] * J.P[i][a];
+                d[a] = e[a] + o;
+            }
+            double qk = d[0] * d[0];
+            if (DIM > 1) {
+                double T = d[1] * d[1];
+#pragma unroll
+                for (int a = 2; a < DIM; ++a)
+                    T = T + d[a] * d[a];
+                qk = qk + T;
+            }
+            q = fmin(q, qk);
+            // next translation of the box (the same for every thread)
+            int i = 0;
+            for (; i < DIM; ++i) {
+                if (++cnt[i] < S.kn[LAT ? i : 0][LAT ? k : 0]) {
+                    kk[i] += 1.0;
+                    break;
+                }
+                cnt[i] = 0;
+                kk[i] = S.klo[LAT ? i : 0][LAT ? k : 0];
+            }
+            if (i == DIM)
+                break;
+        }
     }
     const double p = S.p[k];
     if (KIND == KIND_VORONOI)
@@ -323,12 +476,12 @@ __device__ inline double nd_key(const NdDev& J, const NdLds& S, int k, const dou
     return J.jm_div ? p + key_sqrt(q) / J.growth : p + key_sqrt(q) * J.rgrowth;
 }
 
-template <int KIND, int DIM>
-__device__ inline void nd_evaluate(const NdDev& J, const NdLds& S, int count, const double* x, double& best,
-                                   int& blab)
+template <int KIND, int DIM, bool LAT>
+__device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int count, const double* x,
+                                   double& best, int& blab)
 {
     for (int k = 0; k < count; ++k) {
-        const double key = nd_key<KIND, DIM>(J, S, k, x);
+        const double key = nd_key<KIND, DIM, LAT>(J, S, k, x);
         const int id = S.idx[k];
         if (key < best || (key == best && id < blab)) {
             best = key;
@@ -337,54 +490,169 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds& S, int count, co
     }
 }
 
+// General periods: the box of translations k that can bring sorted site
+// `pos` within key `cut` of the tile.  Returns false when none can.
 template <int KIND, int DIM>
+__device__ inline bool lattice_reach(const NdDev& J, const NdConst& C, int64_t pos, const NdTile<DIM>& G,
+                                     double cut, double* klo, int* kn)
+{
+    const double p = J.sp[pos];
+    double qmax;  // largest squared distance at which the key stays <= cut
+    if (KIND == KIND_VORONOI)
+        qmax = cut;
+    else if (KIND == KIND_LAGUERRE)
+        qmax = cut + p;
+    else
+        qmax = cut >= p ? ((cut - p) * J.growth) * ((cut - p) * J.growth) : -1.0;
+    if (!(qmax >= 0.0))
+        return false;
+    const double R = sqrt(qmax) * (1.0 + 0x1p-20);
+    double lo[DIM];
+    int64_t total = 1;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        const double f = J.sf[pos * DIM + i];
+        const double rho = R * J.rown[i] * (1.0 + 0x1p-20) + 0x1p-30 * (1.0 + fabs(f));
+        const double a = ceil(G.lo[i] - rho - f), b = floor(G.hi[i] + rho - f);
+        if (a > b)
+            return false;
+        lo[i] = a;
+        kn[i] = (int)fmin(b - a + 1.0, 1048576.0);
+        total = total * kn[i] < ((int64_t)1 << 40) ? total * kn[i] : ((int64_t)1 << 40);
+    }
+    // keep only the translations whose image can come within reach of the
+    // tile's box; when the box is large, keep it whole
+    if (total <= 4096) {
+        double nlo[DIM], nhi[DIM], k[DIM];
+        int cnt[DIM];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            cnt[i] = 0;
+            k[i] = lo[i];
+            nlo[i] = __builtin_inf();
+            nhi[i] = -__builtin_inf();
+        }
+        for (;;) {
+            double img[DIM], lq, uq;
+            lattice_image<DIM>(J, pos, k, img);
+            box_q<DIM>(G, img, lq, uq);
+            if (key_of_q<KIND>(lq, p, C) <= cut + C.M) {
+                any = true;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    nlo[i] = fmin(nlo[i], k[i]);
+                    nhi[i] = fmax(nhi[i], k[i]);
+                }
+            }
+            int i = 0;
+            for (; i < DIM; ++i) {
+                if (++cnt[i] < kn[i]) {
+                    k[i] += 1.0;
+                    break;
+                }
+                cnt[i] = 0;
+                k[i] = lo[i];
+            }
+            if (i == DIM)
+                break;
+        }
+        if (!any)
+            return false;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            lo[i] = nlo[i];
+            kn[i] = (int)(nhi[i] - nlo[i] + 1.0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+        klo[i] = lo[i];
+    return true;
+}
+
+template <int KIND, int DIM, bool LAT>
 __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
 {
-    __shared__ NdLds S;
+    __shared__ NdLds<DIM, LAT> S;
     const int tid = threadIdx.x;
-    const int nd = DIM;
     const bool bad = *(volatile int32_t*)J.status != 0;
     NdConst C;
     {
-        double sumL2 = 0.0;
-        for (int a = 0; a < nd; ++a)
-            sumL2 += J.L[a] * J.L[a];
         C.rv = J.rgrowth;
         C.pmax = C.pmin = 0.0;
         if (KIND != KIND_VORONOI && !bad) {
             C.pmax = nd_from_ordered(J.pbound[0]);
             C.pmin = -nd_from_ordered(J.pbound[1]);
         }
+        double S2;  // squared length scale of the computed differences
+        if (LAT) {
+            const double mag = bad ? 0.0 : nd_from_ordered(J.pbound[2]);
+            const double D = sqrt((double)DIM) * (2.0 * mag + 3.0 * J.cell_d);
+            S2 = D * D;
+        } else {
+            S2 = 0.0;
+            for (int a = 0; a < DIM; ++a)
+                S2 += J.L[a] * J.L[a];
+        }
         const double pabs = fmax(fabs(C.pmax), fabs(C.pmin));
-        const double scale = KIND == KIND_VORONOI ? sumL2
-                           : KIND == KIND_LAGUERRE ? sumL2 + 2.0 * pabs
-                                                   : sqrt(sumL2) * C.rv + 2.0 * pabs;
+        const double scale = KIND == KIND_VORONOI ? S2
+                           : KIND == KIND_LAGUERRE ? S2 + 2.0 * pabs
+                                                   : sqrt(S2) * C.rv + 2.0 * pabs;
         C.M = scale * 0x1p-36;
     }
     for (int64_t t = blockIdx.x; t < J.ntiles; t += gridDim.x) {
-        // the tile: voxels [v0, ve] per axis; centres [lo, hi]
-        int64_t v0[kMaxDim], ve[kMaxDim], vi[kMaxDim];
-        double lo[kMaxDim], hi[kMaxDim], x[kMaxDim];
-        int bl[kMaxDim], bh[kMaxDim];
+        int64_t v0[DIM], ve[DIM], vi[DIM];
+        double x[DIM];
+        int bl[DIM], bh[DIM];
+        NdTile<DIM> G;
         int64_t rem = t;
         int l = tid;
         bool live = true;
 #pragma unroll
-        for (int a = 0; a < nd; ++a) {
+        for (int a = 0; a < DIM; ++a) {
             const int64_t tc = rem % J.nt[a];
             rem /= J.nt[a];
             v0[a] = tc * J.T[a];
             ve[a] = (v0[a] + J.T[a] < J.n[a] ? v0[a] + J.T[a] : J.n[a]) - 1;
-            lo[a] = ((double)v0[a] + 0.5) * J.h[a];
-            hi[a] = ((double)ve[a] + 0.5) * J.h[a];
             const int off = l % J.T[a];
             l /= J.T[a];
             vi[a] = v0[a] + off;
             live = live && vi[a] <= ve[a];
-            x[a] = ((double)vi[a] + 0.5) * J.h[a];
-            const int b0 = (int)(lo[a] * J.inv_bs[a]), b1 = (int)(hi[a] * J.inv_bs[a]);
+            if (LAT) {
+                G.lo[a] = ((double)v0[a] + 0.5) / (double)J.n[a];
+                G.hi[a] = ((double)ve[a] + 0.5) / (double)J.n[a];
+                G.cen[a] = 0.5 * (G.lo[a] + G.hi[a]);
+            } else {
+                G.lo[a] = ((double)v0[a] + 0.5) * J.h[a];
+                G.hi[a] = ((double)ve[a] + 0.5) * J.h[a];
+                x[a] = ((double)vi[a] + 0.5) * J.h[a];
+            }
+            const int b0 = (int)(G.lo[a] * J.inv_bs[a]), b1 = (int)(G.hi[a] * J.inv_bs[a]);
             bl[a] = min(max(b0, 0), J.nb[a] - 1);
             bh[a] = min(max(b1, 0), J.nb[a] - 1);
+        }
+        if (LAT) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                // the voxel centre, summed as the definition sums it
+                double acc = ((double)vi[0] + 0.5) * J.hv[0][a];
+#pragma unroll
+                for (int i = 1; i < DIM; ++i)
+                    acc = acc + ((double)vi[i] + 0.5) * J.hv[i][a];
+                x[a] = acc;
+                // bounding box of the tile's centres, term by term
+                double b0 = 0.0, b1 = 0.0;
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    const double t0 = ((double)v0[i] + 0.5) * J.hv[i][a];
+                    const double t1 = ((double)ve[i] + 0.5) * J.hv[i][a];
+                    b0 += fmin(t0, t1);
+                    b1 += fmax(t0, t1);
+                }
+                G.blo[a] = b0;
+                G.bhi[a] = b1;
+            }
         }
         live = live && l == 0;
         double best = __builtin_inf();
@@ -403,13 +671,17 @@ __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
                         continue;
                     const int s1 = J.bin_start[lin + 1];
                     for (int s = J.bin_start[lin]; s < s1; ++s) {
-                        double kl, ku;
-                        site_bounds<KIND, DIM>(J, C, s, lo, hi, kl, ku);
-                        my = fmin(my, ku);
+                        if (LAT) {
+                            my = fmin(my, lattice_upper<KIND, DIM>(J, C, s, G));
+                        } else {
+                            double kl, ku;
+                            site_bounds<KIND, DIM>(J, C, s, G, kl, ku);
+                            my = fmin(my, ku);
+                        }
                     }
                 }
                 UB = fmin(UB, block_min(my, S));
-                const double g = outside_gap<DIM>(J, B, lo, hi);
+                const double g = outside_gap<DIM, LAT>(J, B, G);
                 if (g == __builtin_inf())
                     break;
                 const double lb_out = KIND == KIND_VORONOI ? g * g
@@ -439,13 +711,28 @@ __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
                 for (int k = 0; k < rounds; ++k) {
                     if (s0 + k < s1) {
                         const int s = s0 + k;
-                        double kl, ku;
-                        site_bounds<KIND, DIM>(J, C, s, lo, hi, kl, ku);
-                        if (kl <= cut) {
+                        bool keep;
+                        double klo[DIM];
+                        int kn[DIM];
+                        if (LAT) {
+                            keep = lattice_reach<KIND, DIM>(J, C, s, G, cut, klo, kn);
+                        } else {
+                            double kl, ku;
+                            site_bounds<KIND, DIM>(J, C, s, G, kl, ku);
+                            keep = kl <= cut;
+                        }
+                        if (keep) {
                             const int slot = atomicAdd(&S.count, 1);
 #pragma unroll
-                            for (int a = 0; a < nd; ++a)
-                                S.c[a][slot] = J.sc[(int64_t)s * nd + a];
+                            for (int a = 0; a < DIM; ++a)
+                                S.c[a][slot] = J.sc[(int64_t)s * DIM + a];
+                            if (LAT) {
+#pragma unroll
+                                for (int a = 0; a < DIM; ++a) {
+                                    S.klo[LAT ? a : 0][LAT ? slot : 0] = klo[a];
+                                    S.kn[LAT ? a : 0][LAT ? slot : 0] = kn[a];
+                                }
+                            }
                             S.p[slot] = J.sp[s];
                             S.idx[slot] = J.sidx[s];
                         }
@@ -455,7 +742,7 @@ __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
                         if (live)
-                            nd_evaluate<KIND, DIM>(J, S, cnt, x, best, blab);
+                            nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, best, blab);
                         __syncthreads();
                         if (tid == 0)
                             S.count = 0;
@@ -465,13 +752,13 @@ __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
             }
             const int cnt = S.count;
             if (live && cnt > 0)
-                nd_evaluate<KIND, DIM>(J, S, cnt, x, best, blab);
+                nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, best, blab);
             __syncthreads();
         }
         if (live) {
             int64_t lin = 0, stride = 1;
 #pragma unroll
-            for (int a = 0; a < nd; ++a) {
+            for (int a = 0; a < DIM; ++a) {
                 lin += vi[a] * stride;
                 stride *= J.n[a];
             }
@@ -480,6 +767,32 @@ __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
                 J.keys[lin] = bad ? __builtin_nan("") : best;
         }
     }
+}
+
+template <int DIM, bool LAT>
+void launch_nd_dim(const NdDev& J, unsigned g, hipStream_t s)
+{
+    if (J.kind == KIND_VORONOI)
+        k_nd_label<KIND_VORONOI, DIM, LAT><<<g, NDT, 0, s>>>(J);
+    else if (J.kind == KIND_LAGUERRE)
+        k_nd_label<KIND_LAGUERRE, DIM, LAT><<<g, NDT, 0, s>>>(J);
+    else
+        k_nd_label<KIND_JM, DIM, LAT><<<g, NDT, 0, s>>>(J);
+}
+
+template <bool LAT>
+hipError_t launch_nd_lat(const NdDev& J, unsigned g, hipStream_t s)
+{
+    switch (J.ndim) {
+    case 1: launch_nd_dim<1, LAT>(J, g, s); break;
+    case 2: launch_nd_dim<2, LAT>(J, g, s); break;
+    case 3: launch_nd_dim<3, LAT>(J, g, s); break;
+    case 4: launch_nd_dim<4, LAT>(J, g, s); break;
+    case 5: launch_nd_dim<5, LAT>(J, g, s); break;
+    case 6: launch_nd_dim<6, LAT>(J, g, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -498,34 +811,10 @@ hipError_t launch_nd_bin_scatter(const NdDev& J, hipStream_t s)
     return hipGetLastError();
 }
 
-namespace {
-
-template <int DIM>
-void launch_nd_dim(const NdDev& J, unsigned g, hipStream_t s)
-{
-    if (J.kind == KIND_VORONOI)
-        k_nd_label<KIND_VORONOI, DIM><<<g, NDT, 0, s>>>(J);
-    else if (J.kind == KIND_LAGUERRE)
-        k_nd_label<KIND_LAGUERRE, DIM><<<g, NDT, 0, s>>>(J);
-    else
-        k_nd_label<KIND_JM, DIM><<<g, NDT, 0, s>>>(J);
-}
-
-}  // namespace
-
 hipError_t launch_nd_label(const NdDev& J, hipStream_t s)
 {
     const unsigned g = (unsigned)(J.ntiles < kNdGrid ? J.ntiles : kNdGrid);
-    switch (J.ndim) {
-    case 1: launch_nd_dim<1>(J, g, s); break;
-    case 2: launch_nd_dim<2>(J, g, s); break;
-    case 3: launch_nd_dim<3>(J, g, s); break;
-    case 4: launch_nd_dim<4>(J, g, s); break;
-    case 5: launch_nd_dim<5>(J, g, s); break;
-    case 6: launch_nd_dim<6>(J, g, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return J.lattice ? launch_nd_lat<true>(J, g, s) : launch_nd_lat<false>(J, g, s);
 }
 
 }  // namespace vt

@@ -123,6 +123,15 @@ struct NdDev {
     double L[kMaxDim], h[kMaxDim], H[kMaxDim];
     double bs[kMaxDim], inv_bs[kMaxDim];
     double growth, rgrowth;
+    // General period vectors (lattice != 0; App. A, eq. L-distance_def).  The
+    // bins, L, H, bs and inv_bs above then live in fractional coordinates
+    // (period 1 per axis).
+    int32_t lattice, pad2;
+    double P[kMaxDim][kMaxDim];    // P[i][a]: component a of period vector i
+    double hv[kMaxDim][kMaxDim];   // P[i][a] / n_i: voxel steps
+    double Pinv[kMaxDim][kMaxDim]; // Pinv[i][a]: fractional coordinate i per Cartesian a
+    double rown[kMaxDim];          // norm of row i of Pinv
+    double cell_d;                 // sum of |P_i|
     const double* coords;          // [nsites][ndim], caller input
     const double* param;           // [nsites] or null
     int32_t* labels;               // caller output
@@ -132,10 +141,11 @@ struct NdDev {
     int32_t* bin_start;            // [nbins + 1]
     int32_t* site_bin;             // [nsites]
     int32_t* site_rank;            // [nsites]
-    double* sc;                    // [nsites][ndim] sorted coordinates, inside the cell
+    double* sc;                    // [nsites][ndim] sorted coordinates (inside the cell unless lattice)
+    double* sf;                    // [nsites][ndim] sorted fractional coordinates (lattice only)
     double* sp;                    // [nsites] sorted parameters
     int32_t* sidx;                 // sorted -> input index
-    unsigned long long* pbound;    // [2]: ordered bits of max(param), max(-param)
+    unsigned long long* pbound;    // [3]: ordered bits of max(param), max(-param), max |coordinate|
 };
 
 hipError_t launch_nd_bin_count(const NdDev& J, hipStream_t s);

@@ -41,7 +41,7 @@ class VtJobNd(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("n", ctypes.c_int64 * MAX_DIM), ("L", ctypes.c_double * MAX_DIM),
                 ("growth", ctypes.c_double), ("nsites", ctypes.c_int64),
                 ("coords", ctypes.c_void_p), ("param", ctypes.c_void_p), ("labels", ctypes.c_void_p),
-                ("keys", ctypes.c_void_p)]
+                ("keys", ctypes.c_void_p), ("periods", ctypes.c_void_p)]
 
 
 class VtError(RuntimeError):
@@ -130,6 +130,7 @@ class Job:
     growth: float = 1.0
     labels: object = None     # torch int32 with prod(n) elements, allocated if None
     keys: object = None       # torch float64 with prod(n) elements for the distance image, or None
+    periods: object = None    # host d x d array-like (row i = period vector L_i) or None
 
     def _check_tensors(self):
         import torch
@@ -150,8 +151,8 @@ class Job:
 
     def to_c(self):
         d = len(self.n)
-        if d not in (2, 3):
-            raise ValueError("vt_job holds 2 or 3 axes; use Context.tessellate_nd")
+        if d not in (2, 3) or self.periods is not None:
+            raise ValueError("vt_job holds 2 or 3 axes and orthogonal periods; use Context.tessellate_nd")
         self._check_tensors()
         j = VtJob()
         j.ndim = d
@@ -188,6 +189,13 @@ class Job:
         j.param = self.param.data_ptr() if self.param is not None else None
         j.labels = self.labels.data_ptr()
         j.keys = self.keys.data_ptr() if self.keys is not None else None
+        j.periods = None
+        if self.periods is not None:
+            flat = [float(v) for row in self.periods for v in row]
+            if len(flat) != d * d:
+                raise ValueError("periods must be ndim x ndim")
+            self._periods_buf = (ctypes.c_double * (d * d))(*flat)   # alive while the job is
+            j.periods = ctypes.cast(self._periods_buf, ctypes.c_void_p).value
         return j
 
 

@@ -61,8 +61,8 @@ def test_job_structs_match_the_c_compiler(tmp_path):
 int main(void) {
     printf("%zu %zu %zu %zu\\n", sizeof(vt_job), offsetof(vt_job, coords), offsetof(vt_job, keys),
            offsetof(vt_job, growth));
-    printf("%zu %zu %zu %zu\\n", sizeof(vt_job_nd), offsetof(vt_job_nd, coords), offsetof(vt_job_nd, keys),
-           offsetof(vt_job_nd, growth));
+    printf("%zu %zu %zu %zu %zu\\n", sizeof(vt_job_nd), offsetof(vt_job_nd, coords), offsetof(vt_job_nd, keys),
+           offsetof(vt_job_nd, growth), offsetof(vt_job_nd, periods));
     return 0;
 }
 """)
@@ -71,10 +71,12 @@ int main(void) {
                    check=True)
     rows = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     for row, S in zip(rows, (vtess.VtJob, vtess.VtJobNd)):
-        size, coords, keys, growth = (int(v) for v in row.split())
-        assert (size, coords, keys, growth) == (ctypes.sizeof(S), S.coords.offset, S.keys.offset,
-                                                S.growth.offset)
-    assert ctypes.sizeof(vtess.VtJobNd) == 16 + 48 + 48 + 8 + 8 + 32
+        got = [int(v) for v in row.split()]
+        want = [ctypes.sizeof(S), S.coords.offset, S.keys.offset, S.growth.offset]
+        if S is vtess.VtJobNd:
+            want.append(S.periods.offset)
+        assert got == want
+    assert ctypes.sizeof(vtess.VtJobNd) == 16 + 48 + 48 + 8 + 8 + 40
 
 
 def test_product_code_never_imports_the_oracle():
