@@ -14,7 +14,8 @@ in HBM.  The line printed at the end also carries
     the host's cores on the same workload, and the device labels of the timed
     configuration checked against the oracle at sampled voxels;
   - general_path (with --nd): the general-dimension kernel on a 4D Voronoi
-    diagram, 64^4 voxels and 16,384 sites;
+    diagram, 64^4 voxels and 16,384 sites, and on a 3D Voronoi diagram of
+    20,000 sites in a triclinic periodic cell (128^3 voxels);
   - serving: a short request stream replayed through the continuous-batching
     loop and one job at a time (p50/p99 latency), unless --no-serving.
 """
@@ -160,9 +161,22 @@ def nd_workload():
     return n, L, inputs.uniform_sites(rng, 16384, L)
 
 
-def nd_sampled_parity(labels):
+# Triclinic cell of the general-period workload (rows = period vectors).
+LATTICE_CELL = [[128.0, 0.0, 0.0], [40.0, 120.0, 0.0], [25.0, -18.0, 110.0]]
+
+
+def lattice_workload():
+    """3D Voronoi in a triclinic periodic cell, 128^3 voxels, 20,000 sites
+    uniform in the cell, seed 7."""
+    import numpy as np
+    n = (128, 128, 128)
+    rng = np.random.default_rng(7)
+    return n, np.array(LATTICE_CELL), rng.random((20000, 3)) @ np.array(LATTICE_CELL)
+
+
+def nd_sampled_parity(labels, lat_labels=None):
     """Part of the CPU leg: the general kernel's labels at sampled voxels
-    against the oracle."""
+    against the oracle (4D workload, and the triclinic one if given)."""
     import numpy as np
     import oracle
     n, L, coords = nd_workload()
@@ -170,7 +184,16 @@ def nd_sampled_parity(labels):
     vox = np.stack([rng.integers(0, v, 2000) for v in n], axis=1)
     ref, _ = oracle.label_points(oracle.problem(n, L, oracle.VORONOI, True), coords, None, vox)
     got = labels[tuple(vox[:, a] for a in reversed(range(len(n))))]
-    return {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}
+    out = {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}
+    if lat_labels is not None:
+        n, P, coords = lattice_workload()
+        vox = np.stack([rng.integers(0, v, 2000) for v in n], axis=1)
+        ref, _ = oracle.label_points(oracle.problem(n, [1.0] * 3, oracle.VORONOI, True, periods=P),
+                                     coords, None, vox)
+        got = lat_labels[tuple(vox[:, a] for a in reversed(range(3)))]
+        out["lattice_voxels"] = int(len(vox))
+        out["lattice_mismatches"] = int((got != ref).sum())
+    return out
 
 
 def general_path(ctx, steps, warmup):
@@ -194,10 +217,28 @@ def general_path(ctx, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     nvox = int(np.prod(n))
-    return {"workload": "4D Voronoi 64^4, 16,384 sites, periodic, seed 6", "ms_per_call": round(ms, 4),
-            "value": round(nvox / (ms * 1e-3) / 1e9, 3), "unit": "Gvoxels/s",
-            "hbm_write_frac": round(4.0 * nvox / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "labels": job.labels.cpu().numpy()}
+    out = {"workload": "4D Voronoi 64^4, 16,384 sites, periodic, seed 6", "ms_per_call": round(ms, 4),
+           "value": round(nvox / (ms * 1e-3) / 1e9, 3), "unit": "Gvoxels/s",
+           "hbm_write_frac": round(4.0 * nvox / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "labels": job.labels.cpu().numpy()}
+    # general period vectors
+    n, P, coords = lattice_workload()
+    lj = vtess.Job(n=n, L=(1.0, 1.0, 1.0), kind=inputs.VORONOI, periodic=True,
+                   coords=torch.from_numpy(coords).to(dev), periods=P.tolist())
+    for _ in range(warmup):
+        ctx.tessellate_nd(lj, stream=stream)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.tessellate_nd(lj, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nvox = int(np.prod(n))
+    out["lattice"] = {"workload": "3D Voronoi 128^3, triclinic periodic cell, 20,000 sites, seed 7",
+                      "ms_per_call": round(ms, 4), "value": round(nvox / (ms * 1e-3) / 1e9, 3),
+                      "unit": "Gvoxels/s"}
+    out["lattice_labels"] = lj.labels.cpu().numpy()
+    return out
 
 
 def main():
@@ -327,6 +368,7 @@ def main():
         print("[bench] general-dimension kernel (4D)", file=sys.stderr, flush=True)
         g = general_path(ctx, max(args.steps // 4, 2), 1)
         nd_labels = g.pop("labels")
+        lat_labels = g.pop("lattice_labels")
         out["general_path"] = g
     if not args.no_serving:
         from paper_2201_13234_amd import serve
@@ -338,7 +380,7 @@ def main():
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, lab)
         if args.nd:
-            out["cpu_baseline"]["general_path_sampled_parity"] = nd_sampled_parity(nd_labels)
+            out["cpu_baseline"]["general_path_sampled_parity"] = nd_sampled_parity(nd_labels, lat_labels)
     ctx.close()
     print(json.dumps(out), flush=True)
 
