@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "vt_internal.h"
+#include "nd_internal.h"
 #include "vtess.h"
 
 using vt::JobDev;

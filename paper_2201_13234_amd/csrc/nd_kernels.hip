@@ -31,7 +31,7 @@
 // M = 2^-36 of the key scale, far above the rounding error of any bound or
 // key, so a dropped site's (or translation's) computed key is strictly
 // above the winner's.
-#include "vt_internal.h"
+#include "nd_internal.h"
 
 namespace vt {
 
