@@ -18,11 +18,12 @@
 //
 // Labelling: one workgroup of 256 threads per tile of at most 256 voxels
 // (powers of two per axis), one voxel per thread.
-//   1. Rings of bins around the tile are visited until every site beyond them
-//      provably loses: UB = the smallest upper bound of a visited site's key
-//      over the tile's voxel centres, and the sites outside the visited box
-//      are at least `gap` away, so their keys exceed gap^2 (Voronoi),
-//      gap^2 - max w (Laguerre), min t + gap / v (Johnson-Mehl).
+//   1. The box of visited bins around the tile grows (face by face, or by
+//      whole rings for general periods) until the sites beyond it provably
+//      lose: UB = the smallest upper bound of a visited site's key over the
+//      tile's voxel centres, and the sites beyond a face are at least its
+//      `gap` away, so their keys exceed gap^2 (Voronoi), gap^2 - max w
+//      (Laguerre), min t + gap / v (Johnson-Mehl).
 //   2. The visited sites whose lower bound over the tile is <= UB + M are
 //      staged in LDS (for general periods with the box of translations that
 //      can bring them within reach) and every thread takes the lexicographic
@@ -314,8 +315,9 @@ __device__ inline double lattice_upper(const NdDev& J, const NdConst& C, int64_t
     return key_of_q<KIND>(uq, J.sp[pos], C);
 }
 
-// The visited bin box of ring r around the tile's bins [bl, bh]: per axis the
-// first bin (unwrapped) and the width; full = the axis is covered entirely.
+// The visited bin box: the tile's bins [bl, bh] grown by elo bins below and
+// ehi bins above along each axis.  Per axis the first bin (unwrapped) and the
+// width; full = the axis is covered entirely.
 struct NdBox {
     int first[kMaxDim], width[kMaxDim];
     bool full[kMaxDim];
@@ -323,13 +325,13 @@ struct NdBox {
 };
 
 template <int DIM>
-__device__ inline NdBox ring_box(const NdDev& J, const int* bl, const int* bh, int r)
+__device__ inline NdBox grown_box(const NdDev& J, const int* bl, const int* bh, const int* elo, const int* ehi)
 {
     NdBox B;
     B.count = 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        int f = bl[a] - r, e = bh[a] + r;
+        int f = bl[a] - elo[a], e = bh[a] + ehi[a];
         if (J.bc) {
             B.full[a] = e - f + 1 >= J.nb[a];
             if (B.full[a]) {
@@ -375,31 +377,58 @@ __device__ inline int64_t box_bin(const NdDev& J, const NdBox& B, int64_t j, con
     return lin;
 }
 
-// Smallest distance from the tile to a site outside the visited box
-// (infinite once every site has been visited).  General periods: a
-// fractional gap gamma along axis i is at least gamma / |row i of Pinv| in
-// Cartesian distance.
-template <int DIM, bool LAT>
-__device__ inline double outside_gap(const NdDev& J, const NdBox& B, const NdTile<DIM>& G)
+// General periods grow whole rings: the box of ring r, and the smallest
+// Cartesian distance from the tile to a site outside it (infinite once every
+// site has been visited): a fractional gap gamma along axis a is at least
+// gamma / |row a of Pinv| in Cartesian distance.
+template <int DIM>
+__device__ inline NdBox ring_box(const NdDev& J, const int* bl, const int* bh, int r)
+{
+    int e[DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        e[a] = r;
+    return grown_box<DIM>(J, bl, bh, e, e);
+}
+
+template <int DIM>
+__device__ inline double ring_gap(const NdDev& J, const NdBox& B, const NdTile<DIM>& G)
 {
     double g = __builtin_inf();
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        if (J.bc) {
-            if (B.full[a])
-                continue;
-            const double low = G.lo[a] - (double)B.first[a] * J.bs[a];
-            const double high = (double)(B.first[a] + B.width[a]) * J.bs[a] - G.hi[a];
-            const double ga = fmax(fmin(low, high), 0.0);
-            g = fmin(g, LAT ? ga / J.rown[a] : ga);
-        } else {
-            if (B.first[a] > 0)
-                g = fmin(g, G.lo[a] - (double)B.first[a] * J.bs[a]);
-            if (B.first[a] + B.width[a] < J.nb[a])
-                g = fmin(g, (double)(B.first[a] + B.width[a]) * J.bs[a] - G.hi[a]);
-        }
+        if (B.full[a])
+            continue;
+        const double low = G.lo[a] - (double)B.first[a] * J.bs[a];
+        const double high = (double)(B.first[a] + B.width[a]) * J.bs[a] - G.hi[a];
+        g = fmin(g, fmax(fmin(low, high), 0.0) / J.rown[a]);
     }
-    return fmax(g, 0.0);
+    return g;
+}
+
+// Orthogonal periods or none: distances from the tile to the sites beyond
+// the low and high faces of the visited box along axis a (infinite where no
+// site lies beyond).  On a periodic axis that is not covered entirely, the
+// sites beyond either face are the same ones, seen through the two nearest
+// periods, so each face gap only bounds them together with the other.
+template <int DIM>
+__device__ inline void face_gaps(const NdDev& J, const NdBox& B, const NdTile<DIM>& G, int a, double& glo,
+                                 double& ghi)
+{
+    glo = ghi = __builtin_inf();
+    const double low = G.lo[a] - (double)B.first[a] * J.bs[a];
+    const double high = (double)(B.first[a] + B.width[a]) * J.bs[a] - G.hi[a];
+    if (J.bc) {
+        if (B.full[a])
+            return;
+        glo = fmax(low, 0.0);
+        ghi = fmax(high, 0.0);
+    } else {
+        if (B.first[a] > 0)
+            glo = fmax(low, 0.0);
+        if (B.first[a] + B.width[a] < J.nb[a])
+            ghi = fmax(high, 0.0);
+    }
 }
 
 // The exact key of staged candidate k at voxel centre x (the operations of
@@ -658,40 +687,91 @@ __global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
         double best = __builtin_inf();
         int blab = 0x7fffffff;
         if (!bad) {
-            // 1. rings of bins until the sites beyond them provably lose
+            // 1. grow the box of visited bins until the sites beyond it
+            //    provably lose; their keys are at least gap^2, gap^2 - max w
+            //    or min t + gap / v for the gap to the box
             double UB = __builtin_inf();
-            int r = 0;
-            NdBox B = ring_box<DIM>(J, bl, bh, 0), P = B;
-            for (;;) {
-                double my = __builtin_inf();
-                for (int64_t j = tid; j < B.count; j += NDT) {
-                    bool in_prev;
-                    const int64_t lin = box_bin<DIM>(J, B, j, P, r > 0, in_prev);
-                    if (in_prev)
-                        continue;
-                    const int s1 = J.bin_start[lin + 1];
-                    for (int s = J.bin_start[lin]; s < s1; ++s) {
-                        if (LAT) {
+            NdBox B, P;
+            if (LAT) {
+                // general periods: whole rings from the tile's own bins (their
+                // staging filter is loose in a skewed cell, so a small box pays)
+                int r = 0;
+                B = ring_box<DIM>(J, bl, bh, 0);
+                P = B;
+                for (;;) {
+                    double my = __builtin_inf();
+                    for (int64_t j = tid; j < B.count; j += NDT) {
+                        bool in_prev;
+                        const int64_t lin = box_bin<DIM>(J, B, j, P, r > 0, in_prev);
+                        if (in_prev)
+                            continue;
+                        const int s1 = J.bin_start[lin + 1];
+                        for (int s = J.bin_start[lin]; s < s1; ++s)
                             my = fmin(my, lattice_upper<KIND, DIM>(J, C, s, G));
-                        } else {
+                    }
+                    UB = fmin(UB, block_min(my, S));
+                    const double g = ring_gap<DIM>(J, B, G);
+                    if (g == __builtin_inf())
+                        break;
+                    const double lb_out = KIND == KIND_VORONOI ? g * g
+                                        : KIND == KIND_LAGUERRE ? g * g - C.pmax
+                                                                : C.pmin + g * C.rv;
+                    if (lb_out > UB + C.M)
+                        break;
+                    ++r;
+                    P = B;
+                    B = ring_box<DIM>(J, bl, bh, r);
+                }
+            } else {
+                // orthogonal periods or none: start from the first ring of
+                // neighbour bins, which makes UB tight, then move only the
+                // faces whose sites might still win
+                int elo[DIM], ehi[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+                    elo[a] = ehi[a] = 1;
+                B = grown_box<DIM>(J, bl, bh, elo, ehi);
+                P = B;
+                bool grown = false;
+                for (;;) {
+                    double my = __builtin_inf();
+                    for (int64_t j = tid; j < B.count; j += NDT) {
+                        bool in_prev;
+                        const int64_t lin = box_bin<DIM>(J, B, j, P, grown, in_prev);
+                        if (in_prev)
+                            continue;
+                        const int s1 = J.bin_start[lin + 1];
+                        for (int s = J.bin_start[lin]; s < s1; ++s) {
                             double kl, ku;
                             site_bounds<KIND, DIM>(J, C, s, G, kl, ku);
                             my = fmin(my, ku);
                         }
                     }
+                    UB = fmin(UB, block_min(my, S));
+                    bool grow = false;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        double glo, ghi;
+                        face_gaps<DIM>(J, B, G, a, glo, ghi);
+                        const double llo = KIND == KIND_VORONOI ? glo * glo
+                                         : KIND == KIND_LAGUERRE ? glo * glo - C.pmax
+                                                                 : C.pmin + glo * C.rv;
+                        const double lhi = KIND == KIND_VORONOI ? ghi * ghi
+                                         : KIND == KIND_LAGUERRE ? ghi * ghi - C.pmax
+                                                                 : C.pmin + ghi * C.rv;
+                        // (an infinite gap has no site beyond it: that face stays)
+                        const bool mlo = glo != __builtin_inf() && !(llo > UB + C.M);
+                        const bool mhi = ghi != __builtin_inf() && !(lhi > UB + C.M);
+                        elo[a] += mlo;
+                        ehi[a] += mhi;
+                        grow = grow || mlo || mhi;
+                    }
+                    if (!grow)
+                        break;
+                    P = B;
+                    B = grown_box<DIM>(J, bl, bh, elo, ehi);
+                    grown = true;
                 }
-                UB = fmin(UB, block_min(my, S));
-                const double g = outside_gap<DIM, LAT>(J, B, G);
-                if (g == __builtin_inf())
-                    break;
-                const double lb_out = KIND == KIND_VORONOI ? g * g
-                                    : KIND == KIND_LAGUERRE ? g * g - C.pmax
-                                                            : C.pmin + g * C.rv;
-                if (lb_out > UB + C.M)
-                    break;
-                ++r;
-                P = B;
-                B = ring_box<DIM>(J, bl, bh, r);
             }
             // 2. stage the candidates and take the lexicographic minimum
             if (tid == 0)
