@@ -253,15 +253,16 @@ __device__ inline void site_bounds(const NdDev& J, const NdConst& C, int64_t pos
             dmin = fmax(0.0, fmax(G.lo[a] - s, s - G.hi[a]));
             dmax = fmax(fabs(s - G.lo[a]), fabs(s - G.hi[a]));
         } else {
-            // images s - L, s, s + L cover every voxel centre of the cell
-            dmin = __builtin_inf();
-            dmax = __builtin_inf();
-            for (int k = -1; k <= 1; ++k) {
-                const double sk = s + (double)k * J.L[a];
-                dmin = fmin(dmin, fmax(0.0, fmax(G.lo[a] - sk, sk - G.hi[a])));
-                dmax = fmin(dmax, fmax(fabs(sk - G.lo[a]), fabs(sk - G.hi[a])));
-            }
-            dmax = fmin(dmax, J.H[a]);
+            // the image nearest the centre c of [lo, hi]: no other image comes
+            // nearer to the interval (c is at most L/2 from it, every other
+            // image at least L/2), and from it no voxel of the interval is
+            // farther than |s - c| + half width (nor than L/2, the largest
+            // minimum-image distance)
+            const double c = 0.5 * (G.lo[a] + G.hi[a]), hw = 0.5 * (G.hi[a] - G.lo[a]);
+            double e = fabs(s - c);
+            e = fmin(e, J.L[a] - e);
+            dmin = fmax(0.0, e - hw);
+            dmax = fmin(e + hw, J.H[a]);
         }
         lq += dmin * dmin;
         uq += dmax * dmax;
@@ -601,7 +602,7 @@ __device__ inline bool lattice_reach(const NdDev& J, const NdConst& C, int64_t p
 }
 
 template <int KIND, int DIM, bool LAT>
-__global__ __launch_bounds__(NDT) void k_nd_label(NdDev J)
+__global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
 {
     __shared__ NdLds<DIM, LAT> S;
     const int tid = threadIdx.x;
