@@ -26,9 +26,11 @@
 //      (Laguerre), min t + gap / v (Johnson-Mehl).
 //   2. The visited sites whose lower bound over the tile is <= UB + M are
 //      staged in LDS (for general periods with the box of translations that
-//      can bring them within reach) and every thread takes the lexicographic
-//      minimum of (key, site index) over them: the brute-force result with
-//      ties to the lowest index, whatever the order of the candidates.
+//      can bring them within reach).  Voronoi and Laguerre with orthogonal
+//      periods drop those that the site attaining UB beats on the whole tile
+//      (linear key difference).  Every thread takes the lexicographic minimum
+//      of (key, site index) over the rest: the brute-force result with ties
+//      to the lowest index, whatever the order of the candidates.
 // M = 2^-36 of the key scale, far above the rounding error of any bound or
 // key, so a dropped site's (or translation's) computed key is strictly
 // above the winner's.
@@ -183,6 +185,7 @@ struct NdLds {
     int32_t kn[LAT ? D : 1][LAT ? ND_CAP : 1];
     double p[ND_CAP];
     int32_t idx[ND_CAP];
+    int32_t dead[ND_CAP];    // beaten on the whole tile by the reference site
     int32_t count;
     double red[NDT / WAVE];
     int32_t ired[NDT / WAVE];
@@ -200,6 +203,34 @@ __device__ inline double block_min(double v, L& S)
     double r = S.red[0];
     for (int w = 1; w < NDT / WAVE; ++w)
         r = fmin(r, S.red[w]);
+    return r;
+}
+
+// Smallest v over the workgroup and a `pos` that attains it.
+template <class L>
+__device__ inline double block_argmin(double v, int pos, L& S, int& at)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o);
+        const int q = __shfl_xor(pos, o);
+        if (w < v || (w == v && q < pos)) {
+            v = w;
+            pos = q;
+        }
+    }
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        S.red[threadIdx.x / WAVE] = v;
+        S.ired[threadIdx.x / WAVE] = pos;
+    }
+    __syncthreads();
+    double r = S.red[0];
+    at = S.ired[0];
+    for (int w = 1; w < NDT / WAVE; ++w)
+        if (S.red[w] < r) {
+            r = S.red[w];
+            at = S.ired[w];
+        }
     return r;
 }
 
@@ -432,6 +463,62 @@ __device__ inline void face_gaps(const NdDev& J, const NdBox& B, const NdTile<DI
     }
 }
 
+// Voronoi and Laguerre, orthogonal periods or none: true when the reference
+// site (ce = its coordinates, pr its parameter) beats staged candidate k by
+// more than M at every voxel centre of the tile.  With images that stay the
+// same over the tile, the difference of the two keys is, along each axis,
+// (x - e)^2 - (x - r)^2, linear in x, so its minimum over [lo, hi] is at an
+// end; the sum of those minima bounds the difference from below.
+template <int KIND, int DIM, bool LAT>
+__device__ inline bool beaten_on_tile(const NdDev& J, const NdConst& C, const NdTile<DIM>& G,
+                                      const NdLds<DIM, LAT>& S, int k, const double* cr, double pr)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double e = S.c[a][k], r = cr[a];
+        if (J.bc) {
+            // nearest images to the tile's centre, kept only when each is the
+            // minimum image for every voxel of the tile
+            const double c = 0.5 * (G.lo[a] + G.hi[a]), hw = 0.5 * (G.hi[a] - G.lo[a]);
+            const double lim = J.H[a] * (1.0 - 0x1p-30);
+            double de = e - c, dr = r - c;
+            de = de >= J.H[a] ? de - J.L[a] : (de < -J.H[a] ? de + J.L[a] : de);
+            dr = dr >= J.H[a] ? dr - J.L[a] : (dr < -J.H[a] ? dr + J.L[a] : dr);
+            if (!(fabs(de) + hw < lim && fabs(dr) + hw < lim))
+                return false;
+            e = c + de;
+            r = c + dr;
+        }
+        const double vlo = (G.lo[a] - e) * (G.lo[a] - e) - (G.lo[a] - r) * (G.lo[a] - r);
+        const double vhi = (G.hi[a] - e) * (G.hi[a] - e) - (G.hi[a] - r) * (G.hi[a] - r);
+        acc += fmin(vlo, vhi);
+    }
+    if (KIND == KIND_LAGUERRE)
+        acc -= S.p[k] - pr;
+    return acc > C.M;
+}
+
+// Marks the staged candidates [0, cnt) that the reference site beats on the
+// whole tile (Voronoi and Laguerre with orthogonal periods or none).
+template <int KIND, int DIM, bool LAT>
+__device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTile<DIM>& G, NdLds<DIM, LAT>& S,
+                                   int cnt, int ref)
+{
+    double cr[DIM];
+    double pr = 0.0;
+    const bool use = !LAT && KIND != KIND_JM && ref >= 0;
+    if (use) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+            cr[a] = J.sc[(int64_t)ref * DIM + a];
+        pr = J.sp[ref];
+    }
+    for (int k = threadIdx.x; k < cnt; k += NDT)
+        S.dead[k] = use ? beaten_on_tile<KIND, DIM, LAT>(J, C, G, S, k, cr, pr) : 0;
+    __syncthreads();
+}
+
 // The exact key of staged candidate k at voxel centre x (the operations of
 // the definition in the file comment).
 template <int KIND, int DIM, bool LAT>
@@ -511,6 +598,8 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
                                    double& best, int& blab)
 {
     for (int k = 0; k < count; ++k) {
+        if (S.dead[k])  // the same for every thread
+            continue;
         const double key = nd_key<KIND, DIM, LAT>(J, S, k, x);
         const int id = S.idx[k];
         if (key < best || (key == best && id < blab)) {
@@ -692,6 +781,7 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
             //    provably lose; their keys are at least gap^2, gap^2 - max w
             //    or min t + gap / v for the gap to the box
             double UB = __builtin_inf();
+            int ubpos = -1;  // a sorted site attaining UB (orthogonal periods or none)
             NdBox B, P;
             if (LAT) {
                 // general periods: whole rings from the tile's own bins (their
@@ -736,6 +826,7 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                 bool grown = false;
                 for (;;) {
                     double my = __builtin_inf();
+                    int mypos = -1;
                     for (int64_t j = tid; j < B.count; j += NDT) {
                         bool in_prev;
                         const int64_t lin = box_bin<DIM>(J, B, j, P, grown, in_prev);
@@ -745,10 +836,18 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                         for (int s = J.bin_start[lin]; s < s1; ++s) {
                             double kl, ku;
                             site_bounds<KIND, DIM>(J, C, s, G, kl, ku);
-                            my = fmin(my, ku);
+                            if (ku < my) {
+                                my = ku;
+                                mypos = s;
+                            }
                         }
                     }
-                    UB = fmin(UB, block_min(my, S));
+                    int at;
+                    const double m = block_argmin(my, mypos, S, at);
+                    if (m < UB) {
+                        UB = m;
+                        ubpos = at;
+                    }
                     bool grow = false;
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) {
@@ -822,6 +921,7 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                     const int cnt = S.count;
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
+                        mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
                         if (live)
                             nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, best, blab);
                         __syncthreads();
@@ -832,6 +932,7 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                 }
             }
             const int cnt = S.count;
+            mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
             if (live && cnt > 0)
                 nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, best, blab);
             __syncthreads();
