@@ -4,12 +4,14 @@
 One step = one whole plain-path call (vt_tessellate): counting-sort binning of
 the sites plus labelling of all 134,217,728 voxels, inputs already resident
 in HBM.  The line printed at the end also carries
-  - roofline: the labelling kernel's algorithmic HBM write bytes (4 B per
-    voxel) over its average duration, timed with HIP events recorded by the
-    library on the stream the kernel runs on, against 8 TB/s, with the HBM
-    traffic and the FP64 / VALU issue rates measured by hardware counters
-    (committed counter summary, used only while it matches the kernel
-    source);
+  - roofline: the labelling kernel is bound by binary64 arithmetic
+    ("alu"): its algorithmic work, the paper's ln N + 1 key evaluations per
+    voxel (eq. dl) times the operations of one key, over its average
+    duration (HIP events recorded by the library on the stream the kernel
+    runs on), against the FP64 vector peak of 78.6 TFLOP/s; beside it the
+    HBM write roofline (4 B per voxel against 8 TB/s), and the HBM traffic
+    and FP64 / VALU issue rates measured by hardware counters (committed
+    counter summary, used only while it matches the kernel source);
   - cpu_baseline: the CPU oracle (paper's two-step ball algorithm) timed on
     the host's cores on the same workload, and the device labels of the timed
     configuration checked against the oracle at sampled voxels;
@@ -21,6 +23,7 @@ in HBM.  The line printed at the end also carries
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -321,14 +324,28 @@ def main():
     bin_avg_ms = bin_ms / max(calls, 1)
     ovf_avg_ms = ovf_ms / max(calls, 1)
     write_bytes = 4.0 * w.nvox
-    achieved = write_bytes / (label_avg_ms * 1e-3) / 1e9
+    hbm = write_bytes / (label_avg_ms * 1e-3) / 1e9
+    # The kernel is bound by binary64 arithmetic.  Algorithmic work: the
+    # paper's key evaluations per voxel, ln N + 1 (eq. dl), times the
+    # operations of one key (3D: 3 subtractions, 3 multiplications, 2
+    # additions; Laguerre one subtraction more; Johnson-Mehl a square root
+    # and a multiplication more; 2D one subtraction, one multiplication and
+    # one addition fewer).
+    per_key = {0: 8, 1: 9, 2: 10}[w.kind] - (3 if w.ndim == 2 else 0)
+    evals = math.log(w.nsites) + 1.0
+    alg_flops = w.nvox * evals * per_key
+    tflops = alg_flops / (label_avg_ms * 1e-3) / 1e12
     cnt = load_counters(w.name)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
                 "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
                 "kernel": "k_label_single (main labelling kernel)",
                 "kernel_avg_ms": round(label_avg_ms, 4),
-                "algorithmic_bytes": write_bytes}
+                "algorithmic_flops": alg_flops,
+                "algorithmic_basis": f"{evals:.2f} key evaluations per voxel (ln N + 1) x {per_key} binary64 "
+                                     f"operations per key, {w.nvox} voxels",
+                "hbm_write": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(hbm / HBM_PEAK_GBS, 4), "algorithmic_bytes": write_bytes}}
     if cnt and "sq_per_launch" in cnt:
         sq = cnt["sq_per_launch"]
         sec = label_avg_ms * 1e-3
@@ -336,8 +353,8 @@ def main():
             # the counter sums FP64 operations per wavefront instruction (FMA = 2);
             # times 64 lanes (an upper bound: it assumes full execution masks)
             f64 = sq["SQ_INSTS_VALU_FLOPS_FP64"] * 64 / sec / 1e12
-            roofline["fp64"] = {"achieved": round(f64, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                "frac": round(f64 / FP64_PEAK_TFLOPS, 4)}
+            roofline["fp64_counted"] = {"achieved": round(f64, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                        "frac": round(f64 / FP64_PEAK_TFLOPS, 4)}
         if "SQ_INSTS_VALU" in sq:
             v = sq["SQ_INSTS_VALU"] * 64 / sec / 1e12
             roofline["valu_issue"] = {"achieved": round(v, 2), "peak": round(VALU_PEAK_TOPS, 2),
