@@ -505,9 +505,11 @@ template <int KIND, int DIM, bool LAT>
 __device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTile<DIM>& G, NdLds<DIM, LAT>& S,
                                    int cnt, int ref)
 {
+    if (LAT || KIND == KIND_JM)
+        return;  // nothing to mark: the evaluation does not look at the marks
     double cr[DIM];
     double pr = 0.0;
-    const bool use = !LAT && KIND != KIND_JM && ref >= 0;
+    const bool use = ref >= 0;
     if (use) {
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
@@ -598,7 +600,7 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
                                    double& best, int& blab)
 {
     for (int k = 0; k < count; ++k) {
-        if (S.dead[k])  // the same for every thread
+        if (!LAT && KIND != KIND_JM && S.dead[k])  // the same for every thread
             continue;
         const double key = nd_key<KIND, DIM, LAT>(J, S, k, x);
         const int id = S.idx[k];
