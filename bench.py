@@ -13,8 +13,10 @@ in HBM.  The line printed at the end also carries
     and FP64 / VALU issue rates measured by hardware counters (committed
     counter summary, used only while it matches the kernel source);
   - cpu_baseline: the CPU oracle (paper's two-step ball algorithm) timed on
-    the host's cores on the same workload, and the device labels of the timed
-    configuration checked against the oracle at sampled voxels;
+    the host's cores on the same workload, the device labels of the timed
+    configuration checked against the oracle at sampled voxels, and every
+    125th served job's labels (checksums) against the oracle's; with
+    --oracle-survey also the oracle's times on M1-M4;
   - general_path (with --nd): the general-dimension kernel on a 4D Voronoi
     diagram, 64^4 voxels and 16,384 sites, and on a 3D Voronoi diagram of
     20,000 sites in a triclinic periodic cell (128^3 voxels);
@@ -153,6 +155,53 @@ def cpu_baseline(w, labels):
             "sampled_parity": {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}}
 
 
+def serving_sampled_parity(keep, every=125):
+    """Part of the CPU leg: labels of a stratified sample of the served jobs
+    (every `every`-th job of the stream), as checksums of the batched replay,
+    against the oracle's labels of the same jobs."""
+    import oracle
+    from paper_2201_13234_amd import serve
+    jobs, dig = keep["jobs"], keep["digests"]
+    checked = bad = 0
+    vox = 0
+    for r in jobs[::every]:
+        w = r.workload
+        p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+        lab, _, _ = oracle.tessellate(p, w.coords, w.param)
+        checked += 1
+        vox += int(lab.size)
+        bad += int(dig.get(r.rid) != serve.digest_host(lab))
+    return {"jobs": checked, "voxels": vox, "mismatches": bad}
+
+
+def oracle_survey():
+    """Oracle wall times on the benchmark configurations: M1 (median of 3,
+    all cores and one thread, and by brute force) and M2-M4 (one run each,
+    all cores)."""
+    import statistics
+    import oracle
+    from paper_2201_13234_amd import inputs
+    out = {"cores": oracle.max_threads()}
+    for name in ("M1", "M2", "M3", "M4"):
+        w = inputs.CONFIGS[name]()
+        p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+        reps = 3 if name == "M1" else 1
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.tessellate(p, w.coords, w.param)
+            ts.append(time.perf_counter() - t0)
+        out[name] = {"seconds": round(statistics.median(ts), 3), "gvox_per_s": round(w.nvox / statistics.median(ts) / 1e9, 5)}
+        if name == "M1":
+            t0 = time.perf_counter()
+            oracle.tessellate(p, w.coords, w.param, nthreads=1)
+            out["M1_one_thread_seconds"] = round(time.perf_counter() - t0, 3)
+            t0 = time.perf_counter()
+            oracle.brute(p, w.coords, w.param)
+            out["M1_brute_force_seconds"] = round(time.perf_counter() - t0, 3)
+    return out
+
+
 def nd_workload():
     """4D Voronoi, 64^4 voxels, 16,384 uniform periodic sites (about M2's
     voxels per site), seed 6."""
@@ -253,6 +302,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream replay")
     ap.add_argument("--nd", action="store_true", help="also time the general-dimension kernel (4D)")
+    ap.add_argument("--oracle-survey", action="store_true",
+                    help="in the CPU leg, also time the oracle on M1-M4 (about a minute of CPU work)")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="request-stream length (the stream of 2,000 seeded jobs by default)")
     ap.add_argument("--serving-scale", type=float, default=1.0,
@@ -387,15 +438,22 @@ def main():
         nd_labels = g.pop("labels")
         lat_labels = g.pop("lattice_labels")
         out["general_path"] = g
+    keep = {}
     if not args.no_serving:
         from paper_2201_13234_amd import serve
         print(f"[bench] serving replay ({args.serving_jobs} jobs)", file=sys.stderr, flush=True)
         out["serving"] = serve.benchmark(ctx, n_jobs=args.serving_jobs, side_scale=args.serving_scale,
                                          log=lambda m: print(f"[bench] serving: {m}", file=sys.stderr,
-                                                             flush=True))
+                                                             flush=True), keep=keep)
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, lab)
+        if keep:
+            print("[bench] CPU oracle on a sample of the served jobs", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["serving_sampled_parity"] = serving_sampled_parity(keep)
+        if args.oracle_survey:
+            print("[bench] oracle survey M1-M4", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["oracle_survey"] = oracle_survey()
         if args.nd:
             out["cpu_baseline"]["general_path_sampled_parity"] = nd_sampled_parity(nd_labels, lat_labels)
     ctx.close()

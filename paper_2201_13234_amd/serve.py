@@ -452,14 +452,16 @@ def make_stream(n_jobs, rate, side_scale=0.25, first_job=0):
 
 
 def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, lanes=2, calib_jobs=0,
-              max_batch=64, extra_loads=(0.95,), log=None):
+              max_batch=64, extra_loads=(0.95,), log=None, keep=None):
     """Replays a request stream twice on the GPU -- continuous batching and one
     by one -- with the same arrival times.  The arrival rate is `load` times
     the one-by-one service rate, measured on all jobs (or the first
     `calib_jobs`) run back to back.  Returns p50/p99 latency and throughput of both modes, and
     whether every job's labels (device checksums) are the same in both.  Each
     of `extra_loads` repeats the comparison at that load (reported under
-    "other_loads")."""
+    "other_loads").  keep (a dict, optional) receives the jobs and the
+    batched replay's per-job label checksums at `load`, so that a caller
+    can check a sample of them against another implementation."""
     say = log or (lambda msg: None)
     ex = GpuExecutor(ctx, lanes=lanes, max_batch=max(max_batch, 1))
     say(f"generating {n_jobs} jobs")
@@ -475,6 +477,7 @@ def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, l
     ex.collect_digests()
     service = max(r.done for r in cal) / len(cal)
     from . import inputs
+    last_digests = {}
 
     def replay(ld):
         rate = ld / service
@@ -484,6 +487,8 @@ def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, l
         srv = Server(ex, mem_budget=mem_budget, max_batch=max_batch)
         batched = srv.run(copy(stream))
         db = ex.collect_digests()
+        last_digests.clear()
+        last_digests.update(db)
         say(f"load {ld}: one-by-one replay")
         alone = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(stream))
         da = ex.collect_digests()
@@ -495,6 +500,9 @@ def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, l
                 "labels_identical": bool(same), "checked_jobs": len(db)}
 
     out = replay(load)
+    if keep is not None:
+        keep["jobs"] = jobs
+        keep["digests"] = dict(last_digests)
     nvox = [r.nvox for r in jobs]
     out.update({"jobs": n_jobs, "side_scale": side_scale, "service_ms_alone": round(service * 1e3, 3),
                 "lanes": lanes, "max_batch": max_batch, "voxels_total": int(sum(nvox)),
