@@ -26,8 +26,12 @@ __device__ inline int job_of_region(const JobDev* jobs, int njobs, int64_t g)
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
+// The job's record is held in scalar registers across the region loop, and
+// without a bound the scalar registers that spill into vector registers halve
+// the occupancy; asking for 4 waves per SIMD (3 for Laguerre, measured)
+// trades that for a few vector-register spills and is faster.
 template <int KIND, int DIM, int CFG>
-__global__ __launch_bounds__(NT) void k_label_batch(const JobDev* __restrict__ jobs, int njobs, int64_t total,
+__global__ __launch_bounds__(NT, KIND == KL ? 3 : 4) void k_label_batch(const JobDev* __restrict__ jobs, int njobs, int64_t total,
                                                     int32_t* counters)
 {
     __shared__ Smem sm;
@@ -41,7 +45,11 @@ __global__ __launch_bounds__(NT) void k_label_batch(const JobDev* __restrict__ j
             if (tid == 0)
                 got = rb + (int64_t)atomicAdd(&counters[x], 1);
             __syncthreads();
-            const int64_t g = got;
+            // the same for every lane: say so, so that the region's geometry
+            // and its job's record stay in scalar registers
+            const int64_t gv = got;
+            const int64_t g = ((int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(gv >> 32)) << 32) |
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)gv);
             __syncthreads();
             if (g >= re)
                 break;
