@@ -1175,16 +1175,20 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 int l = (int)(BR.lo[a] * J.inv_bs[a]), h = (int)(BR.hi[a] * J.inv_bs[a]);
                 l = max(0, min(l, nb - 1));
                 h = max(l, min(h, nb - 1));
+                // first box: the region's bins and GM more on each side
+                // (Johnson-Mehl reaches farther: its gather would almost
+                // always need a second round from one)
+                constexpr int GM = (KIND == KJM || KIND == KJD) ? 2 : 1;
                 if (periodic) {
-                    blo[a] = l - 1;
-                    bhi[a] = h + 1;
+                    blo[a] = l - GM;
+                    bhi[a] = h + GM;
                     if (bhi[a] - blo[a] + 1 >= nb) {
                         blo[a] = l;
                         bhi[a] = l + nb - 1;
                     }
                 } else {
-                    blo[a] = max(l - 1, 0);
-                    bhi[a] = min(h + 1, nb - 1);
+                    blo[a] = max(l - GM, 0);
+                    bhi[a] = min(h + GM, nb - 1);
                 }
             } else {
                 blo[a] = bhi[a] = 0;
