@@ -107,23 +107,56 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDe
             lo = ordered_bits(-p);
         }
     }
-    // Parameter bounds: when every live lane of the wavefront belongs to one
-    // job, reduce over the wavefront (all lanes take part, dead lanes carry 0)
-    // and let the first live lane issue the atomics; otherwise one atomic per
-    // site.
+    // Parameter bounds.  A wavefront whose live lanes belong to one job reduces
+    // over its lanes (dead lanes carry 0); a block whose wavefronts all do so
+    // for the same job reduces once more through LDS and issues one atomic per
+    // bound, so that the atomics on the two shared addresses stay few.
+    // Otherwise the wavefront's first lane, or each site of a mixed
+    // wavefront, issues its own.  Live lanes are a prefix of the grid, so lane
+    // 0 of a wavefront (thread 0 of a block) is live if any lane is.
+    __shared__ int bjob[kBlock / WAVE];
+    __shared__ unsigned long long bhi[kBlock / WAVE], blo[kBlock / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int j0 = __shfl(j, 0);
-    if (__all(!live || j == j0)) {
+    const bool wuni = __all(!live || j == j0);
+    if (wuni) {
         for (int o = 32; o > 0; o >>= 1) {
             const unsigned long long h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
             hi = h2 > hi ? h2 : hi;
             lo = l2 > lo ? l2 : lo;
         }
-        const unsigned long long lv = __ballot(live);
-        if (!live || __lane_id() != (unsigned)(__ffsll(lv) - 1))
-            return;
-    } else if (!live) {
+    }
+    if (lane == 0) {
+        bjob[w] = !wuni ? -2 : (live ? j0 : -1);
+        bhi[w] = hi;
+        blo[w] = lo;
+    }
+    __syncthreads();
+    int jb = -1;
+    bool buni = true;
+    for (int k = 0; k < kBlock / WAVE; ++k) {
+        const int v = bjob[k];
+        if (v == -2 || (v >= 0 && jb >= 0 && v != jb))
+            buni = false;
+        if (v >= 0)
+            jb = v;
+    }
+    if (buni) {
+        if (threadIdx.x == 0 && jb >= 0 && weighted) {
+            for (int k = 1; k < kBlock / WAVE; ++k) {
+                hi = bhi[k] > hi ? bhi[k] : hi;
+                lo = blo[k] > lo ? blo[k] : lo;
+            }
+            const JobDev& J = jobs ? jobs[jb] : single;
+            if (hi)
+                atomicMax(&J.pbound[0], hi);
+            if (lo)
+                atomicMax(&J.pbound[1], lo);
+        }
         return;
     }
+    if (!live || (wuni && lane != 0))
+        return;
     if (weighted) {
         const JobDev& J = jobs ? jobs[j] : single;
         if (hi)
@@ -193,93 +226,142 @@ __device__ inline int find_bin_job(const JobDev* jobs, int n, int64_t g)
     return lo;
 }
 
-// Marks (in site_bin, indexed by the job's sorted position) the sites that
-// some other site swallows.  One wavefront per site; its lanes take the bins
-// of the search box in parallel.
-__global__ __launch_bounds__(kBlock) void k_jm_mark(JobDev single, const JobDev* __restrict__ jobs, int njobs,
-                                                    const int64_t* __restrict__ prefix, int64_t total)
+// Whether another site swallows the site at sorted position g (see above).
+// The wavefront's lanes take the bins of the search box, 64 at a time, and
+// each lane reads its bin's sites four at a time so that their loads are in
+// flight together.  The test compares squares, (d / v)^2 < (t_s - M - t_r)^2
+// with t_s - M - t_r > 0: its rounding, a few units in the last place of the
+// key scale, is as far below M as that of the key itself.
+template <int ND>
+__device__ inline bool jm_swallowed(const JobDev& J, int64_t g, int lane)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t g = blockIdx.x * (int64_t)(kBlock / WAVE) + threadIdx.x / WAVE;  // wave-uniform
-    if (g >= total)
-        return;
-    const int j = jobs ? find_segment(prefix, njobs, g) : 0;
-    const JobDev& J = jobs ? jobs[j] : single;
-    if (J.kind != KIND_JM)
-        return;
-    const int nd = J.ndim;
     const double4 s = J.sites[g];
     const double sc[3] = {s.x, s.y, s.z};
     const double tmin = -from_ordered_bits(J.pbound[1]), tmax = from_ordered_bits(J.pbound[0]);
     double sumL2 = 0.0;
-    for (int a = 0; a < nd; ++a)
+#pragma unroll
+    for (int a = 0; a < ND; ++a)
         sumL2 += J.L[a] * J.L[a];
     const double M = (sqrt(sumL2) * J.rgrowth + 2.0 * fmax(fabs(tmin), fabs(tmax))) * 0x1p-36;
     const bool periodic = J.bc != 0;
     bool inside = true;
-    for (int a = 0; a < nd; ++a)
+#pragma unroll
+    for (int a = 0; a < ND; ++a)
         inside = inside && sc[a] >= 0.0 && sc[a] < J.L[a];  // invalid input (reported by the count kernel): keep
-    const double gap = (s.w - M) - tmin;
-    bool dead = false;
-    if (inside && gap > 0.0) {
-        const double R = gap * J.growth * (1.0 + 0x1p-20) + J.L[0] * 0x1p-30;
-        int lo[3] = {0, 0, 0}, cnt3[3] = {1, 1, 1};
-        int64_t nbox = 1;
-        for (int a = 0; a < nd; ++a) {
-            const int nb = J.nb[a];
-            const double l = floor((sc[a] - R) * J.inv_bs[a]), h = floor((sc[a] + R) * J.inv_bs[a]);
-            int la, ha;
-            if (!(h - l + 1.0 < (double)nb)) {  // the whole axis (also catches a huge R)
-                la = 0;
-                ha = nb - 1;
-            } else if (periodic) {
-                la = (int)l;  // in (-nb, 2 nb): wrapped below
-                ha = (int)h;
-            } else {
-                la = max((int)l, 0);
-                ha = min((int)h, nb - 1);
-            }
-            lo[a] = la;
-            cnt3[a] = ha - la + 1;
-            nbox *= cnt3[a];
+    const double tcut = s.w - M;
+    const double gap = tcut - tmin;
+    if (!(inside && gap > 0.0))
+        return false;
+    const double R = gap * J.growth * (1.0 + 0x1p-20) + J.L[0] * 0x1p-30;
+    int lo[3] = {0, 0, 0}, cnt3[3] = {1, 1, 1};
+    int64_t nbox = 1;
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        const int nb = J.nb[a];
+        const double l = floor((sc[a] - R) * J.inv_bs[a]), h = floor((sc[a] + R) * J.inv_bs[a]);
+        int la, ha;
+        if (!(h - l + 1.0 < (double)nb)) {  // the whole axis (also catches a huge R)
+            la = 0;
+            ha = nb - 1;
+        } else if (periodic) {
+            la = (int)l;  // in (-nb, 2 nb): wrapped below
+            ha = (int)h;
+        } else {
+            la = max((int)l, 0);
+            ha = min((int)h, nb - 1);
         }
-        if (nbox <= kPruneMaxBins) {
-            const int nx = cnt3[0], nxy = cnt3[0] * cnt3[1];
-            for (int e0 = 0; e0 < (int)nbox && !dead; e0 += WAVE) {
-                const int e = e0 + lane;
-                bool hit = false;
-                if (e < (int)nbox) {
-                    const int ez = e / nxy, rem = e - ez * nxy, ey = rem / nx, ex = rem - ey * nx;
-                    const int bb[3] = {lo[0] + ex, lo[1] + ey, lo[2] + ez};
-                    int w3[3];
-                    for (int a = 0; a < 3; ++a) {
-                        const int nb = J.nb[a];
-                        w3[a] = bb[a] < 0 ? bb[a] + nb : (bb[a] >= nb ? bb[a] - nb : bb[a]);
-                    }
-                    const int lin = w3[0] + J.nb[0] * (w3[1] + J.nb[1] * w3[2]);
-                    const int b0 = J.bin_start[lin], cnt = J.bin_count[lin];
-                    for (int k = 0; k < cnt && !hit; ++k) {
-                        const int64_t r = b0 + k;
-                        if (r == g)
-                            continue;
-                        const double4 q = J.sites[r];
-                        const double qc[3] = {q.x, q.y, q.z};
-                        double d2 = 0.0;
-                        for (int a = 0; a < nd; ++a) {
-                            double d = sc[a] - qc[a];
-                            if (periodic)
-                                d = d >= 0.5 * J.L[a] ? d - J.L[a] : (d < -0.5 * J.L[a] ? d + J.L[a] : d);
-                            d2 += d * d;
-                        }
-                        hit = q.w + sqrt(d2) * J.rgrowth < s.w - M;
-                    }
-                }
-                dead = __ballot(hit) != 0;
-            }
-        }
+        lo[a] = la;
+        cnt3[a] = ha - la + 1;
+        nbox *= cnt3[a];
     }
+    if (nbox > kPruneMaxBins)
+        return false;
+    const double rg2 = J.rgrowth * J.rgrowth;
+    double Lh[3], La[3];
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+        La[a] = J.L[a];
+        Lh[a] = 0.5 * J.L[a];
+    }
+    const int nx = cnt3[0], nxy = cnt3[0] * cnt3[1];
+    for (int e0 = 0; e0 < (int)nbox; e0 += WAVE) {
+        const int e = e0 + lane;
+        bool hit = false;
+        if (e < (int)nbox) {
+            const int ez = e / nxy, rem = e - ez * nxy, ey = rem / nx, ex = rem - ey * nx;
+            const int bb[3] = {lo[0] + ex, lo[1] + ey, lo[2] + ez};
+            int w3[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < ND; ++a) {
+                const int nb = J.nb[a];
+                w3[a] = bb[a] < 0 ? bb[a] + nb : (bb[a] >= nb ? bb[a] - nb : bb[a]);
+            }
+            const int lin = w3[0] + J.nb[0] * (w3[1] + J.nb[1] * w3[2]);
+            const int b0 = J.bin_start[lin], cnt = J.bin_count[lin];
+            for (int k = 0; k < cnt && !hit; k += 4) {
+                double4 q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    q[u] = k + u < cnt ? J.sites[b0 + k + u] : s;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double qc[3] = {q[u].x, q[u].y, q[u].z};
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int a = 0; a < ND; ++a) {
+                        double d = sc[a] - qc[a];
+                        if (periodic)
+                            d = d >= Lh[a] ? d - La[a] : (d < -Lh[a] ? d + La[a] : d);
+                        d2 += d * d;
+                    }
+                    const double rhs = tcut - q[u].w;
+                    const bool other = k + u < cnt && (int64_t)b0 + k + u != g;
+                    hit = hit || (other && rhs > 0.0 && d2 * rg2 < rhs * rhs);
+                }
+            }
+        }
+        if (__ballot(hit) != 0)
+            return true;
+    }
+    return false;
+}
+
+template <int ND>
+__device__ inline void jm_mark_site(const JobDev& J, int64_t g, int lane)
+{
+    const bool dead = jm_swallowed<ND>(J, g, lane);
     if (lane == 0)
         J.site_bin[g - J.site_begin] = dead ? 1 : 0;
+}
+
+// Marks (in site_bin, indexed by the job's sorted position) the sites that
+// some other site swallows.  One wavefront per site.  The job's record is
+// copied into registers once (scalar loads), so that the search loops read
+// none of its fields through memory.
+__global__ __launch_bounds__(kBlock) void k_jm_mark(JobDev single, const JobDev* __restrict__ jobs, int njobs,
+                                                    const int64_t* __restrict__ prefix, int64_t total)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t g = blockIdx.x * (int64_t)(kBlock / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    if (g >= total)
+        return;
+    if (jobs) {
+        const int j = __builtin_amdgcn_readfirstlane(find_segment(prefix, njobs, g));
+        const JobDev J = jobs[j];
+        if (J.kind != KIND_JM)
+            return;
+        if (J.ndim == 3)
+            jm_mark_site<3>(J, g, lane);
+        else
+            jm_mark_site<2>(J, g, lane);
+    } else {
+        if (single.kind != KIND_JM)
+            return;
+        if (single.ndim == 3)
+            jm_mark_site<3>(single, g, lane);
+        else
+            jm_mark_site<2>(single, g, lane);
+    }
 }
 
 // Moves the live sites of each bin to the front of its range and stores their
