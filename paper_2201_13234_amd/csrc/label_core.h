@@ -130,19 +130,6 @@ __device__ inline int wrap_bin(int b, int nb)
     return b;
 }
 
-// fmin() of two keys, without the quieting of its operands.  fmin() puts a
-// self-max before v_min_f64 on any operand the compiler cannot prove to be a
-// quiet value, which includes a running minimum carried across loop
-// iterations: one extra instruction in five in the evaluation loops.  Keys
-// and running minima are results of arithmetic or +inf, never signalling
-// NaNs, so v_min_f64 alone gives what fmin() gives.
-__device__ inline double min_key(double a, double b)
-{
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-
 __device__ inline double from_ordered(unsigned long long u)
 {
     unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
@@ -723,7 +710,7 @@ __device__ inline void evaluate(const double4* base, const int2* cm, int nc, boo
                 for (int q = 0; q < RUN; ++q) {
                     const double key = dist_key<KIND>(dx2[q] + c[r], s.w, C.v, C.rv);
                     lab[r * RUN + q] = key < best[r * RUN + q] ? idx : lab[r * RUN + q];
-                    best[r * RUN + q] = min_key(best[r * RUN + q], key);
+                    best[r * RUN + q] = fmin(best[r * RUN + q], key);
                 }
             } else {
 #pragma unroll
@@ -731,7 +718,7 @@ __device__ inline void evaluate(const double4* base, const int2* cm, int nc, boo
                     const double key = dist_key<KIND>(dx2[q] + c[r], s.w, C.v, C.rv);
                     const bool lt = key < best[r * RUN + q] || (key == best[r * RUN + q] && idx < lab[r * RUN + q]);
                     lab[r * RUN + q] = lt ? idx : lab[r * RUN + q];
-                    best[r * RUN + q] = min_key(best[r * RUN + q], key);
+                    best[r * RUN + q] = fmin(best[r * RUN + q], key);
                 }
             }
         }
@@ -847,7 +834,7 @@ __device__ inline void evaluate_rec(const TileLds& S, int nc, const JobDev& J, c
                 for (int q = 0; q < XRUN; ++q) {
                     const double key = dist_key_fast<KIND>(dx2[q] + c[r], sp, C.v, C.rv);
                     lab[r * XRUN + q] = key < best[r * XRUN + q] ? idx : lab[r * XRUN + q];
-                    best[r * XRUN + q] = min_key(best[r * XRUN + q], key);
+                    best[r * XRUN + q] = fmin(best[r * XRUN + q], key);
                 }
             }
         } else {
@@ -857,7 +844,7 @@ __device__ inline void evaluate_rec(const TileLds& S, int nc, const JobDev& J, c
                 for (int q = 0; q < XRUN; ++q) {
                     const double key = dist_key<KIND>(dx2[q] + c[r], sp, C.v, C.rv);
                     lab[r * XRUN + q] = key < best[r * XRUN + q] ? idx : lab[r * XRUN + q];
-                    best[r * XRUN + q] = min_key(best[r * XRUN + q], key);
+                    best[r * XRUN + q] = fmin(best[r * XRUN + q], key);
                 }
             }
         }
