@@ -184,6 +184,42 @@ def test_dominant_weight_and_swallowed_sites(ctx):
             check(ctx, workload(n, 2, periodic, pts, t, g, name=f"jm_swallow{g}"))
 
 
+def test_parameter_extremes_in_later_blocks(ctx):
+    """The binning pass reduces max(param) and max(-param) over wavefronts and
+    blocks before its atomics.  The extreme values sit in later wavefronts
+    and blocks, and in the last, partial block: a bound that missed one of
+    them would cut the search short where that site wins."""
+    import torch
+    rng = np.random.default_rng(29)
+    n = (40, 36, 44)
+    ns = 2000
+    pts = I.uniform_sites(rng, ns, [float(v) for v in n])
+    w = rng.uniform(0.0, 10.0, ns)
+    w[1300] = 2500.0                    # block 5, wavefront 0
+    w[777] = -400.0                     # block 3, wavefront 0
+    t = rng.uniform(20.0, 30.0, ns)
+    t[1999] = -60.0                     # last, partial block: wins most of the grid
+    t[450] = -20.0                      # block 1, wavefront 3
+    ws = []
+    for periodic in (True, False):
+        ws.append(workload(n, 1, periodic, pts, w, name="lag_extremes"))
+        ws.append(workload(n, 2, periodic, pts, t, 1.0, name="jm_extremes"))
+    for x in ws:
+        check(ctx, x)
+    # the same jobs behind a Voronoi job of 100 sites in one batch: the first
+    # block then mixes two jobs
+    from gpu_util import to_dev
+    front = workload((30, 30, 30), 0, True, I.uniform_sites(rng, 100, [30.0] * 3), None, name="front")
+    batch = [front] + ws
+    jobs = [to_dev(x) for x in batch]
+    ctx.tessellate_batch(jobs)
+    torch.cuda.synchronize()
+    for x, j in zip(batch, jobs):
+        ref = run_oracle(x)
+        got = j.labels.cpu().numpy()
+        assert np.array_equal(got, ref), f"batch {x.name}: " + describe_mismatch(got, ref)
+
+
 @pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("d", [2, 3])
 def test_dense_sites_default_tiles(ctx, kind, d):
