@@ -13,7 +13,7 @@ constexpr int kMaxDim = 6;
 struct NdDev {
     int32_t ndim, kind, bc, jm_div;
     int32_t nsites, nbins;
-    int32_t T[kMaxDim];            // tile voxels per axis (powers of two, product <= 256)
+    int32_t T[kMaxDim];            // tile voxels per axis (powers of two; product / vpt <= 256 threads)
     int32_t nb[kMaxDim];           // bins per axis
     int64_t n[kMaxDim];            // voxels per axis
     int64_t nt[kMaxDim];           // tiles per axis
@@ -24,7 +24,8 @@ struct NdDev {
     // General period vectors (lattice != 0; App. A, eq. L-distance_def).  The
     // bins, L, H, bs and inv_bs above then live in fractional coordinates
     // (period 1 per axis).
-    int32_t lattice, pad2;
+    int32_t lattice;
+    int32_t vpt;                   // voxels per thread (1 or 2), the second T[0] / vpt further along axis 0
     double P[kMaxDim][kMaxDim];    // P[i][a]: component a of period vector i
     double hv[kMaxDim][kMaxDim];   // P[i][a] / n_i: voxel steps
     double Pinv[kMaxDim][kMaxDim]; // Pinv[i][a]: fractional coordinate i per Cartesian a

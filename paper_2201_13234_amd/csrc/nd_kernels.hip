@@ -523,6 +523,16 @@ __device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTil
 
 // The exact key of staged candidate k at voxel centre x (the operations of
 // the definition in the file comment).
+template <int KIND>
+__device__ inline double nd_key_q(const NdDev& J, double q, double p)
+{
+    if (KIND == KIND_VORONOI)
+        return q;
+    if (KIND == KIND_LAGUERRE)
+        return q - p;
+    return J.jm_div ? p + key_sqrt(q) / J.growth : p + key_sqrt(q) * J.rgrowth;
+}
+
 template <int KIND, int DIM, bool LAT>
 __device__ inline double nd_key(const NdDev& J, const NdLds<DIM, LAT>& S, int k, const double* x)
 {
@@ -587,26 +597,55 @@ __device__ inline double nd_key(const NdDev& J, const NdLds<DIM, LAT>& S, int k,
                 break;
         }
     }
-    const double p = S.p[k];
-    if (KIND == KIND_VORONOI)
-        return q;
-    if (KIND == KIND_LAGUERRE)
-        return q - p;
-    return J.jm_div ? p + key_sqrt(q) / J.growth : p + key_sqrt(q) * J.rgrowth;
+    return nd_key_q<KIND>(J, q, S.p[k]);
 }
 
+// Evaluates the staged candidates [0, count) at the thread's voxel x and,
+// when `two`, at its second voxel, which differs from x on axis 0 only
+// (orthogonal periods: x1[0]; general periods: x1 in full).  With orthogonal
+// periods the terms of axes 1 .. DIM-1 are the same for both voxels and are
+// summed once, in the order of the definition.
 template <int KIND, int DIM, bool LAT>
 __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int count, const double* x,
-                                   double& best, int& blab)
+                                   const double* x1, bool two, double& best, int& blab, double& best1, int& blab1)
 {
     for (int k = 0; k < count; ++k) {
         if (!LAT && KIND != KIND_JM && S.dead[k])  // the same for every thread
             continue;
-        const double key = nd_key<KIND, DIM, LAT>(J, S, k, x);
         const int id = S.idx[k];
+        double key, key1 = 0.0;
+        if (LAT) {
+            key = nd_key<KIND, DIM, LAT>(J, S, k, x);
+            if (two)
+                key1 = nd_key<KIND, DIM, LAT>(J, S, k, x1);
+        } else {
+            double T = 0.0;
+#pragma unroll
+            for (int a = 1; a < DIM; ++a) {
+                double e = S.c[a][k] - x[a];
+                if (J.bc)
+                    e = e >= J.H[a] ? e - J.L[a] : (e < -J.H[a] ? e + J.L[a] : e);
+                T = a == 1 ? e * e : T + e * e;
+            }
+            const double p = S.p[k];
+            double e = S.c[0][k] - x[0];
+            if (J.bc)
+                e = e >= J.H[0] ? e - J.L[0] : (e < -J.H[0] ? e + J.L[0] : e);
+            key = nd_key_q<KIND>(J, DIM > 1 ? e * e + T : e * e, p);
+            if (two) {
+                double e1 = S.c[0][k] - x1[0];
+                if (J.bc)
+                    e1 = e1 >= J.H[0] ? e1 - J.L[0] : (e1 < -J.H[0] ? e1 + J.L[0] : e1);
+                key1 = nd_key_q<KIND>(J, DIM > 1 ? e1 * e1 + T : e1 * e1, p);
+            }
+        }
         if (key < best || (key == best && id < blab)) {
             best = key;
             blab = id;
+        }
+        if (two && (key1 < best1 || (key1 == best1 && id < blab1))) {
+            best1 = key1;
+            blab1 = id;
         }
     }
 }
@@ -729,17 +768,23 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
         NdTile<DIM> G;
         int64_t rem = t;
         int l = tid;
-        bool live = true;
+        // threads along axis 0; with two voxels per thread the second is tx0
+        // voxels further along axis 0
+        const int tx0 = J.T[0] / J.vpt;
+        const bool two = J.vpt > 1;
+        bool live = true, live1 = two;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             const int64_t tc = rem % J.nt[a];
             rem /= J.nt[a];
             v0[a] = tc * J.T[a];
             ve[a] = (v0[a] + J.T[a] < J.n[a] ? v0[a] + J.T[a] : J.n[a]) - 1;
-            const int off = l % J.T[a];
-            l /= J.T[a];
+            const int ta = a == 0 ? tx0 : J.T[a];
+            const int off = l % ta;
+            l /= ta;
             vi[a] = v0[a] + off;
             live = live && vi[a] <= ve[a];
+            live1 = live1 && vi[a] + (a == 0 ? tx0 : 0) <= ve[a];
             if (LAT) {
                 G.lo[a] = ((double)v0[a] + 0.5) / (double)J.n[a];
                 G.hi[a] = ((double)ve[a] + 0.5) / (double)J.n[a];
@@ -753,15 +798,22 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
             bl[a] = min(max(b0, 0), J.nb[a] - 1);
             bh[a] = min(max(b1, 0), J.nb[a] - 1);
         }
+        double x1[LAT ? DIM : 1];
+        if (!LAT)
+            x1[0] = ((double)(vi[0] + tx0) + 0.5) * J.h[0];
         if (LAT) {
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                // the voxel centre, summed as the definition sums it
+                // the voxel centres, summed as the definition sums them
                 double acc = ((double)vi[0] + 0.5) * J.hv[0][a];
+                double acc1 = ((double)(vi[0] + tx0) + 0.5) * J.hv[0][a];
 #pragma unroll
-                for (int i = 1; i < DIM; ++i)
+                for (int i = 1; i < DIM; ++i) {
                     acc = acc + ((double)vi[i] + 0.5) * J.hv[i][a];
+                    acc1 = acc1 + ((double)vi[i] + 0.5) * J.hv[i][a];
+                }
                 x[a] = acc;
+                x1[LAT ? a : 0] = acc1;
                 // bounding box of the tile's centres, term by term
                 double b0 = 0.0, b1 = 0.0;
 #pragma unroll
@@ -776,8 +828,9 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
             }
         }
         live = live && l == 0;
-        double best = __builtin_inf();
-        int blab = 0x7fffffff;
+        live1 = live1 && l == 0;
+        double best = __builtin_inf(), best1 = __builtin_inf();
+        int blab = 0x7fffffff, blab1 = 0x7fffffff;
         if (!bad) {
             // 1. grow the box of visited bins until the sites beyond it
             //    provably lose; their keys are at least gap^2, gap^2 - max w
@@ -924,8 +977,8 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
                         mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
-                        if (live)
-                            nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, best, blab);
+                        if (live || live1)
+                            nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, x1, two, best, blab, best1, blab1);
                         __syncthreads();
                         if (tid == 0)
                             S.count = 0;
@@ -935,20 +988,27 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
             }
             const int cnt = S.count;
             mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
-            if (live && cnt > 0)
-                nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, best, blab);
+            if ((live || live1) && cnt > 0)
+                nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, x1, two, best, blab, best1, blab1);
             __syncthreads();
         }
-        if (live) {
+        if (live || live1) {
             int64_t lin = 0, stride = 1;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 lin += vi[a] * stride;
                 stride *= J.n[a];
             }
-            J.labels[lin] = bad ? -1 : blab;
-            if (J.keys)
-                J.keys[lin] = bad ? __builtin_nan("") : best;
+            if (live) {
+                J.labels[lin] = bad ? -1 : blab;
+                if (J.keys)
+                    J.keys[lin] = bad ? __builtin_nan("") : best;
+            }
+            if (live1) {
+                J.labels[lin + tx0] = bad ? -1 : blab1;
+                if (J.keys)
+                    J.keys[lin + tx0] = bad ? __builtin_nan("") : best1;
+            }
         }
     }
 }

@@ -335,6 +335,40 @@ def test_lattice_larger_sampled(ctx, kind):
     assert np.array_equal(key[idx].view(np.int64), refk.view(np.int64))
 
 
+@pytest.mark.parametrize("case", ["2d_ragged", "3d_laguerre", "3d_jm", "4d_sampled"])
+def test_two_voxels_per_thread(ctx, case):
+    """Grids large enough for the general kernel to give each thread two
+    voxels along axis 0 (orthogonal periods, 2 to 4 axes, axis 0 at least
+    eight thread widths long, 8,192 or more doubled tiles), with ragged tails
+    on every axis: labels and keys against the oracle."""
+    rng = np.random.default_rng(940 + len(case))
+    if case == "2d_ragged":
+        w = workload((2007, 2100), 0, True, I.uniform_sites(rng, 20000, [2007.0, 2100.0]), name=case)
+    elif case == "3d_laguerre":
+        n = (200, 190, 180)
+        c = I.uniform_sites(rng, 8000, [float(v) for v in n])
+        w = workload(n, 1, False, c, I.lognormal_weights(rng, 8000, 3.0, 0.3), name=case)
+    elif case == "3d_jm":
+        n = (160, 170, 176)
+        c = I.uniform_sites(rng, 5000, [float(v) for v in n])
+        w = workload(n, 2, True, c, rng.uniform(0.0, 15.0, 5000), 0.7, name=case)
+    else:
+        n = (56, 40, 44, 48)
+        c = I.uniform_sites(rng, 9000, [float(v) for v in n])
+        w = workload(n, 0, True, c, name=case)
+        lab, key, st = run_nd(ctx, w)
+        assert st == 0
+        vox = np.stack([rng.integers(0, v, 20000) for v in n], axis=1)
+        vox[:4] = [[55, 39, 43, 47], [54, 0, 0, 0], [0, 39, 43, 47], [7, 20, 30, 40]]  # tails, both halves
+        p = oracle.problem(n, w.L, 0, True, 1.0)
+        ref, refk = oracle.label_points(p, w.coords, None, vox)
+        idx = tuple(vox[:, a] for a in reversed(range(4)))
+        assert np.array_equal(lab[idx], ref)
+        assert np.array_equal(key[idx].view(np.int64), refk.view(np.int64))
+        return
+    check(ctx, w, generic=True)
+
+
 def test_lattice_errors(ctx):
     from paper_2201_13234_amd import vtess
     w, P = lattice_case("hex2", 0, 920)
