@@ -325,7 +325,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the labelling path "
-              "has no multi-GPU part; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "has no multi-GPU part (one process labels whole diagrams on one device).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
