@@ -118,6 +118,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _dev_ptr(t, name, dtype, min_numel):
+    """Pointer to a contiguous device tensor of `dtype` with at least
+    `min_numel` elements (the kernels write that many), else ValueError."""
+    import torch
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} needs at least {min_numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _status_ptr(status, njobs):
+    import torch
+    return _dev_ptr(status, "status", torch.int32, njobs)
+
+
 @dataclass
 class Job:
     """One diagram: device tensors for sites, parameters and labels."""
@@ -144,6 +162,8 @@ class Job:
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor")
         if self.coords.dim() != 2 or self.coords.shape[1] != d:
             raise ValueError("coords must be [nsites, ndim]")
+        if self.param is not None and self.param.numel() != self.coords.shape[0]:
+            raise ValueError("param must hold one value per site")
         if self.labels.numel() != int(_prod(self.n)):
             raise ValueError("labels must hold prod(n) elements")
         if self.keys is not None and self.keys.numel() != int(_prod(self.n)):
@@ -239,7 +259,7 @@ class Context:
 
     def tessellate(self, job, status=None, stream=None):
         cj = job.to_c()
-        _check(lib().vt_tessellate(self.handle, ctypes.byref(cj), _ptr(status), _stream(stream)),
+        _check(lib().vt_tessellate(self.handle, ctypes.byref(cj), _status_ptr(status, 1), _stream(stream)),
                "vt_tessellate")
         return job.labels
 
@@ -247,26 +267,27 @@ class Context:
         """Any number of axes from 1 to 6 (vt_tessellate_nd); generic=True
         runs the general kernel also for 2 and 3 axes."""
         cj = job.to_c_nd(generic)
-        _check(lib().vt_tessellate_nd(self.handle, ctypes.byref(cj), _ptr(status), _stream(stream)),
+        _check(lib().vt_tessellate_nd(self.handle, ctypes.byref(cj), _status_ptr(status, 1), _stream(stream)),
                "vt_tessellate_nd")
         return job.labels
 
     def tessellate_batch(self, jobs, status=None, stream=None):
         arr = (VtJob * len(jobs))(*[j.to_c() for j in jobs])
-        _check(lib().vt_tessellate_batch(self.handle, arr, len(jobs), _ptr(status), _stream(stream)),
+        _check(lib().vt_tessellate_batch(self.handle, arr, len(jobs), _status_ptr(status, len(jobs)),
+                                         _stream(stream)),
                "vt_tessellate_batch")
         return [j.labels for j in jobs]
 
     def bins_build(self, job, status=None, stream=None):
         cj = job.to_c()
         h = ctypes.c_void_p()
-        _check(lib().vt_bins_build(self.handle, ctypes.byref(cj), ctypes.byref(h), _ptr(status),
+        _check(lib().vt_bins_build(self.handle, ctypes.byref(cj), ctypes.byref(h), _status_ptr(status, 1),
                                    _stream(stream)), "vt_bins_build")
         return Bins(self, h, job)
 
     def label_batch(self, bins, status=None, stream=None):
         arr = (ctypes.c_void_p * len(bins))(*[b.handle for b in bins])
-        _check(lib().vt_label_batch(self.handle, arr, len(bins), _ptr(status), _stream(stream)),
+        _check(lib().vt_label_batch(self.handle, arr, len(bins), _status_ptr(status, len(bins)), _stream(stream)),
                "vt_label_batch")
 
     def autotune(self, samples, cache_path=None):
@@ -297,8 +318,10 @@ class Context:
         """Adds the checksum terms of a device int32 label image to `acc` (a
         zeroed int64 device tensor of one element); the checksum is
         int(acc) % (2**31 - 1) once the stream reaches this point."""
-        _check(lib().vt_label_digest(self.handle, _ptr(labels), labels.numel(), _ptr(acc), _stream(stream)),
-               "vt_label_digest")
+        import torch
+        lp = _dev_ptr(labels, "labels", torch.int32, 0)
+        ap = _dev_ptr(acc, "acc", torch.int64, 1)
+        _check(lib().vt_label_digest(self.handle, lp, labels.numel(), ap, _stream(stream)), "vt_label_digest")
 
     def label_digest(self, labels, stream=None):
         """Checksum of a device label image (waits for the stream)."""
@@ -322,8 +345,10 @@ class Context:
     def numerics_probe(self, x, den, stream=None):
         """Device sqrt(x) and x / den (binary64), for checking IEEE rounding."""
         import torch
+        xp = _dev_ptr(x, "x", torch.float64, 0)
+        dp = _dev_ptr(den, "den", torch.float64, x.numel())
         s = torch.empty_like(x)
         q = torch.empty_like(x)
-        _check(lib().vt_numerics_probe(self.handle, _ptr(x), _ptr(den), _ptr(s), _ptr(q), x.numel(),
+        _check(lib().vt_numerics_probe(self.handle, xp, dp, _ptr(s), _ptr(q), x.numel(),
                                        _stream(stream)), "vt_numerics_probe")
         return s, q

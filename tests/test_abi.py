@@ -107,3 +107,21 @@ def test_inputs_are_deterministic():
     assert abs(np.median(np.sqrt(w.param)) / (0.5 * sp) - 1) < 0.02
     j = I.stream_job(5)
     assert j.ndim in (2, 3) and 10 <= j.nsites <= 20_000
+
+
+def test_binding_rejects_bad_tensors_before_any_call():
+    """The binding checks what the kernels will read and write (dtype,
+    device, contiguity, length) before it calls the library."""
+    import pytest
+    import torch
+    from paper_2201_13234_amd import vtess
+    with pytest.raises(ValueError, match="device tensor"):
+        vtess._status_ptr(torch.zeros(4, dtype=torch.int32), 1)        # host memory
+    with pytest.raises(ValueError, match="device tensor"):
+        vtess._status_ptr(torch.zeros(4, dtype=torch.int64), 1)        # wrong dtype
+    assert vtess._status_ptr(None, 5).value is None
+    job = vtess.Job(n=(4, 4), L=(4.0, 4.0), kind=vtess.LAGUERRE, periodic=True,
+                    coords=torch.zeros(3, 2, dtype=torch.float64), param=torch.zeros(2, dtype=torch.float64),
+                    labels=torch.zeros(16, dtype=torch.int32))
+    with pytest.raises(ValueError, match="device tensor"):
+        job.to_c()                                                       # host tensors

@@ -320,6 +320,15 @@ def test_invalid_scalars_raise_before_launch(ctx):
     w = workload((8, 8, 8), 1, True, np.full((3, 3), 1.0), None)
     with pytest.raises(vtess.VtError):
         ctx.tessellate(to_dev(w))
+    # buffers the kernels would overrun are refused by the binding
+    w = workload((8, 8, 8), 1, True, np.full((3, 3), 1.0), np.zeros(3))
+    job = to_dev(w)
+    job.param = job.param[:2]
+    with pytest.raises(ValueError, match="one value per site"):
+        ctx.tessellate(job)
+    jobs = [to_dev(w), to_dev(w), to_dev(w)]
+    with pytest.raises(ValueError, match="at least 3"):
+        ctx.tessellate_batch(jobs, status=torch.zeros(2, dtype=torch.int32, device="cuda:0"))
 
 
 def test_deterministic(ctx):
