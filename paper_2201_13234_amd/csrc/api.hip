@@ -202,11 +202,12 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
             d->h[a] = 1.0;
             d->H[a] = 0.5;
         }
+        // checked before the product: three axes of up to 2^30 overflow int64
+        if (nvox > ((int64_t)1 << 40) / d->n[a])
+            return fail(VT_ERR_INVALID, "more than 2^40 voxels");
         nvox *= d->n[a];
         V *= d->L[a];
     }
-    if (nvox > (int64_t)1 << 40)
-        return fail(VT_ERR_INVALID, "more than 2^40 voxels");
     d->nvox = nvox;
     d->nsites = (int32_t)j->nsites;
     d->growth = j->kind == VT_JOHNSON_MEHL ? j->growth : 1.0;

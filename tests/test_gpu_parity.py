@@ -320,6 +320,17 @@ def test_invalid_scalars_raise_before_launch(ctx):
     w = workload((8, 8, 8), 1, True, np.full((3, 3), 1.0), None)
     with pytest.raises(vtess.VtError):
         ctx.tessellate(to_dev(w))
+    # a grid of more than 2^40 voxels, whose count would overflow int64 when
+    # multiplied out, is refused while planning (no buffer is touched)
+    import ctypes
+    cj = vtess.VtJob()
+    cj.ndim, cj.kind, cj.bc, cj.nsites = 3, 0, 1, 1
+    for a in range(3):
+        cj.n[a], cj.L[a] = 1 << 30, 1.0
+    cj.coords = cj.labels = 256          # never dereferenced: planning fails first
+    nb, cfg, bf = (ctypes.c_int32 * 3)(), ctypes.c_int32(), ctypes.c_double()
+    code = vtess.lib().vt_plan(ctx.handle, ctypes.byref(cj), nb, ctypes.byref(cfg), ctypes.byref(bf))
+    assert code == vtess.ERR_INVALID and "2^40" in vtess.last_error()
     # buffers the kernels would overrun are refused by the binding
     w = workload((8, 8, 8), 1, True, np.full((3, 3), 1.0), np.zeros(3))
     job = to_dev(w)
