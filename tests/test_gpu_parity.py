@@ -373,6 +373,36 @@ def test_numerics_probe_is_ieee(ctx):
     assert np.array_equal(q.cpu().numpy().view(np.uint64), (x / den).view(np.uint64))
 
 
+def test_numerics_probe_hard_cases(ctx):
+    # Square roots whose exact value lies near a rounding midpoint or near a
+    # representable number (x = fl(y^2) for y and for y half an ulp above y)
+    # are the inputs where a refinement without a correct final rounding goes
+    # wrong; 12 M of them plus 4 M random bit patterns, and 4 M divisions with
+    # random operands, against numpy bit for bit.
+    import torch
+    rng = np.random.default_rng(16)
+    m = 4_000_000
+    y = np.exp(rng.uniform(-340.0, 340.0, m))
+    # (y + ulp/2)^2 in extended precision, then rounded: its square root lies
+    # next to the midpoint between y and its neighbour
+    mid = np.longdouble(y) + np.longdouble(np.spacing(y)) / 2
+    x = np.concatenate([y * y, (y + np.spacing(y)) * (y + np.spacing(y)), (mid * mid).astype(np.float64),
+                        rng.integers(1, 0x7FF0000000000000, m, dtype=np.int64).view(np.float64)])
+    x = x[np.isfinite(x) & (x > 0)]
+    num = np.exp(rng.uniform(-300.0, 300.0, m))
+    den = np.exp(rng.uniform(-300.0, 300.0, m))
+    dx = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    dd = torch.from_numpy(np.ones_like(x)).cuda()
+    s, _ = ctx.numerics_probe(dx, dd)
+    torch.cuda.synchronize()
+    bad = np.flatnonzero(s.cpu().numpy().view(np.uint64) != np.sqrt(x).view(np.uint64))
+    assert bad.size == 0, f"{bad.size} square roots differ, first x = {x[bad[0]]!r}"
+    _, q = ctx.numerics_probe(torch.from_numpy(num).cuda(), torch.from_numpy(den).cuda())
+    torch.cuda.synchronize()
+    bad = np.flatnonzero(q.cpu().numpy().view(np.uint64) != (num / den).view(np.uint64))
+    assert bad.size == 0, f"{bad.size} quotients differ, first {num[bad[0]]!r} / {den[bad[0]]!r}"
+
+
 # ------------------------------------------------------------ full-size configs
 
 @pytest.mark.parametrize("name", ["M2", "M3", "M4"])
