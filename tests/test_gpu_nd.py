@@ -369,6 +369,14 @@ def test_two_voxels_per_thread(ctx, case):
     check(ctx, w, generic=True)
 
 
+def test_nd_many_bins(ctx):
+    # 80,000 sites in 4D: tens of thousands of bins, a multi-block bin scan
+    rng = np.random.default_rng(950)
+    n = (20, 18, 22, 16)
+    w = workload(n, 0, True, I.uniform_sites(rng, 80_000, [float(v) for v in n]), name="nd_many_bins")
+    check(ctx, w)
+
+
 def test_lattice_errors(ctx):
     from paper_2201_13234_amd import vtess
     w, P = lattice_case("hex2", 0, 920)

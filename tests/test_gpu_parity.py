@@ -157,6 +157,18 @@ def test_more_sites_than_voxels(ctx):
             check(ctx, workload(n, kind, kind != 1, pts, param, 1.0, name=f"dense{d}{kind}"))
 
 
+@pytest.mark.parametrize("nsites", [60_000, 100_000])
+def test_many_bins(ctx, nsites):
+    """Dense sites on a small grid: 59,319 and 97,336 bins, so the bin scan
+    spans 15 and 24 blocks."""
+    rng = np.random.default_rng(nsites)
+    n = (96, 96, 96)
+    w = workload(n, 0, True, I.uniform_sites(rng, nsites, [96.0] * 3), name=f"bins{nsites}")
+    bins = ctx.plan(__import__("gpu_util").to_dev(w))["bins"]
+    assert int(np.prod(bins)) == (59_319 if nsites == 60_000 else 97_336)
+    check(ctx, w)
+
+
 def test_thin_grids(ctx):
     rng = np.random.default_rng(12)
     for n in ((1, 300), (300, 1), (1, 1, 500), (500, 1, 1), (1, 200, 3), (9, 1, 130)):
