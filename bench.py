@@ -55,14 +55,23 @@ def source_digest():
     return h.hexdigest()
 
 
-def load_counters(workload):
+def plan_key(plan):
+    """A launch plan (bins per axis, tile configuration, bin factor) in the
+    form the counter summary stores."""
+    return {"bins": [int(b) for b in plan["bins"]], "tile_cfg": int(plan["tile_cfg"]),
+            "bin_factor": float(plan["bin_factor"])}
+
+
+def load_counters(workload, plan):
     """Committed counter summary for this workload, if it was taken on the
-    current labelling kernel source (else None)."""
+    current labelling kernel source with the same launch plan (else None)."""
     try:
         rec = json.load(open(counters_path(workload)))
     except (OSError, ValueError):
         return None
     if rec.get("label_kernel_sha256") != source_digest() or rec.get("workload") != workload:
+        return None
+    if rec.get("plan") != plan_key(plan):
         return None
     return rec
 
@@ -89,6 +98,14 @@ def _per_dispatch(path, counter, match):
     tot = sum(sums[k][counter] for k in hits)
     n = sum(nd[k] for k in hits)
     return tot / n, n, hits
+
+
+def plan_from_log(path):
+    """The launch plan printed in the bench line of a counter run's log."""
+    lines = [l for l in open(path) if l.startswith("{") and '"metric"' in l]
+    if not lines:
+        raise SystemExit(f"{path}: no bench line")
+    return plan_key(json.loads(lines[-1])["config"]["plan"])
 
 
 def summarize_counters(args):
@@ -119,6 +136,7 @@ def summarize_counters(args):
         "hbm_read_bytes_per_launch": round(lf * 1024.0 * fetch_scale),
         "hbm_write_bytes_per_launch": round(lw * 1024.0 * write_scale),
         "dispatches": n_lf,
+        "plan": plan_from_log(args.plan_from),
         "commands": args.commands,
     }
     rec["hbm_bytes_per_launch"] = rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
@@ -315,12 +333,16 @@ def main():
                     help="no GPU run: write the counter summary of --config from three rocprofv3 "
                          "counter_collection.csv files (SQ_CSV may be '-')")
     ap.add_argument("--commands", default="", help="with --summarize: the commands that made the CSVs")
+    ap.add_argument("--plan-from", default="", help="with --summarize: a log of one of those runs (its "
+                                                     "bench line gives the launch plan)")
     args = ap.parse_args()
     if args.summarize:
         from paper_2201_13234_amd import inputs
         args.workload_name = inputs.CONFIGS[args.config]().name
         if args.copy_probe_mib <= 0:
             raise SystemExit("--summarize needs --copy-probe-mib (the size the runs copied)")
+        if not args.plan_from:
+            raise SystemExit("--summarize needs --plan-from (a log with the runs' bench line)")
         summarize_counters(args)
         return
     if args.gpus != 1:
@@ -386,7 +408,7 @@ def main():
     evals = math.log(w.nsites) + 1.0
     alg_flops = w.nvox * evals * per_key
     tflops = alg_flops / (label_avg_ms * 1e-3) / 1e12
-    cnt = load_counters(w.name)
+    cnt = load_counters(w.name, ctx.plan(job))
     roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
                 "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
