@@ -141,8 +141,10 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
             // many more sites than their tiles need
             bf = vps >= 2000.0 ? 2.0 : 1.2;
         } else {
+            // measured from 447 to 4,474 voxels per site (divided by 1.5):
+            // bins of one spacing beat 1.2 spacings by 0.3 to 3 %
             cfg = cfg == 0 ? 1 : cfg;
-            bf = 1.2;
+            bf = 1.0;
         }
     } else {
         cfg = vps >= 144.0 ? 0 : (vps >= 81.0 ? 1 : (vps >= 20.0 ? 2 : 3));
