@@ -114,16 +114,16 @@ const TuneEntry* find_tune(const vt_ctx* ctx, const vt_job* j, int64_t nvox)
 }
 
 // Tile configuration and bin size: forced, tuned, or default.  The default
-// tile shrinks as sites get denser (voxels per site), so that a tile's
-// candidate list stays well under its capacity: thresholds from the candidate
-// counts of uniform random sites, 1.5 times stricter for Laguerre and
-// Johnson-Mehl diagrams, whose weights and times let farther sites compete.
-// Among the sparse settings, the fastest measured for 3D uniform random
-// sites: Voronoi and Laguerre diagrams gather from bins larger than the mean
-// site spacing (fewer bin visits per region; Laguerre cells vary more in
-// size); a Johnson-Mehl diagram, whose cells reach further, labels best with
-// 8x8x8 tiles.  Batched launches group jobs by configuration, so the same
-// choice holds there.
+// tile shrinks as sites get denser (voxels per site, divided by 1.5 for
+// Laguerre and Johnson-Mehl diagrams, whose weights and times let farther
+// sites compete), so that a tile's candidate list stays within its capacity
+// or overflows to the fallback rarely enough to pay.  The 3D thresholds and
+// bin factors are the fastest measured per kind on uniform random sites
+// (384^3 and 512^3 grids): larger bins than the mean spacing mean fewer bin
+// visits per region, until dense grids overflow tiles; a Johnson-Mehl
+// diagram, whose cells reach further, labels best with 8x8x8 tiles.
+// Batched launches group jobs by configuration, so the same choice holds
+// there.
 void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_out, double* bf_out)
 {
     const double vps = (double)nvox / (double)std::max<int64_t>(j->nsites, 1) /
@@ -131,19 +131,22 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
     int cfg;
     double bf = 1.0;
     if (j->ndim == 3) {
-        cfg = vps >= 1100.0 ? 0 : (vps >= 216.0 ? 1 : (vps >= 91.0 ? 2 : 3));
         if (j->kind == VT_VORONOI) {
-            // measured: 1.6 spacings below 2,500 voxels per site (M2 at 1,342:
-            // 0.718 -> 0.692 ms against 1.4), 1.4 in sparser grids
-            bf = vps >= 2500.0 ? 1.4 : 1.6;
+            cfg = vps >= 1100.0 ? 0 : (vps >= 140.0 ? 1 : (vps >= 91.0 ? 2 : 3));
+            // 1.6 spacings below 2,500 voxels per site (M2 at 1,342: 0.718 ->
+            // 0.692 ms against 1.4), 1.4 in sparser grids, 1.2 in the dense
+            // end of 8x8x8 tiles, where larger bins overflow tiles
+            bf = vps >= 2500.0 ? 1.4 : (vps >= 225.0 ? 1.6 : 1.2);
         } else if (j->kind == VT_LAGUERRE) {
+            // near the thresholds, where a few heavy weights (the reach uses
+            // the largest) overflow region lists on some site sets, the next
+            // smaller tile is kept
+            cfg = vps >= 1100.0 ? 0 : (vps >= 240.0 ? 1 : (vps >= 91.0 ? 2 : 3));
             // large bins only where sites are sparse: denser jobs would gather
             // many more sites than their tiles need
             bf = vps >= 2000.0 ? 2.0 : 1.2;
         } else {
-            // measured from 447 to 4,474 voxels per site (divided by 1.5):
-            // bins of one spacing beat 1.2 spacings by 0.3 to 3 %
-            cfg = cfg == 0 ? 1 : cfg;
+            cfg = vps >= 130.0 ? 1 : (vps >= 91.0 ? 2 : 3);
             bf = 1.0;
         }
     } else {

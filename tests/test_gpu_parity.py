@@ -241,7 +241,7 @@ def test_dense_sites_default_tiles(ctx, kind, d):
     n = (48, 40, 36) if d == 3 else (200, 150)
     nvox = int(np.prod(n))
     seen = set()
-    for vps in (1500, 400, 200, 60, 8):
+    for vps in (1500, 400, 200, 160, 60, 8):
         w = I.make(n, kind, True, max(1, nvox // vps), 900 + vps + 7 * kind + d, growth=0.9)
         seen.add(ctx.plan(to_dev(w))["tile_cfg"])
         check(ctx, w)
