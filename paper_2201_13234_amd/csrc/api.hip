@@ -138,10 +138,10 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
             // end of 8x8x8 tiles, where larger bins overflow tiles
             bf = vps >= 2500.0 ? 1.4 : (vps >= 225.0 ? 1.6 : 1.2);
         } else if (j->kind == VT_LAGUERRE) {
-            // near the thresholds, where a few heavy weights (the reach uses
-            // the largest) overflow region lists on some site sets, the next
-            // smaller tile is kept
-            cfg = vps >= 1100.0 ? 0 : (vps >= 240.0 ? 1 : (vps >= 91.0 ? 2 : 3));
+            // (the region gather leaves out sites that provably lose when a
+            // round would overflow, which keeps these larger tiles usable
+            // where a few heavy weights set the reach for everyone)
+            cfg = vps >= 800.0 ? 0 : (vps >= 200.0 ? 1 : (vps >= 91.0 ? 2 : 3));
             // large bins only where sites are sparse: denser jobs would gather
             // many more sites than their tiles need
             bf = vps >= 2000.0 ? 2.0 : 1.2;

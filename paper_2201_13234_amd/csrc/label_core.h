@@ -1198,6 +1198,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
         }
         int nR = 0, nDone = 0;
         bool overflow = false;
+        double skip_cut = __builtin_inf();  // UB + M of the previous round (Laguerre load test)
         double ubT = __builtin_inf();  // this tile's upper bound (wave-uniform)
         int ubPos = -1;                // region-list position of a site attaining it
         for (int round = 0;; ++round) {
@@ -1237,15 +1238,64 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     }
                 }
                 int total;
-                const int off = block_excl_scan(cnt, total, R.wsum, tid);
+                int off = block_excl_scan(cnt, total, R.wsum, tid);
+                // Laguerre, from the second round on, when the round's bins
+                // would overflow the list: a site whose own lower bound over
+                // the region (gap to its nearest periodic image, squared,
+                // minus its weight) exceeds UB + M loses at every voxel, so
+                // it is not loaded.  The reach follows the largest weight of
+                // all sites, and this keeps one heavy site from overflowing
+                // the lists of every region near it.  (The condition is the
+                // same for the whole workgroup; bins of more than 64 sites
+                // load whole.)
+                unsigned long long keep = ~0ull;
+                const bool filtered = KIND == KL && nR + total > CAP_R && skip_cut < __builtin_inf();
+                if (filtered) {
+                    int nload = cnt;
+                    if (cnt > 0 && cnt <= 64) {
+                        keep = 0ull;
+                        nload = 0;
+                        for (int k = 0; k < cnt; ++k) {
+                            const double4 sv = J.sites[src + k];
+                            const double sc[3] = {sv.x, sv.y, sv.z};
+                            double g2 = 0.0;
+#pragma unroll
+                            for (int a = 0; a < DIM; ++a) {
+                                double gap = fmax(BR.lo[a] - sc[a], sc[a] - BR.hi[a]);
+                                if (periodic) {
+                                    const double lo = sc[a] - J.L[a], hi = sc[a] + J.L[a];
+                                    gap = fmin(gap, fmin(fmax(BR.lo[a] - lo, lo - BR.hi[a]),
+                                                         fmax(BR.lo[a] - hi, hi - BR.hi[a])));
+                                }
+                                g2 += gap > 0.0 ? gap * gap : 0.0;
+                            }
+                            if (g2 - sv.w <= skip_cut) {
+                                keep |= 1ull << k;
+                                ++nload;
+                            }
+                        }
+                    }
+                    off = block_excl_scan(nload, total, R.wsum, tid);
+                }
                 if (nR + total > CAP_R) {
                     overflow = true;
                     break;
                 }
-                for (int k = 0; k < cnt; ++k) {
-                    R.rs[nR + off + k] = J.sites[src + k];
-                    R.ri[nR + off + k] = J.sidx[src + k];
-                    R.rf[nR + off + k] = code;
+                if (!filtered) {
+                    for (int k = 0; k < cnt; ++k) {
+                        R.rs[nR + off + k] = J.sites[src + k];
+                        R.ri[nR + off + k] = J.sidx[src + k];
+                        R.rf[nR + off + k] = code;
+                    }
+                } else {
+                    for (int k = 0, d = 0; k < cnt; ++k) {
+                        if (!((keep >> k) & 1ull))
+                            continue;
+                        R.rs[nR + off + d] = J.sites[src + k];
+                        R.ri[nR + off + d] = J.sidx[src + k];
+                        R.rf[nR + off + d] = code;
+                        ++d;
+                    }
                 }
                 nR += total;
             }
@@ -1276,6 +1326,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             }
             nDone = nR;
             const double UB = block_max(G.live ? ubT : -__builtin_inf(), R.wred, tid);
+            skip_cut = UB + C.M;
             // move the faces that are too close
             const double reach = needed_reach<KIND>(C, UB);
             const double need = reach + reach * 0x1p-20 + 1e-300;

@@ -232,6 +232,37 @@ def test_parameter_extremes_in_later_blocks(ctx):
         assert np.array_equal(got, ref), f"batch {x.name}: " + describe_mismatch(got, ref)
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_laguerre_heavy_weights_fill_region_lists(ctx, periodic):
+    """Laguerre sites at about 340 voxels per site with a few weights far
+    above the rest: the gather reach follows the largest weight, so later
+    gather rounds would overflow the region lists and the gather leaves out
+    the sites that provably lose (their own lower bound over the region above
+    UB + M).  Labels and keys must still equal the oracle's."""
+    import torch
+    from gpu_util import to_dev
+    rng = np.random.default_rng(960 + int(periodic))
+    n = (160, 150, 170)
+    ns = int(np.prod(n) // 340)
+    coords = I.uniform_sites(rng, ns, [float(v) for v in n])
+    sp = (np.prod(n) / ns) ** (1 / 3)
+    w = I.lognormal_weights(rng, ns, 0.5 * sp, 0.3)
+    w[rng.integers(0, ns, 6)] *= 25.0
+    wl = workload(n, 1, periodic, coords, w, name=f"lag_heavy_{periodic}")
+    assert ctx.plan(to_dev(wl))["tile_cfg"] == 1
+    job = to_dev(wl)
+    job.keys = torch.empty(tuple(reversed(n)), dtype=torch.float64, device="cuda:0")
+    st = torch.full((1,), 99, dtype=torch.int32, device="cuda:0")
+    ctx.tessellate(job, status=st)
+    torch.cuda.synchronize()
+    p = oracle.problem(n, [float(v) for v in n], 1, periodic)
+    ref, refk, _ = oracle.tessellate(p, coords, w, want_keys=True)
+    assert int(st.item()) == 0
+    got = job.labels.cpu().numpy()
+    assert np.array_equal(got, ref), describe_mismatch(got, ref)
+    assert np.array_equal(job.keys.cpu().numpy().view(np.int64), refk.view(np.int64))
+
+
 @pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("d", [2, 3])
 def test_dense_sites_default_tiles(ctx, kind, d):
