@@ -150,7 +150,15 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
             bf = 1.0;
         }
     } else {
-        cfg = vps >= 144.0 ? 0 : (vps >= 81.0 ? 1 : (vps >= 20.0 ? 2 : 3));
+        // measured per kind on 512^2 to 4096^2 grids from 12 to 300 voxels
+        // per site (same-box comparisons against the former common
+        // thresholds 144 / 81 / 20)
+        if (j->kind == VT_VORONOI)
+            cfg = vps >= 144.0 ? 0 : (vps >= 60.0 ? 1 : (vps >= 20.0 ? 2 : 3));
+        else if (j->kind == VT_LAGUERRE)
+            cfg = vps >= 90.0 ? 0 : (vps >= 38.0 ? 1 : (vps >= 20.0 ? 2 : 3));
+        else
+            cfg = vps >= 200.0 ? 0 : (vps >= 45.0 ? 1 : (vps >= 9.5 ? 2 : 3));
         // measured on 2048^2 to 8192^2 grids with 2,000 to 100,000 sites:
         // Voronoi and Laguerre label fastest from bins of 1.6 spacings (up
         // to 12 % faster than one spacing), Johnson-Mehl from 1.2 to 1.4
