@@ -132,7 +132,7 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
     double bf = 1.0;
     if (j->ndim == 3) {
         if (j->kind == VT_VORONOI) {
-            cfg = vps >= 1100.0 ? 0 : (vps >= 140.0 ? 1 : (vps >= 91.0 ? 2 : 3));
+            cfg = vps >= 1100.0 ? 0 : (vps >= 145.0 ? 1 : (vps >= 50.0 ? 2 : 3));
             // 1.6 spacings below 2,500 voxels per site (M2 at 1,342: 0.718 ->
             // 0.692 ms against 1.4), 1.4 in sparser grids, 1.2 in the dense
             // end of 8x8x8 tiles, where larger bins overflow tiles
@@ -141,12 +141,12 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
             // (the region gather leaves out sites that provably lose when a
             // round would overflow, which keeps these larger tiles usable
             // where a few heavy weights set the reach for everyone)
-            cfg = vps >= 800.0 ? 0 : (vps >= 200.0 ? 1 : (vps >= 91.0 ? 2 : 3));
+            cfg = vps >= 800.0 ? 0 : (vps >= 200.0 ? 1 : (vps >= 33.0 ? 2 : 3));
             // large bins only where sites are sparse: denser jobs would gather
             // many more sites than their tiles need
             bf = vps >= 2000.0 ? 2.0 : 1.2;
         } else {
-            cfg = vps >= 130.0 ? 1 : (vps >= 91.0 ? 2 : 3);
+            cfg = vps >= 130.0 ? 1 : (vps >= 45.0 ? 2 : 3);
             bf = 1.0;
         }
     } else {
