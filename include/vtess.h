@@ -184,7 +184,8 @@ vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path);
  * (tile_cfg < 0 and bin_factor <= 0 restore the tuned/default choice).
  * Tile configurations (voxels, x first): 3D 0 = 8x16x8, 1 = 8x8x8,
  * 2 = 8x4x4, 3 = 4x4x4; 2D 0 = 32x32, 1 = 32x16, 2 = 16x8, 3 = 8x8.  By default
- * the tile shrinks as the sites get denser (voxels per site). */
+ * the tile shrinks as the sites get denser (voxels per site).  The bin factor
+ * (bin side over the mean site spacing) applies to vt_tessellate_nd too. */
 vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor);
 
 /* Bins per axis and tile configuration the next call would use for job. */

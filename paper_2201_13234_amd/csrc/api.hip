@@ -697,7 +697,7 @@ void nd_tile_shape(const vt_job_nd* j, int32_t* T)
     }
 }
 
-vt_status plan_nd(const vt_job_nd* j, vt::NdDev* d)
+vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
 {
     if (!j)
         return fail(VT_ERR_INVALID, "job is NULL");
@@ -776,9 +776,13 @@ vt_status plan_nd(const vt_job_nd* j, vt::NdDev* d)
         V = std::fabs(det);
     }
 
-    // Bins: side ~ the mean site spacing (V / N)^(1/d), at most 2^20 per axis
-    // and about 4 N + 64 in total.
-    const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim);
+    // Bins: side ~ 1.2 mean site spacings (V / N)^(1/d), or the bin factor
+    // vt_set_params forces; at most 2^20 per axis and about 4 N + 64 in total.
+    // 1.2 measured fastest or level from 2 to 6 axes and in a triclinic cell
+    // (4D 64^4: 2.04 -> 1.93 ms against one spacing; 5D 24^5, 8,000 sites:
+    // 4.34 -> 3.28 ms).
+    const double bin_factor = ctx->force_bin > 0.0 ? ctx->force_bin : 1.2;
+    const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim) * bin_factor;
     int64_t nbins = 1;
     for (int a = 0; a < j->ndim; ++a) {
         const double f = std::floor(extent[a] / spacing + 0.5);
@@ -856,7 +860,7 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     }
     hipStream_t s = (hipStream_t)stream;
     vt::NdDev d;
-    vt_status st = plan_nd(job, &d);
+    vt_status st = plan_nd(ctx, job, &d);
     if (st != VT_OK)
         return st;
     VT_HIP(hipSetDevice(ctx->device));
