@@ -164,8 +164,8 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
         // to 12 % faster than one spacing), Johnson-Mehl from 1.2 to 1.4
         bf = j->kind == VT_JOHNSON_MEHL ? 1.2 : 1.6;
     }
-    if (cfg >= 2)
-        bf = 1.0;  // small regions: bins of one spacing keep the region list short
+    if (cfg >= 2)  // small regions: bins near one spacing keep the region list short
+        bf = j->ndim == 3 ? 1.2 : 1.0;  // 3D measured 2-4 % faster at 1.2, 2D level
     if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
         cfg = t->cfg;
         bf = t->bin_factor;

@@ -157,15 +157,15 @@ def test_more_sites_than_voxels(ctx):
             check(ctx, workload(n, kind, kind != 1, pts, param, 1.0, name=f"dense{d}{kind}"))
 
 
-@pytest.mark.parametrize("nsites", [60_000, 100_000])
-def test_many_bins(ctx, nsites):
-    """Dense sites on a small grid: 59,319 and 97,336 bins, so the bin scan
-    spans 15 and 24 blocks."""
+@pytest.mark.parametrize("nsites, nbins", [(60_000, 35_937), (100_000, 59_319), (240_000, 140_608)])
+def test_many_bins(ctx, nsites, nbins):
+    """Dense sites on a small grid: up to 140,608 bins (bins of 1.2 mean
+    spacings), so the bin scan spans 9 to 35 blocks."""
     rng = np.random.default_rng(nsites)
     n = (96, 96, 96)
     w = workload(n, 0, True, I.uniform_sites(rng, nsites, [96.0] * 3), name=f"bins{nsites}")
     bins = ctx.plan(__import__("gpu_util").to_dev(w))["bins"]
-    assert int(np.prod(bins)) == (59_319 if nsites == 60_000 else 97_336)
+    assert int(np.prod(bins)) == nbins
     check(ctx, w)
 
 
