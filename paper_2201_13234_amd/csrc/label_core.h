@@ -1175,10 +1175,13 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 int l = (int)(BR.lo[a] * J.inv_bs[a]), h = (int)(BR.hi[a] * J.inv_bs[a]);
                 l = max(0, min(l, nb - 1));
                 h = max(l, min(h, nb - 1));
-                // first box: the region's bins and GM more on each side
-                // (Johnson-Mehl reaches farther: its gather would almost
-                // always need a second round from one)
-                constexpr int GM = (KIND == KJM || KIND == KJD) ? 2 : 1;
+                // first box: the region's bins and GM more on each side.
+                // Johnson-Mehl reaches farther: its gather would almost
+                // always need a second round from one.  Laguerre takes the
+                // margin its plan gives (two with bins near the mean spacing,
+                // one with the large bins of sparse grids, whose first box
+                // would otherwise overflow).
+                const int GM = (KIND == KJM || KIND == KJD) ? 2 : (KIND == KL ? J.gather_margin : 1);
                 if (periodic) {
                     blo[a] = l - GM;
                     bhi[a] = h + GM;

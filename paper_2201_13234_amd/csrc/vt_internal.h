@@ -19,7 +19,8 @@ constexpr int WAVE = 64;
 struct JobDev {
     int32_t ndim, kind, bc, cfg;   // cfg: tile configuration id
     int32_t jm_div;                // Johnson-Mehl: 1 = divide by v, 0 = multiply by exact 1/v
-    int32_t nsites, nbins, pad0;
+    int32_t nsites, nbins;
+    int32_t gather_margin;         // bins beyond the region's own in its first gather box (Laguerre)
     int32_t n[3];                  // voxels per axis (n[2] = 1 in 2D)
     int32_t nb[3];                 // bins per axis (nb[2] = 1 in 2D)
     int32_t nr[3];                 // regions (groups of four tiles) per axis
