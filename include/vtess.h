@@ -29,6 +29,12 @@
  *    are found on the device: that job's labels become -1 and its status word
  *    (if given) becomes VT_ERR_INPUT once the stream has run the call.
  *  - Threading: a vt_ctx is used by one host thread at a time.
+ *  - Scale (Sec. 3 leaves it open; the bound keeps every squared distance, key
+ *    and rounding margin a finite normal binary64 number): lengths L_a, the
+ *    growth rate v and the entries and row lengths of period vectors lie in
+ *    [VT_SCALE_MIN, VT_SCALE_MAX] (else VT_ERR_INVALID before any launch);
+ *    |w_s|, |t_s| and, with period vectors, |coordinates| are at most
+ *    VT_SCALE_MAX (else VT_ERR_INPUT from the device).
  */
 #ifndef VTESS_H
 #define VTESS_H
@@ -51,6 +57,9 @@ typedef enum {
     VT_ERR_INPUT = 5    /* bad site coordinates or parameters, found on the device */
 } vt_status;
 
+#define VT_SCALE_MAX 0x1p200  /* about 1.6e60 */
+#define VT_SCALE_MIN 0x1p-200 /* about 6.2e-61 */
+
 typedef struct vt_ctx vt_ctx;   /* device, scratch pool, tuning table */
 typedef struct vt_bins vt_bins; /* one job's sites binned on the device */
 
@@ -61,15 +70,17 @@ typedef struct {
     int32_t bc;          /* vt_bc */
     int32_t reserved;    /* must be 0 */
     int64_t n[3];        /* voxels per axis, axis 0 fastest in memory; n[2] ignored in 2D */
-    double  L[3];        /* domain lengths > 0; L[2] ignored in 2D */
-    double  growth;      /* Johnson-Mehl growth rate v > 0 (G of eq. JMAK2); ignored otherwise */
+    double  L[3];        /* domain lengths in [VT_SCALE_MIN, VT_SCALE_MAX]; L[2] ignored in 2D */
+    double  growth;      /* Johnson-Mehl growth rate v in [VT_SCALE_MIN, VT_SCALE_MAX] (G of
+                          * eq. JMAK2); ignored otherwise */
     int64_t nsites;      /* 1 .. 2^31 - 1 */
     const double* coords;/* device, [nsites][ndim] binary64: in [0, L_a) for non-periodic
                           * boundaries; any finite value for periodic ones (brought into
                           * [0, L_a) by an exact fmod, then + L_a if negative, 0 if that
                           * sum rounds to L_a: App. A defines the L-periodic distance for
                           * points outside the unit cell) */
-    const double* param; /* device, [nsites]: Laguerre w_s, Johnson-Mehl t_s; NULL for Voronoi */
+    const double* param; /* device, [nsites]: Laguerre w_s, Johnson-Mehl t_s, |value| <=
+                          * VT_SCALE_MAX; NULL for Voronoi */
     int32_t* labels;     /* device, prod(n) int32 written by the call (x fastest) */
     double*  keys;       /* device, prod(n) binary64 or NULL: the winning key per voxel (the
                           * distance image: q for Voronoi, q - w for Laguerre, t + sqrt(q)/v
@@ -188,9 +199,19 @@ vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path);
  * (bin side over the mean site spacing) applies to vt_tessellate_nd too. */
 vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor);
 
-/* Bins per axis and tile configuration the next call would use for job. */
+/* Bins per axis and tile configuration the next call would use for job,
+ * after the same scalar checks as vt_tessellate (VT_ERR_INVALID on failure;
+ * nothing is launched and no device memory is touched).  ctx may be NULL: the
+ * default plan, without tuning cache or forced parameters.  Output pointers
+ * are host memory and may be NULL. */
 vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3,
                   int32_t* tile_cfg, double* bin_factor);
+
+/* The same for vt_tessellate_nd's general kernel: bins per axis and tile
+ * voxels per axis (host arrays of job->ndim entries, or NULL).  ctx may be
+ * NULL.  Jobs that vt_tessellate_nd would send to vt_tessellate are planned
+ * as general-kernel jobs here. */
+vt_status vt_plan_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* bins_per_axis, int32_t* tile_voxels);
 
 /* Device-numerics probe: sqrt_out[i] = sqrt(x[i]) and div_out[i] = x[i] / den[i]
  * computed by the same binary64 operations the labelling kernels use, so that

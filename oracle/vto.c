@@ -338,41 +338,50 @@ int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
         return VTO_ERR_INVALID;
     if (p->kind != VTO_VORONOI && !param)
         return VTO_ERR_INVALID;
-    if (p->kind == VTO_JOHNSON_MEHL && !(isfinite(p->growth) && p->growth > 0.0))
+    if (p->kind == VTO_JOHNSON_MEHL && !(p->growth >= VTO_SCALE_MIN && p->growth <= VTO_SCALE_MAX))
         return VTO_ERR_INVALID;
     if (p->lattice) {
         geo_t g;
+        int i;
         if (!p->periodic)
             return VTO_ERR_INVALID;
         for (a = 0; a < p->ndim * p->ndim; ++a)
-            if (!isfinite(p->periods[a]))
+            if (!(fabs(p->periods[a]) <= VTO_SCALE_MAX))
                 return VTO_ERR_INVALID;
+        for (i = 0; i < p->ndim; ++i) {
+            double len2 = 0.0, len;
+            for (a = 0; a < p->ndim; ++a)
+                len2 += p->periods[i * p->ndim + a] * p->periods[i * p->ndim + a];
+            len = sqrt(len2);
+            if (!(len >= VTO_SCALE_MIN && len <= VTO_SCALE_MAX))
+                return VTO_ERR_INVALID;
+        }
         for (a = 0; a < p->ndim; ++a)
             if (p->n[a] < 1 || p->n[a] > 2147483647LL)
                 return VTO_ERR_INVALID;
         geo_init(&g, p);
         for (a = 0; a < p->ndim; ++a)
-            if (!(g.rown[a] > 0.0))
+            if (!(g.rown[a] > 0.0 && isfinite(g.rown[a])))
                 return VTO_ERR_INVALID; /* singular period matrix */
     }
     for (a = 0; a < p->ndim; ++a) {
         if (p->n[a] < 1 || p->n[a] > 2147483647LL)
             return VTO_ERR_INVALID;
-        if (!(isfinite(p->L[a]) && p->L[a] > 0.0))
+        if (!p->lattice && !(p->L[a] >= VTO_SCALE_MIN && p->L[a] <= VTO_SCALE_MAX))
             return VTO_ERR_INVALID;
     }
     for (s = 0; s < nsites; ++s) {
         for (a = 0; a < p->ndim; ++a) {
             double c = coords[s * p->ndim + a];
             if (p->lattice) {
-                if (!isfinite(c))
+                if (!(fabs(c) <= VTO_SCALE_MAX))
                     return VTO_ERR_INPUT;
                 continue;
             }
             if (p->periodic ? !isfinite(c) : !(c >= 0.0 && c < p->L[a]))
                 return VTO_ERR_INPUT;
         }
-        if (p->kind != VTO_VORONOI && !isfinite(param[s]))
+        if (p->kind != VTO_VORONOI && !(fabs(param[s]) <= VTO_SCALE_MAX))
             return VTO_ERR_INPUT;
     }
     return VTO_OK;

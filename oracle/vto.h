@@ -88,9 +88,18 @@ typedef struct {
     int64_t n_step2;   /* keys evaluated in step 2 (= n_out * N_s) */
 } vto_stats;
 
+/* Supported scale.  The problem statement (Sec. 3) puts no bound on the
+ * lengths, times or weights; binary64 does.  Lengths L_a, the growth rate G
+ * and the period vectors' entries and lengths lie in [VTO_SCALE_MIN,
+ * VTO_SCALE_MAX]; |w_s|, |t_s| and, with period vectors, |site coordinates|
+ * are at most VTO_SCALE_MAX.  Then every squared distance and key is finite
+ * and the rounding margins the tests rely on stay normal numbers. */
+#define VTO_SCALE_MAX 0x1p200
+#define VTO_SCALE_MIN 0x1p-200
+
 /* Checks the problem scalars and every site (finite; inside [0,L_a) unless
- * the boundaries are periodic; finite parameter).  Returns VTO_OK,
- * VTO_ERR_INVALID (bad scalars) or VTO_ERR_INPUT (bad site data). */
+ * the boundaries are periodic; parameter within the scale bound).  Returns
+ * VTO_OK, VTO_ERR_INVALID (bad scalars) or VTO_ERR_INPUT (bad site data). */
 int vto_validate(const vto_problem* p, int64_t nsites, const double* coords,
                  const double* param);
 

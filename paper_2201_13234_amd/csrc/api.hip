@@ -166,18 +166,28 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
     }
     if (cfg >= 2)  // small regions: bins near one spacing keep the region list short
         bf = j->ndim == 3 ? 1.2 : 1.0;  // 3D measured 2-4 % faster at 1.2, 2D level
-    if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
-        cfg = t->cfg;
-        bf = t->bin_factor;
+    if (ctx) {  // planning without a context takes the defaults
+        if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
+            cfg = t->cfg;
+            bf = t->bin_factor;
+        }
+        if (ctx->force_cfg >= 0)
+            cfg = ctx->force_cfg;
+        if (ctx->force_bin > 0.0)
+            bf = ctx->force_bin;
     }
-    if (ctx->force_cfg >= 0)
-        cfg = ctx->force_cfg;
-    if (ctx->force_bin > 0.0)
-        bf = ctx->force_bin;
     if (cfg < 0 || cfg >= vt::kNumCfg)
         cfg = 0;
     *cfg_out = cfg;
     *bf_out = bf;
+}
+
+// A scalar inside the supported scale [VT_SCALE_MIN, VT_SCALE_MAX] (see the
+// header): squared distances, keys and rounding margins then stay finite
+// normal numbers.
+bool in_scale(double x)
+{
+    return x >= VT_SCALE_MIN && x <= VT_SCALE_MAX;
 }
 
 // Checks the scalars of a job and fills the geometry of its device record.
@@ -197,8 +207,8 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
         return fail(VT_ERR_INVALID, "coords and labels must be device pointers");
     if (j->kind != VT_VORONOI && !j->param)
         return fail(VT_ERR_INVALID, "param is required for Laguerre and Johnson-Mehl");
-    if (j->kind == VT_JOHNSON_MEHL && !(std::isfinite(j->growth) && j->growth > 0.0))
-        return fail(VT_ERR_INVALID, "growth rate must be finite and > 0");
+    if (j->kind == VT_JOHNSON_MEHL && !in_scale(j->growth))
+        return fail(VT_ERR_INVALID, "growth rate must lie in [2^-200, 2^200]");
     std::memset(d, 0, sizeof *d);
     d->ndim = j->ndim;
     d->kind = j->kind;
@@ -209,8 +219,8 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
         if (a < j->ndim) {
             if (j->n[a] < 1 || j->n[a] > (1 << 30))
                 return fail(VT_ERR_INVALID, "n[a] must be in [1, 2^30]");
-            if (!(std::isfinite(j->L[a]) && j->L[a] > 0.0))
-                return fail(VT_ERR_INVALID, "L[a] must be finite and > 0");
+            if (!in_scale(j->L[a]))
+                return fail(VT_ERR_INVALID, "L[a] must lie in [2^-200, 2^200]");
             d->n[a] = (int32_t)j->n[a];
             d->L[a] = j->L[a];
             d->h[a] = j->L[a] / (double)j->n[a];
@@ -568,8 +578,6 @@ vt_status vt_set_params(vt_ctx* ctx, int32_t tile_cfg, double bin_factor)
 
 vt_status vt_plan(vt_ctx* ctx, const vt_job* job, int32_t* bins_per_axis3, int32_t* tile_cfg, double* bin_factor)
 {
-    if (!ctx)
-        return fail(VT_ERR_INVALID, "ctx is NULL");
     JobDev d;
     vt_status st = plan_job(ctx, job, &d);
     if (st != VT_OK)
@@ -720,8 +728,8 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
         return fail(VT_ERR_INVALID, "coords and labels must be device pointers");
     if (j->kind != VT_VORONOI && !j->param)
         return fail(VT_ERR_INVALID, "param is required for Laguerre and Johnson-Mehl");
-    if (j->kind == VT_JOHNSON_MEHL && !(std::isfinite(j->growth) && j->growth > 0.0))
-        return fail(VT_ERR_INVALID, "growth rate must be finite and > 0");
+    if (j->kind == VT_JOHNSON_MEHL && !in_scale(j->growth))
+        return fail(VT_ERR_INVALID, "growth rate must lie in [2^-200, 2^200]");
     std::memset(d, 0, sizeof *d);
     d->ndim = j->ndim;
     d->kind = j->kind;
@@ -730,8 +738,8 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
     for (int a = 0; a < j->ndim; ++a) {
         if (j->n[a] < 1 || j->n[a] > (1 << 30))
             return fail(VT_ERR_INVALID, "n[a] must be in [1, 2^30]");
-        if (!j->periods && !(std::isfinite(j->L[a]) && j->L[a] > 0.0))
-            return fail(VT_ERR_INVALID, "L[a] must be finite and > 0");
+        if (!j->periods && !in_scale(j->L[a]))
+            return fail(VT_ERR_INVALID, "L[a] must lie in [2^-200, 2^200]");
         d->n[a] = j->n[a];
         d->L[a] = j->L[a];
         d->h[a] = j->L[a] / (double)j->n[a];
@@ -756,8 +764,15 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
         if (!j->bc)
             return fail(VT_ERR_INVALID, "period vectors need periodic boundaries");
         for (int k = 0; k < nd * nd; ++k)
-            if (!std::isfinite(j->periods[k]))
-                return fail(VT_ERR_INVALID, "period vectors must be finite");
+            if (!(std::fabs(j->periods[k]) <= VT_SCALE_MAX))
+                return fail(VT_ERR_INVALID, "period vector entries must be finite, |entry| <= 2^200");
+        for (int i = 0; i < nd; ++i) {
+            double n2 = 0.0;
+            for (int a = 0; a < nd; ++a)
+                n2 += j->periods[i * nd + a] * j->periods[i * nd + a];
+            if (!in_scale(std::sqrt(n2)))
+                return fail(VT_ERR_INVALID, "period vector lengths must lie in [2^-200, 2^200]");
+        }
         double det = 0.0;
         if (!invert_periods(nd, j->periods, d->Pinv, &det))
             return fail(VT_ERR_INVALID, "period vectors are linearly dependent");
@@ -772,6 +787,8 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
                 r2 += d->Pinv[i][a] * d->Pinv[i][a];
             }
             d->rown[i] = std::sqrt(r2);
+            if (!std::isfinite(d->rown[i]))
+                return fail(VT_ERR_INVALID, "period vectors are too close to linearly dependent");
             d->cell_d += std::sqrt(n2);
             extent[i] = std::sqrt(n2);
             d->L[i] = 1.0;
@@ -786,7 +803,7 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
     // 1.2 measured fastest or level from 2 to 6 axes and in a triclinic cell
     // (4D 64^4: 2.04 -> 1.93 ms against one spacing; 5D 24^5, 8,000 sites:
     // 4.34 -> 3.28 ms).
-    const double bin_factor = ctx->force_bin > 0.0 ? ctx->force_bin : 1.2;
+    const double bin_factor = ctx && ctx->force_bin > 0.0 ? ctx->force_bin : 1.2;
     const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim) * bin_factor;
     int64_t nbins = 1;
     for (int a = 0; a < j->ndim; ++a) {
@@ -838,6 +855,21 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
 }
 
 }  // namespace
+
+vt_status vt_plan_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* bins_per_axis, int32_t* tile_voxels)
+{
+    vt::NdDev d;
+    vt_status st = plan_nd(ctx, job, &d);
+    if (st != VT_OK)
+        return st;
+    for (int a = 0; a < job->ndim; ++a) {
+        if (bins_per_axis)
+            bins_per_axis[a] = d.nb[a];
+        if (tile_voxels)
+            tile_voxels[a] = d.T[a];
+    }
+    return VT_OK;
+}
 
 vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_dev, void* stream)
 {

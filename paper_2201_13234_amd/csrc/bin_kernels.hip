@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDe
         double p = 0.0;
         if (weighted) {
             p = J.param[i];
-            if (!isfinite(p))
+            if (!(fabs(p) <= VT_SCALE_MAX))  // also false for NaN
                 ok = false;
         }
         if (!ok) {

@@ -1292,7 +1292,9 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     }
                 } else {
                     for (int k = 0, d = 0; k < cnt; ++k) {
-                        if (!((keep >> k) & 1ull))
+                        // bins of more than 64 sites load whole (keep has one
+                        // bit per site of the smaller bins only)
+                        if (k < 64 && !((keep >> k) & 1ull))
                             continue;
                         R.rs[nR + off + d] = J.sites[src + k];
                         R.ri[nR + off + d] = J.sidx[src + k];

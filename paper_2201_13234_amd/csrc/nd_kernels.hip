@@ -88,7 +88,9 @@ __global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
         double s[kMaxDim];
         for (int a = 0; a < nd; ++a) {
             s[a] = J.coords[i * nd + a];
-            ok = ok && isfinite(s[a]);
+            // sites taken as they are (period vectors): within the scale
+            // bound, so that the rounding margin stays finite
+            ok = ok && (J.lattice ? fabs(s[a]) <= VT_SCALE_MAX : isfinite(s[a]));
         }
         for (int a = 0; a < nd; ++a) {
             int b = 0;
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
         }
         if (J.kind != KIND_VORONOI) {
             const double p = J.param[i];
-            if (!isfinite(p)) {
+            if (!(fabs(p) <= VT_SCALE_MAX)) {  // also true for NaN
                 ok = false;
             } else {
                 hi = nd_ordered(p);

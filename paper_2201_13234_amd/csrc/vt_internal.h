@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vtess.h"
+
 namespace vt {
 
 enum { KIND_VORONOI = 0, KIND_LAGUERRE = 1, KIND_JM = 2 };
@@ -69,11 +71,16 @@ constexpr TileShape kShape2[kNumCfg] = {{8, 4, 16, 1, 2, 2, 2, 1}, {8, 4, 16, 1,
 
 inline TileShape shape_of(int ndim, int cfg) { return ndim == 3 ? kShape3[cfg] : kShape2[cfg]; }
 
-// Square root with IEEE rounding, for q >= 2^-500: the hardware reciprocal
-// square root refined by the same fused multiply-add steps as the compiler's
-// correctly rounded sqrt, without its rescaling of tiny inputs and its
-// fix-up for zero and infinity (neither is reachable above 2^-500), so the
-// result is the same bit for bit.
+// Square root with IEEE rounding, for q >= 2^-500 (finite): Goldschmidt's
+// iteration for sqrt and 1/(2 sqrt) from the hardware reciprocal square root
+// estimate (one coupled step on g ~ sqrt(q), h ~ 1/(2 sqrt(q))), then two
+// Markstein corrections g += (q - g*g) * h with the residual formed exactly
+// by a fused multiply-add (Markstein, IA-64 and Elementary Functions, 2000).
+// This is the method of the compiler's correctly rounded binary64 sqrt on
+// gfx950, without its rescaling of tiny inputs and its fix-up for zero and
+// infinity (neither is reachable for finite q above 2^-500); the tests
+// compare it bit for bit with host IEEE results on exact squares, their
+// neighbours, rounding midpoints and random bit patterns.
 __device__ inline double sqrt_refined(double q)
 {
     const double y = __builtin_amdgcn_rsq(q);

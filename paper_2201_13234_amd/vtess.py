@@ -15,12 +15,13 @@ LIB_PATH = os.path.join(HERE, "libvtess.so")
 VORONOI, LAGUERRE, JOHNSON_MEHL = 0, 1, 2
 NONPERIODIC, PERIODIC = 0, 1
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BUSY, ERR_INPUT = range(6)
+SCALE_MAX, SCALE_MIN = 2.0 ** 200, 2.0 ** -200  # VT_SCALE_MAX / VT_SCALE_MIN
 
 # Symbols declared in include/vtess.h.
 EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessellate_nd", "vt_tessellate_batch",
            "vt_bins_build",
            "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_load_tuning", "vt_set_params",
-           "vt_plan", "vt_numerics_probe", "vt_label_digest", "vt_profile_enable", "vt_profile_read",
+           "vt_plan", "vt_plan_nd", "vt_numerics_probe", "vt_label_digest", "vt_profile_enable", "vt_profile_read",
            "vt_status_string", "vt_last_error"]
 
 
@@ -80,6 +81,7 @@ def lib():
         L.vt_load_tuning.argtypes = [vp, ctypes.c_char_p]
         L.vt_set_params.argtypes = [vp, i32, dbl]
         L.vt_plan.argtypes = [vp, P(VtJob), P(i32), P(i32), P(dbl)]
+        L.vt_plan_nd.argtypes = [vp, P(VtJobNd), P(i32), P(i32)]
         L.vt_numerics_probe.argtypes = [vp, vp, vp, vp, vp, i64, vp]
         L.vt_label_digest.argtypes = [vp, vp, i64, vp, vp]
         L.vt_reserve.argtypes = [vp, ctypes.c_size_t]
@@ -217,6 +219,47 @@ class Job:
             self._periods_buf = (ctypes.c_double * (d * d))(*flat)   # alive while the job is
             j.periods = ctypes.cast(self._periods_buf, ctypes.c_void_p).value
         return j
+
+
+def plan_scalars(n, L, kind=0, periodic=True, nsites=1, growth=1.0, periods=None, nd=False):
+    """Default plan of a job from its scalars alone (vt_plan / vt_plan_nd with
+    no context): runs the library's scalar checks and bin planning on the
+    host, launches nothing and needs no GPU.  The site, parameter and label
+    pointers are placeholders that the planning never reads.  Raises VtError
+    (VT_ERR_INVALID) for scalars outside the supported range."""
+    d = len(n)
+    fake = 256  # never dereferenced
+    if not nd and periods is None and d in (2, 3):
+        j = VtJob()
+        j.ndim, j.kind, j.bc, j.reserved = d, int(kind), PERIODIC if periodic else NONPERIODIC, 0
+        for a in range(3):
+            j.n[a] = int(n[a]) if a < d else 1
+            j.L[a] = float(L[a]) if a < d else 1.0
+        j.growth, j.nsites = float(growth), int(nsites)
+        j.coords, j.labels = fake, fake
+        j.param = fake if kind != VORONOI else None
+        nb = (ctypes.c_int32 * 3)()
+        cfg = ctypes.c_int32()
+        bf = ctypes.c_double()
+        _check(lib().vt_plan(None, ctypes.byref(j), nb, ctypes.byref(cfg), ctypes.byref(bf)), "vt_plan")
+        return dict(bins=tuple(nb)[:d], tile_cfg=cfg.value, bin_factor=bf.value)
+    j = VtJobNd()
+    j.ndim, j.kind, j.bc, j.flags = d, int(kind), PERIODIC if periodic else NONPERIODIC, ND_GENERIC
+    for a in range(MAX_DIM):
+        j.n[a] = int(n[a]) if a < d else 1
+        j.L[a] = float(L[a]) if a < d else 1.0
+    j.growth, j.nsites = float(growth), int(nsites)
+    j.coords, j.labels = fake, fake
+    j.param = fake if kind != VORONOI else None
+    buf = None
+    if periods is not None:
+        flat = [float(v) for row in periods for v in row]
+        buf = (ctypes.c_double * len(flat))(*flat)
+        j.periods = ctypes.cast(buf, ctypes.c_void_p).value
+    nb = (ctypes.c_int32 * d)()
+    tv = (ctypes.c_int32 * d)()
+    _check(lib().vt_plan_nd(None, ctypes.byref(j), nb, tv), "vt_plan_nd")
+    return dict(bins=tuple(nb), tile=tuple(tv))
 
 
 def _prod(v):

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2201_13234_amd import inputs as I
-from gpu_util import describe_mismatch, run_device, to_dev, workload
+from gpu_util import describe_mismatch, run_device, run_oracle, to_dev, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -396,3 +396,40 @@ def test_lattice_errors(ctx):
     w.coords[5, 1] = np.nan
     lab, key, st = run_lattice(ctx, w, P)
     assert st == 5 and np.all(lab == -1) and np.all(np.isnan(key))
+
+
+def test_scale_bounds_on_the_device(ctx):
+    """Weights and times beyond 2^200, and site coordinates beyond it with
+    period vectors, are bad site data (status 5, labels -1); lengths or growth
+    rates outside [2^-200, 2^200] are refused before any launch."""
+    import torch
+    from paper_2201_13234_amd import vtess
+    big = vtess.SCALE_MAX
+    rng = np.random.default_rng(77)
+    n = (12, 10, 8)
+    pts = I.uniform_sites(rng, 20, [float(v) for v in n])
+    for kind, ok_val, bad_val in ((1, -big, 2 * big), (2, big, -2 * big)):
+        prm = np.zeros(20)
+        prm[4] = ok_val
+        lab, st = run_device(ctx, workload(n, kind, True, pts, prm), status=True)
+        assert st == 0
+        ref = run_oracle(workload(n, kind, True, pts, prm))
+        assert np.array_equal(lab, ref)
+        prm[4] = bad_val
+        lab, st = run_device(ctx, workload(n, kind, True, pts, prm), status=True)
+        assert st == 5 and np.all(lab == -1)
+        # the general path checks the same bound
+        lab, key, st = run_nd(ctx, workload(n + (1,), kind, True, np.c_[pts, np.full(20, 0.5)], prm,
+                                            name="scale_nd"))
+        assert st == 5 and np.all(lab == -1)
+    for bad in (dict(L=(2 * big, 10.0, 8.0)), dict(growth=2 * big)):
+        w = workload(n, 2, True, pts, np.zeros(20), growth=bad.get("growth", 1.0), L=bad.get("L"))
+        with pytest.raises(vtess.VtError) as e:
+            ctx.tessellate(to_dev(w))
+        assert e.value.code == vtess.ERR_INVALID
+    w, P = lattice_case("hex2", 0, 921)
+    w.coords = w.coords.copy()
+    w.coords[3, 0] = 2 * big
+    lab, key, st = run_lattice(ctx, w, P)
+    assert st == 5 and np.all(lab == -1)
+    torch.cuda.synchronize()

@@ -147,6 +147,24 @@ def test_single_site_and_clusters(ctx, kind, periodic):
     check(ctx, workload(n, kind, periodic, pts, param, 1.7))
 
 
+@pytest.mark.parametrize("cfg", [None, (1, 1.2), (2, 1.2)])
+def test_laguerre_filtered_gather_with_crowded_bins(ctx, cfg):
+    """One heavy weight gives every region a long reach, so later gather
+    rounds overflow the region list and take the filtered load; a tight
+    cluster puts more than 64 sites in single bins, which that load takes
+    whole."""
+    rng = np.random.default_rng(23)
+    n = (64, 64, 64)
+    base = I.uniform_sites(rng, 1000, [64.0] * 3)
+    cluster = np.clip(np.array([10.0, 12.0, 9.0]) + rng.normal(0.0, 0.6, (110, 3)), 0.0, 63.9)
+    cluster2 = np.clip(np.array([40.0, 30.0, 50.0]) + rng.normal(0.0, 0.9, (90, 3)), 0.0, 63.9)
+    pts = np.vstack([base, cluster, cluster2])
+    w = I.lognormal_weights(rng, len(pts), 3.2, 0.3)
+    w[0] = 400.0
+    w[1005] = 150.0
+    check(ctx, workload(n, 1, False, pts, w, name="lag_crowded"), cfgs=(cfg,))
+
+
 def test_more_sites_than_voxels(ctx):
     rng = np.random.default_rng(11)
     for d, n in ((3, (24, 24, 24)), (2, (90, 70))):
