@@ -142,6 +142,23 @@ vt_status vt_reserve(vt_ctx* ctx, size_t bytes);
  * context's scratch, which synchronises the device. */
 vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+ * path of vt_tessellate, same kernels and same results, run on a static
+ * scratch array of VT_NOALLOC_SCRATCH_BYTES per device instead of the
+ * context's arena.  It calls no hipMalloc, hipFree or other allocating
+ * routine.  The array is allocated when the library's code object is loaded
+ * on a device and held until the process ends; vt_create looks up its address
+ * on its device.  A job whose binning arrays need more (about 44 bytes per
+ * site plus 8 per bin and 16 per region of four tiles, e.g. some 1.2 million
+ * uniform sites) gets VT_ERR_BUSY before any launch.  Every call on one device
+ * shares that array, whatever its context: calls that overlap on one GPU
+ * (other streams, other threads) race and give wrong labels, so order them.
+ * The kernels clear what must start at zero.  Other arguments and errors as
+ * for vt_tessellate. */
+#define VT_NOALLOC_SCRATCH_BYTES (64u << 20)
+vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
+
 /* Any dimension from 1 to VT_MAX_DIM.  Jobs with 2 or 3 axes and no period
  * vectors go through vt_tessellate unless flags holds VT_ND_GENERIC; the
  * others (and those with the flag) run the general kernel: a counting sort of the sites into a

@@ -41,6 +41,19 @@ vt_status hip_fail(hipError_t e, const char* what)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Scratch of vt_tessellate_noalloc: a file-scope device array, one copy per
+// device, allocated by the runtime when this code object is loaded on that
+// device and held until the process ends.  Host code never uses the name
+// itself as an address (on the host it is only a stand-in): vt_create asks the
+// runtime for its address on the device once (hipGetSymbolAddress, with that
+// device current) and the entry point passes that address to the kernels.
+constexpr size_t kNoallocBytes = VT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices];  // device address of `scratch` per device (null until set up)
+
 // Carves sub-arrays out of one allocation.
 struct Carver {
     size_t off = 0;
@@ -72,8 +85,8 @@ int dens_class(int64_t nvox, int64_t ns)
 struct vt_ctx {
     int device = 0;
     // scratch of the plain path and of batch binning
-    void* scratch = nullptr;
-    size_t scratch_cap = 0;
+    void* arena = nullptr;
+    size_t arena_cap = 0;
     // pinned staging for job tables; the event marks the last copy out of it
     void* pinned = nullptr;
     size_t pinned_cap = 0;
@@ -83,6 +96,8 @@ struct vt_ctx {
     double force_bin = 0.0;
     std::vector<TuneEntry> tune;
     int batch_grid = 0;
+    // this device's copy of the static scratch (vt_tessellate_noalloc)
+    void* noalloc = nullptr;
     // phase timing: three events per recorded call
     bool profile = false;
     std::vector<hipEvent_t> prof_events;
@@ -296,20 +311,20 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
 
 vt_status ensure_scratch(vt_ctx* ctx, size_t bytes)
 {
-    if (bytes <= ctx->scratch_cap)
+    if (bytes <= ctx->arena_cap)
         return VT_OK;
     // Growing replaces memory that queued work may still use.
     VT_HIP(hipDeviceSynchronize());
-    if (ctx->scratch)
-        VT_HIP(hipFree(ctx->scratch));
-    ctx->scratch = nullptr;
-    ctx->scratch_cap = 0;
+    if (ctx->arena)
+        VT_HIP(hipFree(ctx->arena));
+    ctx->arena = nullptr;
+    ctx->arena_cap = 0;
     size_t cap = align_up(bytes + bytes / 4, 1 << 20);
-    if (hipMalloc(&ctx->scratch, cap) != hipSuccess) {
-        ctx->scratch = nullptr;
+    if (hipMalloc(&ctx->arena, cap) != hipSuccess) {
+        ctx->arena = nullptr;
         return fail(VT_ERR_NOMEM, "scratch allocation failed");
     }
-    ctx->scratch_cap = cap;
+    ctx->arena_cap = cap;
     return VT_OK;
 }
 
@@ -540,6 +555,23 @@ vt_status vt_create(int device, vt_ctx** out)
         return fail(VT_ERR_HIP, "event creation failed");
     }
     c->batch_grid = vt::label_batch_grid(device);
+    {
+        // Once per device, with that device current: the address of this
+        // device's copy of `scratch`.
+        std::lock_guard<std::mutex> lock(g_noalloc_mu);
+        if (device < kMaxDevices && !g_noalloc_ptr[device]) {
+            void* p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                (void)hipEventDestroy(c->staging_evt);
+                delete c;
+                return e != hipSuccess ? hip_fail(e, "hipGetSymbolAddress(scratch)")
+                                       : fail(VT_ERR_HIP, "hipGetSymbolAddress(scratch) gave a null address");
+            }
+            g_noalloc_ptr[device] = p;
+        }
+        c->noalloc = device < kMaxDevices ? g_noalloc_ptr[device] : nullptr;
+    }
     if (const char* path = std::getenv("VT_TUNE_CACHE"))
         vt_load_tuning(c, path);  // a missing cache is not an error
     *out = c;
@@ -552,8 +584,8 @@ void vt_destroy(vt_ctx* ctx)
         return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    if (ctx->scratch)
-        (void)hipFree(ctx->scratch);
+    if (ctx->arena)
+        (void)hipFree(ctx->arena);
     if (ctx->pinned)
         (void)hipHostFree(ctx->pinned);
     if (ctx->staging_evt)
@@ -607,7 +639,7 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     const SingleLayout L = single_layout(d);
     if ((st = ensure_scratch(ctx, L.total)) != VT_OK)
         return st;
-    char* base = (char*)ctx->scratch;
+    char* base = (char*)ctx->arena;
     bind_single(d, base, L, status_dev);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (ctx->profile) {
@@ -631,6 +663,34 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     VT_HIP(vt::launch_label_fallback(d, s));
     if (ev[3])
         VT_HIP(hipEventRecord(ev[3], s));
+    return VT_OK;
+}
+
+vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream)
+{
+    if (!ctx)
+        return fail(VT_ERR_INVALID, "ctx is NULL");
+    if (!ctx->noalloc)
+        return fail(VT_ERR_HIP, "the static scratch is not set up on this device");
+    hipStream_t s = (hipStream_t)stream;
+    JobDev d;
+    vt_status st = plan_job(ctx, job, &d);
+    if (st != VT_OK)
+        return st;
+    const SingleLayout L = single_layout(d);
+    if (L.total > kNoallocBytes)
+        return fail(VT_ERR_BUSY, "job needs " + std::to_string(L.total) +
+                                     " bytes of scratch; vt_tessellate_noalloc has " +
+                                     std::to_string(kNoallocBytes) + " (use vt_tessellate)");
+    VT_HIP(hipSetDevice(ctx->device));
+    // The same kernels as vt_tessellate on the device's static scratch; the
+    // first binning kernel clears the counters and bounds that start at zero.
+    char* base = (char*)ctx->noalloc;
+    bind_single(d, base, L, status_dev);
+    if ((st = bin_single(d, base, L, s)) != VT_OK)
+        return st;
+    VT_HIP(vt::launch_label_single(d, s));
+    VT_HIP(vt::launch_label_fallback(d, s));
     return VT_OK;
 }
 
@@ -916,7 +976,7 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     const size_t o_partial = c.take<int32_t>(partial_cap);
     if ((st = ensure_scratch(ctx, align_up(c.off, 256))) != VT_OK)
         return st;
-    char* base = (char*)ctx->scratch;
+    char* base = (char*)ctx->arena;
     d.pbound = (unsigned long long*)(base + o_pbound);
     d.status = status_dev ? status_dev : (int32_t*)(base + o_status);
     d.bin_count = (int32_t*)(base + o_count);
@@ -1032,7 +1092,7 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     vt_status st = ensure_scratch(ctx, align_up(c.off, 256));
     if (st != VT_OK)
         return st;
-    char* base = (char*)ctx->scratch;
+    char* base = (char*)ctx->arena;
     for (int k = 0; k < njobs; ++k) {
         JobDev& d = host[k];
         const Group& g = groups[group_of[k]];

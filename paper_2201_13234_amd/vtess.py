@@ -16,9 +16,11 @@ VORONOI, LAGUERRE, JOHNSON_MEHL = 0, 1, 2
 NONPERIODIC, PERIODIC = 0, 1
 OK, ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_BUSY, ERR_INPUT = range(6)
 SCALE_MAX, SCALE_MIN = 2.0 ** 200, 2.0 ** -200  # VT_SCALE_MAX / VT_SCALE_MIN
+NOALLOC_SCRATCH_BYTES = 64 << 20                # VT_NOALLOC_SCRATCH_BYTES
 
 # Symbols declared in include/vtess.h.
-EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessellate_nd", "vt_tessellate_batch",
+EXPORTS = ["vt_create", "vt_reserve", "vt_destroy", "vt_tessellate", "vt_tessellate_noalloc", "vt_tessellate_nd",
+           "vt_tessellate_batch",
            "vt_bins_build",
            "vt_label_batch", "vt_bins_free", "vt_autotune", "vt_load_tuning", "vt_set_params",
            "vt_plan", "vt_plan_nd", "vt_numerics_probe", "vt_label_digest", "vt_profile_enable", "vt_profile_read",
@@ -72,6 +74,7 @@ def lib():
         L.vt_destroy.argtypes = [vp]
         L.vt_destroy.restype = None
         L.vt_tessellate.argtypes = [vp, P(VtJob), vp, vp]
+        L.vt_tessellate_noalloc.argtypes = [vp, P(VtJob), vp, vp]
         L.vt_tessellate_nd.argtypes = [vp, P(VtJobNd), vp, vp]
         L.vt_tessellate_batch.argtypes = [vp, P(VtJob), i32, vp, vp]
         L.vt_bins_build.argtypes = [vp, P(VtJob), P(vp), vp, vp]
@@ -304,6 +307,17 @@ class Context:
         cj = job.to_c()
         _check(lib().vt_tessellate(self.handle, ctypes.byref(cj), _status_ptr(status, 1), _stream(stream)),
                "vt_tessellate")
+        return job.labels
+
+    def tessellate_noalloc(self, job, status=None, stream=None):
+        """vt_tessellate_noalloc: the plain path on the device's static
+        scratch (no device allocation; the labels and status tensors must
+        exist already).  Calls on one device must not overlap."""
+        if job.labels is None:
+            raise ValueError("tessellate_noalloc needs job.labels allocated by the caller")
+        cj = job.to_c()
+        _check(lib().vt_tessellate_noalloc(self.handle, ctypes.byref(cj), _status_ptr(status, 1),
+                                           _stream(stream)), "vt_tessellate_noalloc")
         return job.labels
 
     def tessellate_nd(self, job, status=None, stream=None, generic=False):

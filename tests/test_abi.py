@@ -63,6 +63,7 @@ int main(void) {
            offsetof(vt_job, growth));
     printf("%zu %zu %zu %zu %zu\\n", sizeof(vt_job_nd), offsetof(vt_job_nd, coords), offsetof(vt_job_nd, keys),
            offsetof(vt_job_nd, growth), offsetof(vt_job_nd, periods));
+    printf("%zu\\n", (size_t)VT_NOALLOC_SCRATCH_BYTES);
     return 0;
 }
 """)
@@ -77,6 +78,7 @@ int main(void) {
             want.append(S.periods.offset)
         assert got == want
     assert ctypes.sizeof(vtess.VtJobNd) == 16 + 48 + 48 + 8 + 8 + 40
+    assert int(rows[2]) == vtess.NOALLOC_SCRATCH_BYTES
 
 
 def test_product_code_never_imports_the_oracle():
