@@ -1284,10 +1284,14 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     overflow = true;
                     break;
                 }
+                // Each bin first writes the sorted position and wrap code of
+                // its sites into their list slots (LDS only); then one thread
+                // per slot loads its site, so that every global load of the
+                // round is in flight at once instead of one bin's sites
+                // following each other.
                 if (!filtered) {
                     for (int k = 0; k < cnt; ++k) {
-                        R.rs[nR + off + k] = J.sites[src + k];
-                        R.ri[nR + off + k] = J.sidx[src + k];
+                        R.ri[nR + off + k] = src + k;
                         R.rf[nR + off + k] = code;
                     }
                 } else {
@@ -1296,11 +1300,16 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                         // bit per site of the smaller bins only)
                         if (k < 64 && !((keep >> k) & 1ull))
                             continue;
-                        R.rs[nR + off + d] = J.sites[src + k];
-                        R.ri[nR + off + d] = J.sidx[src + k];
+                        R.ri[nR + off + d] = src + k;
                         R.rf[nR + off + d] = code;
                         ++d;
                     }
+                }
+                __syncthreads();
+                for (int p = tid; p < total; p += NT) {
+                    const int sp = R.ri[nR + p];
+                    R.rs[nR + p] = J.sites[sp];
+                    R.ri[nR + p] = J.sidx[sp];
                 }
                 nR += total;
             }
