@@ -404,6 +404,28 @@ __device__ inline double image_lower_d(const JobConst& C, const TileBox& B, cons
     return p + dmin * C.rv;
 }
 
+// Lower-bound test of a site over box B against the level thr (key <= thr is
+// possible), without square roots: Johnson-Mehl compares the squared minimum
+// distance with ((thr - t) v)^2, widened by a relative 2^-40 that covers the
+// rounding of both sides (the level already carries the margin M).  Voronoi
+// and Laguerre give exactly image_lower(...) <= thr.
+template <int KIND, int DIM>
+__device__ inline bool lower_passes(const JobConst& C, const TileBox& B, const double* sg, double p, double thr)
+{
+    double qmin = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double d = fmax(0.0, fmax(B.lo[a] - sg[a], sg[a] - B.hi[a]));
+        qmin += d * d;
+    }
+    if (KIND == KV)
+        return qmin <= thr;
+    if (KIND == KL)
+        return qmin - p <= thr;
+    const double r = (thr - p) * C.v;
+    return r >= 0.0 && qmin <= (r * r) * (1.0 + 0x1p-40);
+}
+
 // True if site c (minimum image sg, parameter p, minimum distance dminc to
 // the box) loses to the reference site b on the whole box by more than the
 // margin.  Voronoi / Laguerre: key_c - key_b = (e_c - e_b) + 2 x.(g_b - g_c)
@@ -563,14 +585,18 @@ __device__ inline bool dominated(const double4* base, const double4* cg, const i
         if (KIND == KV || KIND == KL) {
             dom = dom || (t != e && !cgen && !ogen && Dq > C.M);
         } else {
+            // (t_c - t_t) + lbd / v > M with lbd the larger of the two lower
+            // bounds of d_c - d_t; the quotient bound Dq / den is tested as
+            // Dq / v > (M - (t_c - t_t)) den (den > 0), without a division.
             const double2 oq = cq[t];
-            double lbd = mq.x - oq.y;
+            const double dt = tc - site_at<IND>(base, t, cm[t].y).w;
+            bool beat = dt + (mq.x - oq.y) * C.rv > C.M;
             if (!cgen && !ogen) {
                 const double den = Dq > 0.0 ? mq.y + oq.y : mq.x + oq.x;
                 if (den >= C.sqrtL2 * 0x1p-10)
-                    lbd = fmax(lbd, Dq / den);
+                    beat = beat || Dq * C.rv > (C.M - dt) * den;
             }
-            dom = dom || (t != e && ((tc - site_at<IND>(base, t, cm[t].y).w) + lbd * C.rv) > C.M);
+            dom = dom || (t != e && beat);
         }
     }
     return dom;
@@ -1461,41 +1487,82 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     if (KIND == KJM || KIND == KJD)
                         dbmax = sqrt(qb);
                 }
-                for (int ebase = 0; ebase < nR; ebase += WAVE) {
+                // Voronoi and Laguerre, pass 1: the lower-bound test alone over
+                // the region list, survivors staged in S.ci; pass 2: full
+                // bounds and the reference test of the staged sites, compacted.
+                // A tile with more than CAP_S survivors of pass 1, and every
+                // Johnson-Mehl tile (whose lower bound alone keeps many more
+                // sites), take both tests in one pass instead.
+                int nst = 0;
+                bool many = KIND == KJM || KIND == KJD;
+                for (int ebase = 0; ebase < (many ? 0 : nR); ebase += WAVE) {
                     const int e = ebase + lane;
                     bool keep = false;
                     if (e < nR) {
                         const double4 sv = R.rs[e];
                         double sg[3];
                         site_image<DIM>(J, sv, R.rf[e], wrapped, sg);
-                        double dminc;
-                        keep = image_lower_d<KIND, DIM>(C, BT, sg, sv.w, dminc) <= thr;
-                        if (keep && ubPos >= 0 && e != ubPos)
-                            keep = !beaten_by<KIND, DIM>(C, BT, sg, sv.w, dminc, gb, eb, tb, dbmax);
+                        keep = lower_passes<KIND, DIM>(C, BT, sg, sv.w, thr);
                     }
                     const unsigned long long km = __ballot(keep);
-                    if (nc + __popcll(km) > CAP_S) {
-                        tile_ovf = true;
+                    if (nst + __popcll(km) > CAP_S) {
+                        many = true;
                         break;
                     }
                     if (keep)
-                        S.ci[nc + __popcll(km & lanes_below(lane))] = e;
-                    nc += __popcll(km);
+                        S.ci[nst + __popcll(km & lanes_below(lane))] = e;
+                    nst += __popcll(km);
+                }
+                if (many) {
+                    nst = 0;
+                    for (int ebase = 0; ebase < nR; ebase += WAVE) {
+                        const int e = ebase + lane;
+                        bool keep = false;
+                        if (e < nR) {
+                            const double4 sv = R.rs[e];
+                            double sg[3];
+                            site_image<DIM>(J, sv, R.rf[e], wrapped, sg);
+                            double dminc;
+                            keep = image_lower_d<KIND, DIM>(C, BT, sg, sv.w, dminc) <= thr;
+                            if (keep && ubPos >= 0 && e != ubPos)
+                                keep = !beaten_by<KIND, DIM>(C, BT, sg, sv.w, dminc, gb, eb, tb, dbmax);
+                        }
+                        const unsigned long long km = __ballot(keep);
+                        if (nst + __popcll(km) > CAP_S) {
+                            tile_ovf = true;
+                            break;
+                        }
+                        if (keep)
+                            S.ci[nst + __popcll(km & lanes_below(lane))] = e;
+                        nst += __popcll(km);
+                    }
                 }
                 wave_sync();
-                if (!tile_ovf && lane < nc) {
-                    const int e = S.ci[lane];
+                bool keep = false;
+                int e = 0, code = 0;
+                double ub = 0.0, dmn = 0.0, dmx = 0.0;
+                double4 g = make_double4(0.0, 0.0, 0.0, 0.0);
+                if (!tile_ovf && lane < nst) {
+                    e = S.ci[lane];
                     const double4 sv = R.rs[e];
-                    const int code = R.rf[e];
-                    double sg[3], lb, ub, dmn, dmx;
-                    double4 g;
+                    code = R.rf[e];
+                    double sg[3], lb;
                     site_image<DIM>(J, sv, code, wrapped, sg);
                     image_bounds<KIND, DIM>(C, BT, sg, sv.w, lb, ub, dmn, dmx, g);
-                    S.cg[lane] = g;
-                    S.cq[lane] = make_double2(dmn, dmx);
-                    S.ck[lane] = ub_key(ub, lane);  // replaces this lane's ci entry, read above
-                    S.cm[lane] = make_int2(R.ri[e], code | (e << 8));
+                    keep = true;
+                    if (!many && ubPos >= 0 && e != ubPos)
+                        keep = !beaten_by<KIND, DIM>(C, BT, sg, sv.w, dmn, gb, eb, tb, dbmax);
                 }
+                const unsigned long long km = __ballot(keep);
+                wave_sync();  // every staged position is read before ck (over ci) is written
+                if (keep) {
+                    const int slot = __popcll(km & lanes_below(lane));
+                    S.cg[slot] = g;
+                    S.cq[slot] = make_double2(dmn, dmx);
+                    S.ck[slot] = ub_key(ub, slot);
+                    S.cm[slot] = make_int2(R.ri[e], code | (e << 8));
+                }
+                nc = tile_ovf ? 0 : __popcll(km);
             } else {
                 // Images per tile (box_bounds).  The reference test runs for
                 // sites whose wrap code is uniform over the tile, against the
