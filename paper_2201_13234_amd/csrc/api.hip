@@ -364,13 +364,14 @@ SingleLayout single_layout(const JobDev& d)
     L.status = c.take<int32_t>(1, 4);
     L.ovf_count = c.take<int32_t>(1, 4);
     L.bin_count = c.take<int32_t>(d.nbins, 4);
+    // the scan's flag words, cleared together with the counts
+    L.partial_cap = vt::scan_flags_needed((int64_t)d.nbins);
+    L.partial = c.take<unsigned long long>(L.partial_cap, 8);
     L.bin_start = c.take<int32_t>((int64_t)d.nbins + 1);
     L.site_bin = c.take<int32_t>(d.nsites);
     L.site_rank = c.take<int32_t>(d.nsites);
     L.sites = c.take<double4>(d.nsites);
     L.sidx = c.take<int32_t>(d.nsites);
-    L.partial_cap = vt::scan_partials_needed((int64_t)d.nbins);
-    L.partial = c.take<int32_t>(L.partial_cap);
     L.ovf_list = c.take<int32_t>(d.nregions * 4);
     L.total = align_up(c.off, 256);
     return L;
@@ -411,12 +412,14 @@ hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, h
 // Count, scan and scatter the sites of one job (its arrays already bound).
 vt_status bin_single(const JobDev& d, char* base, const SingleLayout& L, hipStream_t s)
 {
-    // pbound, internal status and bin counts are contiguous from L.pbound.
-    const int64_t words = (int64_t)((L.bin_count - L.pbound) / 4) + d.nbins;
+    // pbound, internal status, bin counts and scan flags are contiguous from
+    // L.pbound.
+    const int64_t words = (int64_t)((L.partial - L.pbound) / 4) + 2 * L.partial_cap;
     int32_t* extra = (d.status != (int32_t*)(base + L.status)) ? d.status : nullptr;
     VT_HIP(launch_prepare((int32_t*)(base + L.pbound), words, extra, s));
     VT_HIP(vt::launch_bin_count(d, nullptr, 1, nullptr, d.nsites, s));
-    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (int32_t*)(base + L.partial), L.partial_cap, s));
+    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(base + L.partial), L.partial_cap,
+                           s));
     VT_HIP(vt::launch_bin_scatter(d, nullptr, 1, nullptr, d.nsites, s));
     if (d.kind == vt::KIND_JM)
         VT_HIP(vt::launch_jm_prune(d, nullptr, 1, nullptr, d.nsites, d.nbins, s));
@@ -965,6 +968,8 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     const size_t o_pbound = c.take<unsigned long long>(3);
     const size_t o_status = c.take<int32_t>(1, 4);
     const size_t o_count = c.take<int32_t>(d.nbins, 4);
+    const int64_t partial_cap = vt::scan_flags_needed((int64_t)d.nbins);
+    const size_t o_partial = c.take<unsigned long long>(partial_cap, 8);  // scan flags, cleared with the counts
     const size_t o_start = c.take<int32_t>((int64_t)d.nbins + 1);
     const size_t o_bin = c.take<int32_t>(d.nsites);
     const size_t o_rank = c.take<int32_t>(d.nsites);
@@ -972,8 +977,6 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     const size_t o_sf = c.take<double>(d.lattice ? (int64_t)d.nsites * d.ndim : 0);
     const size_t o_sp = c.take<double>(d.nsites);
     const size_t o_sidx = c.take<int32_t>(d.nsites);
-    const int64_t partial_cap = vt::scan_partials_needed((int64_t)d.nbins);
-    const size_t o_partial = c.take<int32_t>(partial_cap);
     if ((st = ensure_scratch(ctx, align_up(c.off, 256))) != VT_OK)
         return st;
     char* base = (char*)ctx->arena;
@@ -987,12 +990,13 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     d.sf = d.lattice ? (double*)(base + o_sf) : nullptr;
     d.sp = (double*)(base + o_sp);
     d.sidx = (int32_t*)(base + o_sidx);
-    // pbound, internal status and bin counts are contiguous: zero them
-    // together (and the caller's status word)
-    const int64_t words = (int64_t)((o_count - o_pbound) / 4) + d.nbins;
+    // pbound, internal status, bin counts and scan flags are contiguous: zero
+    // them together (and the caller's status word)
+    const int64_t words = (int64_t)((o_partial - o_pbound) / 4) + 2 * partial_cap;
     VT_HIP(launch_prepare((int32_t*)(base + o_pbound), words, status_dev, s));
     VT_HIP(vt::launch_nd_bin_count(d, s));
-    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (int32_t*)(base + o_partial), partial_cap, s));
+    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(base + o_partial), partial_cap,
+                           s));
     VT_HIP(vt::launch_nd_bin_scatter(d, s));
     VT_HIP(vt::launch_nd_label(d, s));
     return VT_OK;
@@ -1078,14 +1082,14 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     const size_t o_cnt = c.take<int32_t>(total_bins, 4);
     const size_t o_ctr = c.take<int32_t>(8 * (int64_t)ng, 4);
     const size_t o_ovfc = c.take<int32_t>(ng, 4);
+    const int64_t pcap = vt::scan_flags_needed(total_bins);
+    const size_t o_part = c.take<unsigned long long>(pcap, 8);  // scan flags, cleared with the counts
     const size_t zero_end = c.off;
     const size_t o_start = c.take<int32_t>(total_bins + 1);
     const size_t o_sbin = c.take<int32_t>(total_sites);
     const size_t o_srank = c.take<int32_t>(total_sites);
     const size_t o_sites = c.take<double4>(total_sites);
     const size_t o_sidx = c.take<int32_t>(total_sites);
-    const int64_t pcap = vt::scan_partials_needed(total_bins);
-    const size_t o_part = c.take<int32_t>(pcap);
     const size_t o_ovf = c.take<int32_t>(total_tiles * 4);
     const size_t jb = align_up(host.size() * sizeof(JobDev), 256);
     const size_t o_tab = c.take<char>((int64_t)(jb + prefix.size() * sizeof(int64_t)), 256);
@@ -1124,7 +1128,7 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     std::memset(&dummy, 0, sizeof dummy);
     VT_HIP(vt::launch_bin_count(dummy, djobs, njobs, dprefix, total_sites, s));
     VT_HIP(vt::launch_scan((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins,
-                           (int32_t*)(base + o_part), pcap, s));
+                           (unsigned long long*)(base + o_part), pcap, s));
     VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
     VT_HIP(vt::launch_jm_prune(dummy, djobs, njobs, dprefix, total_sites, total_bins, s));
     return launch_groups(ctx, djobs, groups, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovfc),

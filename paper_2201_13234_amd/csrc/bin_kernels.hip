@@ -430,48 +430,61 @@ __device__ inline int block_exclusive_add(int v, int& total)
     return off + inc - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
-                                                              int32_t* __restrict__ partial)
-{
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n)
-            s += in[base + k];
-    int total;
-    block_exclusive_add(s, total);
-    if (threadIdx.x == 0)
-        partial[blockIdx.x] = total;
-}
+// One-pass exclusive scan of the bin counts (a chained scan with decoupled
+// look-back: Merrill and Garland, Single-pass Parallel Prefix Scan with
+// Decoupled Look-back, 2016).  Each workgroup scans one tile of kScanTile
+// counts and publishes, in its flag word, first the tile total and then its
+// inclusive prefix; it finds its own exclusive prefix by walking back over
+// the flags of the tiles before it, adding totals until it meets a published
+// prefix.  A flag word is 0 (nothing yet), kAggr | total or kIncl | prefix
+// (values below 2^31); the flags start at zero (the caller clears them).
+// Workgroups wait only on tiles of lower index, which were dispatched before
+// them.  One launch instead of reduce, scan-of-partials and final passes.
+constexpr unsigned long long kAggr = 1ull << 62, kIncl = 2ull << 62, kValMask = (1ull << 62) - 1;
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(int32_t* partial, int64_t nblk)
+__global__ __launch_bounds__(kScanThreads) void k_scan_onepass(const int32_t* __restrict__ in,
+                                                               int32_t* __restrict__ out, int64_t n,
+                                                               unsigned long long* __restrict__ flags)
 {
-    int carry = 0;
-    for (int64_t base = 0; base < nblk; base += kScanThreads) {
-        int64_t i = base + threadIdx.x;
-        int v = i < nblk ? partial[i] : 0;
-        int total;
-        int ex = block_exclusive_add(v, total);
-        if (i < nblk)
-            partial[i] = carry + ex;
-        carry += total;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_final(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                                                             int64_t n, const int32_t* __restrict__ partial)
-{
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    __shared__ int prefix_sh;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
-    int s = 0;
+    int sum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         v[k] = (base + k < n) ? in[base + k] : 0;
-        s += v[k];
+        sum += v[k];
     }
     int total;
-    int run = block_exclusive_add(s, total) + partial[blockIdx.x];
+    const int ex = block_exclusive_add(sum, total);
+    if (threadIdx.x == 0) {
+        int before = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&flags[0], kIncl | (unsigned long long)total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&flags[tile], kAggr | (unsigned long long)total, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int64_t k = tile - 1; k >= 0;) {
+                const unsigned long long f = __hip_atomic_load(&flags[k], __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                if (f == 0ull) {
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                before += (int)(f & kValMask);
+                if ((f & ~kValMask) == kIncl)
+                    break;
+                --k;
+            }
+            __hip_atomic_store(&flags[tile], kIncl | (unsigned long long)(before + total), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        prefix_sh = before;
+    }
+    __syncthreads();
+    int run = prefix_sh + ex;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n)
@@ -543,17 +556,15 @@ hipError_t launch_jm_prune(const JobDev& single, const JobDev* jobs_dev, int njo
     return hipGetLastError();
 }
 
-int64_t scan_partials_needed(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+int64_t scan_flags_needed(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* partial,
-                       int64_t partial_cap, hipStream_t s)
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, unsigned long long* flags,
+                       int64_t flags_cap, hipStream_t s)
 {
     int64_t nblk = (n + kScanTile - 1) / kScanTile;
-    if (n <= 0 || nblk > partial_cap || nblk > 0x7fffffff)
+    if (n <= 0 || nblk > flags_cap || nblk > 0x7fffffff)
         return hipErrorInvalidValue;
-    k_scan_reduce<<<(unsigned)nblk, kScanThreads, 0, s>>>(in, n, partial);
-    k_scan_partials<<<1, kScanThreads, 0, s>>>(partial, nblk);
-    k_scan_final<<<(unsigned)nblk, kScanThreads, 0, s>>>(in, out, n, partial);
+    k_scan_onepass<<<(unsigned)nblk, kScanThreads, 0, s>>>(in, out, n, flags);
     return hipGetLastError();
 }
 

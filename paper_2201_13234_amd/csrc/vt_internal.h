@@ -107,6 +107,8 @@ __device__ inline double key_sqrt(double q)
 // and a sum that rounds up to L is the origin of the next period.
 __device__ inline double cell_coord(double c, double L)
 {
+    if (c >= 0.0 && c < L)
+        return c + 0.0;  // fmod(c, L) == c: skip its loop (-0.0 -> +0.0 as below)
     double r = fmod(c, L);
     if (r < 0.0) {
         r = r + L;
@@ -123,9 +125,11 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_bin_count(const JobDev& single, const JobDev* jobs_dev, int njobs,
                             const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s);
-hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* partial,
-                       int64_t partial_cap, hipStream_t s);
-int64_t scan_partials_needed(int64_t n);
+// Exclusive scan out[0..n] of in[0..n) in one launch; flags: flags_cap zeroed
+// words (scan_flags_needed(n)), cleared by the caller before every scan.
+hipError_t launch_scan(const int32_t* in, int32_t* out, int64_t n, unsigned long long* flags,
+                       int64_t flags_cap, hipStream_t s);
+int64_t scan_flags_needed(int64_t n);
 hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int njobs,
                               const int64_t* site_prefix_dev, int64_t total_sites, hipStream_t s);
 // Johnson-Mehl jobs: drop from their bins the sites that provably never win
