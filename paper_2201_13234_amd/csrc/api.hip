@@ -95,7 +95,6 @@ struct vt_ctx {
     int force_cfg = -1;
     double force_bin = 0.0;
     std::vector<TuneEntry> tune;
-    int batch_grid = 0;
     // this device's copy of the static scratch (vt_tessellate_noalloc)
     void* noalloc = nullptr;
     // phase timing: three events per recorded call
@@ -350,8 +349,8 @@ vt_status ensure_pinned(vt_ctx* ctx, size_t bytes)
 
 // Binning arrays of one job carved from `base` (device memory).
 struct SingleLayout {
-    size_t pbound, status, ovf_count, bin_count, bin_start, site_bin, site_rank, sites, sidx, partial, ovf_list,
-        total;
+    size_t job, pbound, status, ovf_count, bin_count, bin_start, site_bin, site_rank, sites, sidx, partial,
+        ovf_list, total;
     int64_t partial_cap;
 };
 
@@ -359,6 +358,9 @@ SingleLayout single_layout(const JobDev& d)
 {
     SingleLayout L;
     Carver c;
+    // the job's record, written by the first binning kernel and read by the
+    // labelling kernels
+    L.job = c.take<JobDev>(1);
     // pbound, status, overflow count and bin counts are zeroed together
     L.pbound = c.take<unsigned long long>(2);
     L.status = c.take<int32_t>(1, 4);
@@ -391,7 +393,9 @@ void bind_single(JobDev& d, char* base, const SingleLayout& L, int32_t* status_d
     d.ovf_list = (int32_t*)(base + L.ovf_list);
 }
 
-__global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra)
+// Clears nwords words from zero_begin and the word *extra (if given), and
+// stores the job's record at job_dst (if given).
+__global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, JobDev job, JobDev* job_dst)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -399,13 +403,21 @@ __global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra)
         zero_begin[k] = 0;
     if (i == 0 && extra)
         *extra = 0;
+    if (i == 0 && job_dst)
+        *job_dst = job;
 }
 
-hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, hipStream_t s)
+hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, hipStream_t s,
+                          const JobDev* job = nullptr, JobDev* job_dst = nullptr)
 {
     int64_t g = (nwords + 255) / 256;
     g = std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
-    k_prepare<<<(unsigned)g, 256, 0, s>>>(zero_begin, nwords, extra);
+    JobDev j;
+    if (job)
+        j = *job;
+    else
+        std::memset(&j, 0, sizeof j);
+    k_prepare<<<(unsigned)g, 256, 0, s>>>(zero_begin, nwords, extra, j, job ? job_dst : nullptr);
     return hipGetLastError();
 }
 
@@ -416,7 +428,7 @@ vt_status bin_single(const JobDev& d, char* base, const SingleLayout& L, hipStre
     // L.pbound.
     const int64_t words = (int64_t)((L.partial - L.pbound) / 4) + 2 * L.partial_cap;
     int32_t* extra = (d.status != (int32_t*)(base + L.status)) ? d.status : nullptr;
-    VT_HIP(launch_prepare((int32_t*)(base + L.pbound), words, extra, s));
+    VT_HIP(launch_prepare((int32_t*)(base + L.pbound), words, extra, s, &d, (JobDev*)(base + L.job)));
     VT_HIP(vt::launch_bin_count(d, nullptr, 1, nullptr, d.nsites, s));
     VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(base + L.partial), L.partial_cap,
                            s));
@@ -510,14 +522,13 @@ void make_groups(std::vector<JobDev>& tab, std::vector<int>& order, std::vector<
     }
 }
 
-vt_status launch_groups(vt_ctx* ctx, const JobDev* djobs, const std::vector<Group>& groups, int32_t* counters,
-                        int32_t* ovf_counts, int32_t* ovf_list, hipStream_t s)
+vt_status launch_groups(const JobDev* djobs, const std::vector<Group>& groups, int32_t* ovf_counts,
+                        int32_t* ovf_list, hipStream_t s)
 {
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const Group& g = groups[gi];
         VT_HIP(vt::launch_label_group(djobs + g.first, g.count, g.variant, g.ndim, g.cfg, g.regions,
-                                      counters + 8 * gi, ovf_list + g.ovf_off, ovf_counts + gi, ctx->batch_grid,
-                                      s));
+                                      ovf_list + g.ovf_off, ovf_counts + gi, s));
     }
     return VT_OK;
 }
@@ -557,7 +568,6 @@ vt_status vt_create(int device, vt_ctx** out)
         delete c;
         return fail(VT_ERR_HIP, "event creation failed");
     }
-    c->batch_grid = vt::label_batch_grid(device);
     {
         // Once per device, with that device current: the address of this
         // device's copy of `scratch`.
@@ -660,10 +670,11 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
         return st;
     if (ev[1])
         VT_HIP(hipEventRecord(ev[1], s));
-    VT_HIP(vt::launch_label_single(d, s));
+    const JobDev* jd = (const JobDev*)(base + L.job);
+    VT_HIP(vt::launch_label_single(d, jd, s));
     if (ev[2])
         VT_HIP(hipEventRecord(ev[2], s));
-    VT_HIP(vt::launch_label_fallback(d, s));
+    VT_HIP(vt::launch_label_fallback(d, jd, s));
     if (ev[3])
         VT_HIP(hipEventRecord(ev[3], s));
     return VT_OK;
@@ -692,8 +703,8 @@ vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_
     bind_single(d, base, L, status_dev);
     if ((st = bin_single(d, base, L, s)) != VT_OK)
         return st;
-    VT_HIP(vt::launch_label_single(d, s));
-    VT_HIP(vt::launch_label_fallback(d, s));
+    VT_HIP(vt::launch_label_single(d, (const JobDev*)(base + L.job), s));
+    VT_HIP(vt::launch_label_fallback(d, (const JobDev*)(base + L.job), s));
     return VT_OK;
 }
 
@@ -1073,14 +1084,13 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     if (total_sites > 0x7fffffffLL || total_bins > 0x7ffffffeLL)
         return fail(VT_ERR_BUSY, "batch too large: more than 2^31 sites or bins");
     VT_HIP(hipSetDevice(ctx->device));
-    // Layout: [pbound 2/job][status 1/job][bin_count][counters 8/group][overflow
-    // count 1/group] zeroed together, then bin_start, site arrays, scan
-    // partials, overflow lists.
+    // Layout: [pbound 2/job][status 1/job][bin_count][overflow count 1/group]
+    // [scan flags] zeroed together, then bin_start, site arrays, overflow
+    // lists.
     Carver c;
     const size_t o_pb = c.take<unsigned long long>(2 * (int64_t)njobs);
     const size_t o_st = c.take<int32_t>(njobs, 8);
     const size_t o_cnt = c.take<int32_t>(total_bins, 4);
-    const size_t o_ctr = c.take<int32_t>(8 * (int64_t)ng, 4);
     const size_t o_ovfc = c.take<int32_t>(ng, 4);
     const int64_t pcap = vt::scan_flags_needed(total_bins);
     const size_t o_part = c.take<unsigned long long>(pcap, 8);  // scan flags, cleared with the counts
@@ -1131,7 +1141,7 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
                            (unsigned long long*)(base + o_part), pcap, s));
     VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
     VT_HIP(vt::launch_jm_prune(dummy, djobs, njobs, dprefix, total_sites, total_bins, s));
-    return launch_groups(ctx, djobs, groups, (int32_t*)(base + o_ctr), (int32_t*)(base + o_ovfc),
+    return launch_groups(djobs, groups, (int32_t*)(base + o_ovfc),
                          (int32_t*)(base + o_ovf), s);
 }
 
@@ -1184,20 +1194,18 @@ vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n, int32_t* 
     for (const JobDev& d : host)
         total_tiles += d.nregions;
     VT_HIP(hipSetDevice(ctx->device));
-    // One stream-ordered allocation: job table, the caller's order, then eight
-    // region counters per group and one overflow count per group (zeroed on the
-    // device), then the overflow lists.
+    // One stream-ordered allocation: job table, the caller's order, then one
+    // overflow count per group (zeroed on the device), then the overflow lists.
     const size_t jb = align_up((size_t)n * sizeof(JobDev), 256);
     const size_t ob = align_up((size_t)n * sizeof(int32_t), 256);
-    const size_t cb = align_up((size_t)ng * 9 * sizeof(int32_t), 256);
+    const size_t cb = align_up((size_t)ng * sizeof(int32_t), 256);
     const size_t bytes = jb + ob + cb + (size_t)total_tiles * 4 * sizeof(int32_t);
     void* table = nullptr;
     vt_status st = alloc_table(bytes, s, &table);
     if (st != VT_OK)
         return st;
     int32_t* dorder = (int32_t*)((char*)table + jb);
-    int32_t* counters = (int32_t*)((char*)table + jb + ob);
-    int32_t* ovf_counts = counters + 8 * ng;
+    int32_t* ovf_counts = (int32_t*)((char*)table + jb + ob);
     int32_t* ovf_list = (int32_t*)((char*)table + jb + ob + cb);
     for (int k = 0; k < n; ++k) {
         host[k].ovf_count = ovf_counts + group_of[k];
@@ -1208,9 +1216,9 @@ vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n, int32_t* 
     std::memcpy(blob.data() + jb, order.data(), (size_t)n * sizeof(int32_t));
     if ((st = stage_copy(ctx, table, blob.data(), blob.size(), s)) != VT_OK)
         return st;
-    VT_HIP(vt::launch_fill_i32(counters, 9 * (int64_t)ng, 0, s));
+    VT_HIP(vt::launch_fill_i32(ovf_counts, ng, 0, s));
     const JobDev* djobs = (const JobDev*)table;
-    if ((st = launch_groups(ctx, djobs, groups, counters, ovf_counts, ovf_list, s)) != VT_OK)
+    if ((st = launch_groups(djobs, groups, ovf_counts, ovf_list, s)) != VT_OK)
         return st;
     if (status_dev)
         k_copy_status<<<(n + 255) / 256, 256, 0, s>>>(djobs, n, dorder, status_dev);

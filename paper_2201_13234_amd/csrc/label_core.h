@@ -80,6 +80,19 @@ struct TileBox {
     double lo[3], hi[3];  // box of voxel centres
 };
 
+// A job's record in device memory that no kernel writes while labelling runs
+// (one record for the single-job kernels, the job table for batches), read
+// through the constant address space: the labelling code then loads each
+// field with scalar loads where it needs it, instead of holding a copy of the
+// whole record in registers.  (Measured faster than passing the record as a
+// kernel argument: M2 0.646 against 0.666 ms, M4 0.648 against 0.692 ms.)
+using ConstJob = const __attribute__((address_space(4))) JobDev;
+
+__device__ inline const JobDev& job_ref(const JobDev* jobs, int j)
+{
+    return *(const JobDev*)&((ConstJob*)jobs)[j];
+}
+
 struct JobConst {
     double M;        // pruning margin
     double pmax, pmin;

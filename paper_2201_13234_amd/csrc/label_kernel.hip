@@ -37,18 +37,20 @@ namespace vt {
 namespace {
 
 template <int KIND, int DIM, int CFG>
-__global__ __launch_bounds__(NT) void k_label_single(JobDev J)
+__global__ __launch_bounds__(NT) void k_label_single(const JobDev* __restrict__ jp)
 {
     __shared__ Smem sm;
+    const JobDev& J = job_ref(jp, 0);
     const int64_t r = xcd_unit(blockIdx.x, gridDim.x);
     region_cfg<KIND, DIM, CFG>(J, r, r, sm, threadIdx.x);
 }
 
 // Tiles the main kernel left over, one wavefront each.
 template <int KIND, int DIM, int CFG>
-__global__ __launch_bounds__(WAVE) void k_label_fallback(JobDev J)
+__global__ __launch_bounds__(WAVE) void k_label_fallback(const JobDev* __restrict__ jp)
 {
     __shared__ FallbackLds S;
+    const JobDev& J = job_ref(jp, 0);
     const int n = *(volatile int32_t*)J.ovf_count;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int id = J.ovf_list[i];
@@ -58,51 +60,54 @@ __global__ __launch_bounds__(WAVE) void k_label_fallback(JobDev J)
 }
 
 template <int KIND, int DIM>
-hipError_t launch_single_cfg(const JobDev& job, hipStream_t s, bool fallback)
+hipError_t launch_single_cfg(const JobDev& job, const JobDev* jd, hipStream_t s, bool fallback)
 {
     const unsigned grid = fallback ? kFallbackGrid : (unsigned)job.nregions;
     if (fallback) {
         switch (job.cfg) {
-        case 0: k_label_fallback<KIND, DIM, 0><<<grid, WAVE, 0, s>>>(job); break;
-        case 1: k_label_fallback<KIND, DIM, 1><<<grid, WAVE, 0, s>>>(job); break;
-        case 2: k_label_fallback<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(job); break;
-        default: k_label_fallback<KIND, DIM, 3><<<grid, WAVE, 0, s>>>(job); break;
+        case 0: k_label_fallback<KIND, DIM, 0><<<grid, WAVE, 0, s>>>(jd); break;
+        case 1: k_label_fallback<KIND, DIM, 1><<<grid, WAVE, 0, s>>>(jd); break;
+        case 2: k_label_fallback<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(jd); break;
+        default: k_label_fallback<KIND, DIM, 3><<<grid, WAVE, 0, s>>>(jd); break;
         }
     } else {
         switch (job.cfg) {
-        case 0: k_label_single<KIND, DIM, 0><<<grid, NT, 0, s>>>(job); break;
-        case 1: k_label_single<KIND, DIM, 1><<<grid, NT, 0, s>>>(job); break;
-        case 2: k_label_single<KIND, DIM, 2><<<grid, NT, 0, s>>>(job); break;
-        default: k_label_single<KIND, DIM, 3><<<grid, NT, 0, s>>>(job); break;
+        case 0: k_label_single<KIND, DIM, 0><<<grid, NT, 0, s>>>(jd); break;
+        case 1: k_label_single<KIND, DIM, 1><<<grid, NT, 0, s>>>(jd); break;
+        case 2: k_label_single<KIND, DIM, 2><<<grid, NT, 0, s>>>(jd); break;
+        default: k_label_single<KIND, DIM, 3><<<grid, NT, 0, s>>>(jd); break;
         }
     }
     return hipGetLastError();
 }
 
 template <int DIM>
-hipError_t launch_single_dim(const JobDev& job, hipStream_t s, bool fallback)
+hipError_t launch_single_dim(const JobDev& job, const JobDev* jd, hipStream_t s, bool fallback)
 {
     if (job.kind == KIND_VORONOI)
-        return launch_single_cfg<KV, DIM>(job, s, fallback);
+        return launch_single_cfg<KV, DIM>(job, jd, s, fallback);
     if (job.kind == KIND_LAGUERRE)
-        return launch_single_cfg<KL, DIM>(job, s, fallback);
+        return launch_single_cfg<KL, DIM>(job, jd, s, fallback);
     if (job.jm_div)
-        return launch_single_cfg<KJD, DIM>(job, s, fallback);
-    return launch_single_cfg<KJM, DIM>(job, s, fallback);
+        return launch_single_cfg<KJD, DIM>(job, jd, s, fallback);
+    return launch_single_cfg<KJM, DIM>(job, jd, s, fallback);
 }
 
 }  // namespace
 
-hipError_t launch_label_single(const JobDev& job, hipStream_t s)
+hipError_t launch_label_single(const JobDev& job, const JobDev* job_dev, hipStream_t s)
 {
-    if (job.nregions <= 0 || job.nregions > 0x7fffffffLL)
+    if (job.nregions <= 0 || job.nregions > 0x7fffffffLL || !job_dev)
         return hipErrorInvalidValue;
-    return job.ndim == 3 ? launch_single_dim<3>(job, s, false) : launch_single_dim<2>(job, s, false);
+    return job.ndim == 3 ? launch_single_dim<3>(job, job_dev, s, false)
+                         : launch_single_dim<2>(job, job_dev, s, false);
 }
 
-hipError_t launch_label_fallback(const JobDev& job, hipStream_t s)
+hipError_t launch_label_fallback(const JobDev& job, const JobDev* job_dev, hipStream_t s)
 {
-    return job.ndim == 3 ? launch_single_dim<3>(job, s, true) : launch_single_dim<2>(job, s, true);
+    if (!job_dev)
+        return hipErrorInvalidValue;
+    return job.ndim == 3 ? launch_single_dim<3>(job, job_dev, s, true) : launch_single_dim<2>(job, job_dev, s, true);
 }
 
 }  // namespace vt

@@ -137,17 +137,15 @@ hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int 
 hipError_t launch_jm_prune(const JobDev& single, const JobDev* jobs_dev, int njobs,
                            const int64_t* site_prefix_dev, int64_t total_sites, int64_t total_bins, hipStream_t s);
 
-// Labelling: single job (all its tiles) or a persistent batch launch.
-hipError_t launch_label_single(const JobDev& job, hipStream_t s);
-hipError_t launch_label_fallback(const JobDev& job, hipStream_t s);
-// Persistent launch over one group of a batch: jobs of one kernel variant
-// (label_variant), dimension and tile configuration, contiguous in the device
-// table with region_begin counted from 0 over the group.  counters: 8 zeroed
-// ints; ovf_list: 4 entries per region; ovf_count: one zeroed int.
+// Labelling: a single job (all its tiles; job_dev: the same record in device
+// memory, unchanged until the kernels have run) or one group of a batch: jobs
+// of one kernel variant (label_variant), dimension and tile configuration,
+// contiguous in the device table with region_begin counted from 0 over the
+// group.  ovf_list: 4 entries per region; ovf_count: one zeroed int.
+hipError_t launch_label_single(const JobDev& job, const JobDev* job_dev, hipStream_t s);
+hipError_t launch_label_fallback(const JobDev& job, const JobDev* job_dev, hipStream_t s);
 hipError_t launch_label_group(const JobDev* jobs_dev, int njobs, int variant, int ndim, int cfg,
-                              int64_t total_regions, int32_t* counters, int32_t* ovf_list, int32_t* ovf_count,
-                              int grid, hipStream_t s);
+                              int64_t total_regions, int32_t* ovf_list, int32_t* ovf_count, hipStream_t s);
 int label_variant(const JobDev& J);  // 0 Voronoi, 1 Laguerre, 2/3 Johnson-Mehl (multiply / divide by v)
-int label_batch_grid(int device);
 
 }  // namespace vt
