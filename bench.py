@@ -11,17 +11,22 @@ in HBM.  The line printed at the end also carries
     runs on), against the FP64 vector peak of 78.6 TFLOP/s; beside it the
     HBM write roofline (4 B per voxel against 8 TB/s), and the HBM traffic
     and FP64 / VALU issue rates measured by hardware counters (committed
-    counter summary, used only while it matches the kernel source);
+    counter summary, used only while it matches the kernel source and plan);
+  - configs: the same measurement on the other benchmark configurations
+    (M1 64^3 Voronoi, M3 512^3 Laguerre, M4 384^3 Johnson-Mehl);
+  - autotune: the autotuner on a non-uniform class (clustered sites),
+    built-in against tuned plan on a held-out job of the class;
   - cpu_baseline: the CPU oracle (paper's two-step ball algorithm) timed on
-    the host's cores on the same workload, the device labels of the timed
-    configuration checked against the oracle at sampled voxels, and every
-    125th served job's labels (checksums) against the oracle's; with
-    --oracle-survey also the oracle's times on M1-M4;
+    the host's cores on the same workload, its times on the other
+    configurations, the device labels of every timed configuration checked
+    against the oracle at sampled voxels, and every 125th served job's labels
+    (checksums) against the oracle's;
   - general_path (with --nd): the general-dimension kernel on a 4D Voronoi
     diagram, 64^4 voxels and 16,384 sites, and on a 3D Voronoi diagram of
     20,000 sites in a triclinic periodic cell (128^3 voxels);
-  - serving: a short request stream replayed through the continuous-batching
-    loop and one job at a time (p50/p99 latency), unless --no-serving.
+  - serving: the request stream replayed through the continuous-batching
+    loop and one job at a time (p50/p99 latency, throughput) at 0.8, 0.95 and
+    1.5 times the one-by-one service rate and as a burst, unless --no-serving.
 """
 import argparse
 import json
@@ -192,16 +197,18 @@ def serving_sampled_parity(keep, every=125):
     return {"jobs": checked, "voxels": vox, "mismatches": bad}
 
 
-def oracle_survey():
-    """Oracle wall times on the benchmark configurations: M1 (median of 3,
-    all cores and one thread, and by brute force) and M2-M4 (one run each,
-    all cores)."""
+def oracle_survey(skip=()):
+    """Oracle wall times on the benchmark configurations (all host cores):
+    M1 as the median of 3, with one thread and by brute force too; M2-M4 one
+    run each.  Names in `skip` are left out (already timed)."""
     import statistics
     import oracle
     from paper_2201_13234_amd import inputs
     out = {"cores": oracle.max_threads()}
     for name in ("M1", "M2", "M3", "M4"):
         w = inputs.CONFIGS[name]()
+        if w.name in skip:
+            continue
         p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
         reps = 3 if name == "M1" else 1
         ts = []
@@ -311,6 +318,126 @@ def general_path(ctx, steps, warmup):
     return out
 
 
+def time_config(ctx, w, steps, warmup, stream):
+    """Timed plain-path steps on workload w: wall time per step and the
+    library's event-timed phases (binning, labelling kernel, overflow)."""
+    import torch
+    from paper_2201_13234_amd import vtess
+    dev = torch.device("cuda:0")
+    job = vtess.Job(n=w.n, L=w.L, kind=w.kind, periodic=w.periodic, growth=w.growth,
+                    coords=torch.from_numpy(w.coords).to(dev),
+                    param=None if w.param is None else torch.from_numpy(w.param).to(dev))
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    for _ in range(warmup):
+        ctx.tessellate(job, status=status, stream=stream)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.tessellate(job, status=status, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile_enable(False)
+    bin_ms, label_ms, ovf_ms, calls = ctx.profile_read()
+    return {"job": job, "elapsed": elapsed, "ms_per_step": elapsed * 1e3 / steps,
+            "gvox": w.nvox * steps / elapsed / 1e9, "bin_ms": bin_ms / max(calls, 1),
+            "label_ms": label_ms / max(calls, 1), "ovf_ms": ovf_ms / max(calls, 1), "plan": ctx.plan(job)}
+
+
+def roofline_of(w, label_ms, cnt=None):
+    """Roofline of the labelling kernel on workload w (see the module doc)."""
+    write_bytes = 4.0 * w.nvox
+    hbm = write_bytes / (label_ms * 1e-3) / 1e9
+    # The kernel is bound by binary64 arithmetic.  Algorithmic work: the
+    # paper's key evaluations per voxel, ln N + 1 (eq. dl), times the
+    # operations of one key (3D: 3 subtractions, 3 multiplications, 2
+    # additions; Laguerre one subtraction more; Johnson-Mehl a square root
+    # and a multiplication more; 2D one subtraction, one multiplication and
+    # one addition fewer).
+    per_key = {0: 8, 1: 9, 2: 10}[w.kind] - (3 if w.ndim == 2 else 0)
+    evals = math.log(w.nsites) + 1.0
+    alg_flops = w.nvox * evals * per_key
+    tflops = alg_flops / (label_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+            "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
+            "kernel": "k_label_single (main labelling kernel)",
+            "kernel_avg_ms": round(label_ms, 4),
+            "algorithmic_flops": alg_flops,
+            "algorithmic_basis": f"{evals:.2f} key evaluations per voxel (ln N + 1) x {per_key} binary64 "
+                                 f"operations per key, {w.nvox} voxels",
+            "hbm_write": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(hbm / HBM_PEAK_GBS, 4), "algorithmic_bytes": write_bytes}}
+    if cnt and "sq_per_launch" in cnt:
+        sq = cnt["sq_per_launch"]
+        sec = label_ms * 1e-3
+        if "SQ_INSTS_VALU_FLOPS_FP64" in sq:
+            # the counter sums FP64 operations per wavefront instruction (FMA = 2);
+            # times 64 lanes (an upper bound: it assumes full execution masks)
+            f64 = sq["SQ_INSTS_VALU_FLOPS_FP64"] * 64 / sec / 1e12
+            roof["fp64_counted"] = {"achieved": round(f64, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                    "frac": round(f64 / FP64_PEAK_TFLOPS, 4)}
+        if "SQ_INSTS_VALU" in sq:
+            v = sq["SQ_INSTS_VALU"] * 64 / sec / 1e12
+            roof["valu_issue"] = {"achieved": round(v, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                                  "unit": "Tlane-op/s", "frac": round(v / VALU_PEAK_TOPS, 4)}
+            if "SQ_WAVES" in sq and sq["SQ_WAVES"]:
+                roof["valu_per_wave"] = round(sq["SQ_INSTS_VALU"] / sq["SQ_WAVES"], 1)
+    return roof
+
+
+def sampled_parity(w, labels, nvox=2000, seed=0):
+    """Device labels of workload w against the oracle at sampled voxels."""
+    import numpy as np
+    import oracle
+    p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+    rng = np.random.default_rng(seed)
+    vox = np.stack([rng.integers(0, n, nvox) for n in w.n], axis=1)
+    ref, _ = oracle.label_points(p, w.coords, w.param, vox)
+    got = labels[tuple(vox[:, a] for a in reversed(range(len(w.n))))]
+    return {"voxels": int(len(vox)), "mismatches": int((got != ref).sum())}
+
+
+def autotune_clustered(log):
+    """The autotuner on a non-uniform class (3D Voronoi 256^3, 40,000 sites in
+    200 Gaussian clusters of sigma 6 voxels, periodic): tuned on two samples
+    (seeds 41, 42), then the built-in and the tuned plan timed on a held-out
+    job of the class (seed 43), in contexts of their own."""
+    import json
+    import tempfile
+    import torch
+    from paper_2201_13234_amd import inputs, vtess
+    samples = [inputs.clustered(s) for s in (41, 42)]
+    held = inputs.clustered(43)
+    dev = torch.device("cuda:0")
+    to_job = lambda w: vtess.Job(n=w.n, L=w.L, kind=w.kind, periodic=w.periodic,
+                                 coords=torch.from_numpy(w.coords).to(dev))
+    tuned, plain = vtess.Context(0), vtess.Context(0)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        t0 = time.perf_counter()
+        tuned.autotune([to_job(w) for w in samples], cache_path=path)
+        tune_s = time.perf_counter() - t0
+        entry = json.load(open(path))[0]
+    log(f"autotune: {tune_s:.1f} s, entry {entry}")
+    stream = torch.cuda.current_stream()
+    rt = time_config(tuned, held, 20, 3, stream)
+    rd = time_config(plain, held, 20, 3, stream)
+    same = bool(torch.equal(rt["job"].labels, rd["job"].labels))
+    tuned.close()
+    plain.close()
+    return {"class": "3D Voronoi 256^3, 40,000 sites in 200 Gaussian clusters (sigma 6 voxels), periodic",
+            "samples": [w.name for w in samples], "held_out": held.name, "tuning_s": round(tune_s, 2),
+            "cache_entry": entry,
+            "default": {"plan": rd["plan"], "ms_per_step": round(rd["ms_per_step"], 4),
+                        "label_ms": round(rd["label_ms"], 4)},
+            "tuned": {"plan": rt["plan"], "ms_per_step": round(rt["ms_per_step"], 4),
+                      "label_ms": round(rt["label_ms"], 4)},
+            "labels_identical": same, "_held": held, "_labels": rt["job"].labels.cpu().numpy()}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,9 +446,9 @@ def main():
     ap.add_argument("--config", default="M2", help="M1..M4 (default M2, the headline workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream replay")
+    ap.add_argument("--no-others", action="store_true", help="time only --config (not M1-M4)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner run on the clustered class")
     ap.add_argument("--nd", action="store_true", help="also time the general-dimension kernel (4D)")
-    ap.add_argument("--oracle-survey", action="store_true",
-                    help="in the CPU leg, also time the oracle on M1-M4 (about a minute of CPU work)")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="request-stream length (the stream of 2,000 seeded jobs by default)")
     ap.add_argument("--serving-scale", type=float, default=1.0,
@@ -354,92 +481,34 @@ def main():
     import torch
     from paper_2201_13234_amd import inputs, vtess
 
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
     w = inputs.CONFIGS[args.config]()
-    dev = torch.device("cuda:0")
     ctx = vtess.Context(0)
-    job = vtess.Job(n=w.n, L=w.L, kind=w.kind, periodic=w.periodic, growth=w.growth,
-                    coords=torch.from_numpy(w.coords).to(dev),
-                    param=None if w.param is None else torch.from_numpy(w.param).to(dev))
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    print(f"[bench] {w.name}: warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ctx.tessellate(job, status=status, stream=stream)
-    torch.cuda.synchronize()
-    assert int(status.item()) == 0
-
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.tessellate(job, status=status, stream=stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.profile_enable(False)
-    bin_ms, label_ms, ovf_ms, calls = ctx.profile_read()
-    print(f"[bench] {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    log(f"{w.name}: warmup {args.warmup}, {args.steps} steps")
+    r = time_config(ctx, w, args.steps, args.warmup, stream)
+    log(f"{args.steps} steps in {r['elapsed']:.4f} s")
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib * 2 ** 20
         # int32 -> float32 conversion: one elementwise kernel per call that
         # reads and writes nb bytes (a same-type copy_ would go to the
         # runtime's blit kernels, mixed with other transfers).
-        src = torch.ones(nb // 4, dtype=torch.int32, device=dev)
-        dst = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda:0")
+        dst = torch.empty(nb // 4, dtype=torch.float32, device="cuda:0")
         torch.cuda.synchronize()
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    ms_per_step = elapsed * 1e3 / args.steps
-    gvox = w.nvox * args.steps / elapsed / 1e9
-    label_avg_ms = label_ms / max(calls, 1)
-    bin_avg_ms = bin_ms / max(calls, 1)
-    ovf_avg_ms = ovf_ms / max(calls, 1)
-    write_bytes = 4.0 * w.nvox
-    hbm = write_bytes / (label_avg_ms * 1e-3) / 1e9
-    # The kernel is bound by binary64 arithmetic.  Algorithmic work: the
-    # paper's key evaluations per voxel, ln N + 1 (eq. dl), times the
-    # operations of one key (3D: 3 subtractions, 3 multiplications, 2
-    # additions; Laguerre one subtraction more; Johnson-Mehl a square root
-    # and a multiplication more; 2D one subtraction, one multiplication and
-    # one addition fewer).
-    per_key = {0: 8, 1: 9, 2: 10}[w.kind] - (3 if w.ndim == 2 else 0)
-    evals = math.log(w.nsites) + 1.0
-    alg_flops = w.nvox * evals * per_key
-    tflops = alg_flops / (label_avg_ms * 1e-3) / 1e12
-    cnt = load_counters(w.name, ctx.plan(job))
-    roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
-                "traffic": cnt["hbm_bytes_per_launch"] if cnt else None,
-                "kernel": "k_label_single (main labelling kernel)",
-                "kernel_avg_ms": round(label_avg_ms, 4),
-                "algorithmic_flops": alg_flops,
-                "algorithmic_basis": f"{evals:.2f} key evaluations per voxel (ln N + 1) x {per_key} binary64 "
-                                     f"operations per key, {w.nvox} voxels",
-                "hbm_write": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(hbm / HBM_PEAK_GBS, 4), "algorithmic_bytes": write_bytes}}
-    if cnt and "sq_per_launch" in cnt:
-        sq = cnt["sq_per_launch"]
-        sec = label_avg_ms * 1e-3
-        if "SQ_INSTS_VALU_FLOPS_FP64" in sq:
-            # the counter sums FP64 operations per wavefront instruction (FMA = 2);
-            # times 64 lanes (an upper bound: it assumes full execution masks)
-            f64 = sq["SQ_INSTS_VALU_FLOPS_FP64"] * 64 / sec / 1e12
-            roofline["fp64_counted"] = {"achieved": round(f64, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                        "frac": round(f64 / FP64_PEAK_TFLOPS, 4)}
-        if "SQ_INSTS_VALU" in sq:
-            v = sq["SQ_INSTS_VALU"] * 64 / sec / 1e12
-            roofline["valu_issue"] = {"achieved": round(v, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                                      "unit": "Tlane-op/s", "frac": round(v / VALU_PEAK_TOPS, 4)}
+    cnt = load_counters(w.name, r["plan"])
     out = {
         "metric": "Gvoxels/s at 3D 512^3/100k sites; batched p50/p99 latency vs one-by-one",
-        "value": round(gvox, 3),
+        "value": round(r["gvox"], 3),
         "unit": "Gvoxels/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(r["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -447,15 +516,41 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.n), "sites": w.nsites,
                    "kind": inputs.KIND_NAMES[w.kind], "periodic": w.periodic,
-                   "seed": w.meta.get("seed"), "path": "plain (vt_tessellate)",
-                   "plan": ctx.plan(job)},
-        "phases_ms": {"binning": round(bin_avg_ms, 4), "labelling": round(label_avg_ms, 4),
-                      "overflow": round(ovf_avg_ms, 4)},
-        "roofline": roofline,
+                   "seed": w.meta.get("seed"), "path": "plain (vt_tessellate)", "plan": r["plan"]},
+        "phases_ms": {"binning": round(r["bin_ms"], 4), "labelling": round(r["label_ms"], 4),
+                      "overflow": round(r["ovf_ms"], 4)},
+        "roofline": roofline_of(w, r["label_ms"], cnt),
     }
-    lab = job.labels.cpu().numpy()
+    labels = {w.name: (w, r["job"].labels.cpu().numpy())}
+    del r
+    if not args.no_others:
+        # the other benchmark configurations, same measurement (not the value)
+        out["configs"] = {}
+        for name in ("M1", "M2", "M3", "M4"):
+            wc = inputs.CONFIGS[name]()
+            if wc.name == w.name:
+                rc = {"ms_per_step": out["ms_per_step"], "gvox": out["value"], "bin_ms": out["phases_ms"]["binning"],
+                      "label_ms": out["phases_ms"]["labelling"], "plan": out["config"]["plan"]}
+                roof = out["roofline"]
+            else:
+                log(f"{wc.name}: warmup {args.warmup}, {args.steps} steps")
+                rc = time_config(ctx, wc, args.steps, args.warmup, stream)
+                labels[wc.name] = (wc, rc["job"].labels.cpu().numpy())
+                roof = roofline_of(wc, rc["label_ms"], load_counters(wc.name, rc["plan"]))
+            out["configs"][name] = {
+                "workload": wc.name, "ms_per_step": round(rc["ms_per_step"], 4), "gvox_per_s": round(rc["gvox"], 3),
+                "binning_ms": round(rc["bin_ms"], 4), "labelling_ms": round(rc["label_ms"], 4), "plan": rc["plan"],
+                "alu_frac": roof["frac"], "alu_tflops": roof["achieved"],
+                "hbm_write_frac": roof["hbm_write"]["frac"], "hbm_write_gbs": roof["hbm_write"]["achieved"],
+                **({"valu_issue_frac": roof["valu_issue"]["frac"]} if "valu_issue" in roof else {}),
+                **({"traffic": roof["traffic"]} if roof.get("traffic") else {})}
+    tuned = None
+    if not args.no_tune:
+        log("autotuner on the clustered class")
+        tuned = autotune_clustered(log)
+        out["autotune"] = {k: v for k, v in tuned.items() if not k.startswith("_")}
     if args.nd:
-        print("[bench] general-dimension kernel (4D)", file=sys.stderr, flush=True)
+        log("general-dimension kernel (4D)")
         g = general_path(ctx, max(args.steps // 4, 2), 1)
         nd_labels = g.pop("labels")
         lat_labels = g.pop("lattice_labels")
@@ -463,19 +558,25 @@ def main():
     keep = {}
     if not args.no_serving:
         from paper_2201_13234_amd import serve
-        print(f"[bench] serving replay ({args.serving_jobs} jobs)", file=sys.stderr, flush=True)
+        log(f"serving replay ({args.serving_jobs} jobs)")
         out["serving"] = serve.benchmark(ctx, n_jobs=args.serving_jobs, side_scale=args.serving_scale,
-                                         log=lambda m: print(f"[bench] serving: {m}", file=sys.stderr,
-                                                             flush=True), keep=keep)
+                                         log=lambda m: log(f"serving: {m}"), keep=keep)
     if not args.no_cpu:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, lab)
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(w, labels[w.name][1])
+        log("oracle survey of the other configurations")
+        survey = oracle_survey(skip=(w.name,))
+        survey[w.name.split("_")[0]] = {"seconds": out["cpu_baseline"]["seconds"],
+                                        "gvox_per_s": out["cpu_baseline"]["value"]}
+        out["cpu_baseline"]["oracle_survey"] = survey
+        out["cpu_baseline"]["configs_sampled_parity"] = {name: sampled_parity(wc, lab)
+                                                         for name, (wc, lab) in labels.items()}
+        if tuned is not None:
+            out["cpu_baseline"]["autotune_sampled_parity"] = sampled_parity(tuned["_held"], tuned["_labels"],
+                                                                          nvox=20000)
         if keep:
-            print("[bench] CPU oracle on a sample of the served jobs", file=sys.stderr, flush=True)
+            log("CPU oracle on a sample of the served jobs")
             out["cpu_baseline"]["serving_sampled_parity"] = serving_sampled_parity(keep)
-        if args.oracle_survey:
-            print("[bench] oracle survey M1-M4", file=sys.stderr, flush=True)
-            out["cpu_baseline"]["oracle_survey"] = oracle_survey()
         if args.nd:
             out["cpu_baseline"]["general_path_sampled_parity"] = nd_sampled_parity(nd_labels, lat_labels)
     ctx.close()

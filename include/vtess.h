@@ -199,10 +199,17 @@ vt_status vt_label_batch(vt_ctx* ctx, vt_bins* const* bins, int32_t n,
 /* Releases a bin object after the work queued on `stream` that uses it. */
 vt_status vt_bins_free(vt_ctx* ctx, vt_bins* bins, void* stream);
 
-/* Times the candidate tile shapes and bin sizes on the sample jobs (their
- * label buffers are overwritten), keeps the fastest per job class in the
- * context and, if cache_path is not NULL, writes them there as JSON.
- * Synchronous. */
+/* Picks the launch plan per job class (dimension, kind, boundary, size class
+ * floor(log2(voxels) / 2), density class floor(log2(voxels / sites))) from the
+ * sample jobs.  For each class it times the built-in plan, then every tile
+ * configuration with bins of 1.0, 1.2, 1.4, 1.6 and 2.0 mean spacings (and,
+ * for Laguerre, a first gather box of one or two bins); a round runs each
+ * sample alone (vt_tessellate) and all of the class's samples in one
+ * vt_tessellate_batch call, best of three.  A candidate replaces the built-in
+ * plan only if its round is at least 3 % faster.  The chosen plans stay in the
+ * context (later calls of every path use them) and, if cache_path is not
+ * NULL, go to that file as JSON with both times ("ms", "default_ms").  The
+ * samples' label buffers are overwritten.  Synchronous. */
 vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char* cache_path);
 
 /* Loads a tuning cache written by vt_autotune. */

@@ -71,7 +71,9 @@ struct TuneEntry {
     int ndim, kind, bc, size_cls, dens_cls;
     int cfg;
     double bin_factor;
-    double ms;
+    int gather_margin;  // Laguerre first gather box margin in bins (0: the default rule)
+    double ms;          // tuned round time
+    double default_ms;  // the built-in plan's round time on the same samples
 };
 
 int size_class(int64_t nvox) { return (int)std::floor(std::log2((double)std::max<int64_t>(nvox, 1)) / 2.0); }
@@ -94,6 +96,8 @@ struct vt_ctx {
     bool staging_used = false;
     int force_cfg = -1;
     double force_bin = 0.0;
+    int force_margin = 0;      // Laguerre gather margin forced by the autotuner (0: none)
+    bool skip_tune = false;    // plan without the tuning table (the autotuner's default rounds)
     std::vector<TuneEntry> tune;
     // this device's copy of the static scratch (vt_tessellate_noalloc)
     void* noalloc = nullptr;
@@ -138,7 +142,8 @@ const TuneEntry* find_tune(const vt_ctx* ctx, const vt_job* j, int64_t nvox)
 // diagram, whose cells reach further, labels best with 8x8x8 tiles.
 // Batched launches group jobs by configuration, so the same choice holds
 // there.
-void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_out, double* bf_out)
+void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_out, double* bf_out,
+                   int* margin_out = nullptr)
 {
     const double vps = (double)nvox / (double)std::max<int64_t>(j->nsites, 1) /
                        (j->kind == VT_VORONOI ? 1.0 : 1.5);
@@ -180,20 +185,31 @@ void choose_params(const vt_ctx* ctx, const vt_job* j, int64_t nvox, int* cfg_ou
     }
     if (cfg >= 2)  // small regions: bins near one spacing keep the region list short
         bf = j->ndim == 3 ? 1.2 : 1.0;  // 3D measured 2-4 % faster at 1.2, 2D level
+    int margin = 0;
     if (ctx) {  // planning without a context takes the defaults
-        if (const TuneEntry* t = find_tune(ctx, j, nvox)) {
+        const TuneEntry* t = ctx->skip_tune ? nullptr : find_tune(ctx, j, nvox);
+        if (t) {
             cfg = t->cfg;
             bf = t->bin_factor;
+            margin = t->gather_margin;
         }
         if (ctx->force_cfg >= 0)
             cfg = ctx->force_cfg;
         if (ctx->force_bin > 0.0)
             bf = ctx->force_bin;
+        if (ctx->force_margin > 0)
+            margin = ctx->force_margin;
     }
     if (cfg < 0 || cfg >= vt::kNumCfg)
         cfg = 0;
+    // Laguerre's first gather box: two rings of bins near the mean spacing,
+    // one with larger bins (whose two rings would overflow the region list)
+    if (margin < 1 || margin > 2)
+        margin = bf <= 1.25 ? 2 : 1;
     *cfg_out = cfg;
     *bf_out = bf;
+    if (margin_out)
+        *margin_out = margin;
 }
 
 // A scalar inside the supported scale [VT_SCALE_MIN, VT_SCALE_MAX] (see the
@@ -257,15 +273,15 @@ vt_status plan_job(const vt_ctx* ctx, const vt_job* j, JobDev* d)
     d->rgrowth = 1.0 / d->growth;
     d->jm_div = (j->kind == VT_JOHNSON_MEHL && !is_pow2_scale(d->growth)) ? 1 : 0;
 
-    int cfg;
+    int cfg, margin;
     double bf;
-    choose_params(ctx, j, nvox, &cfg, &bf);
+    choose_params(ctx, j, nvox, &cfg, &bf, &margin);
     d->cfg = cfg;
     // Laguerre regions start their gather two bins out when the bins are near
     // the mean spacing (3-16 % faster on 384^3 grids from 167 to 1,067
     // voxels per site divided by 1.5), one bin out with larger bins, whose
-    // first box would overflow the region list
-    d->gather_margin = (j->kind == VT_LAGUERRE && bf <= 1.25) ? 2 : 1;
+    // first box would overflow the region list (or as tuned)
+    d->gather_margin = j->kind == VT_LAGUERRE ? margin : 1;
 
     // Bins: side ~ bf times the mean site spacing (V / N)^(1/d), at most
     // 2^20 per axis and about 4 N + 64 in total.
@@ -1320,8 +1336,11 @@ vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path)
         TuneEntry t;
         if (std::sscanf(line,
                         " {\"ndim\": %d, \"kind\": %d, \"bc\": %d, \"size_class\": %d, \"density_class\": %d, "
-                        "\"tile_cfg\": %d, \"bin_factor\": %lf, \"ms\": %lf",
-                        &t.ndim, &t.kind, &t.bc, &t.size_cls, &t.dens_cls, &t.cfg, &t.bin_factor, &t.ms) == 8)
+                        "\"tile_cfg\": %d, \"bin_factor\": %lf, \"gather_margin\": %d, \"ms\": %lf, "
+                        "\"default_ms\": %lf",
+                        &t.ndim, &t.kind, &t.bc, &t.size_cls, &t.dens_cls, &t.cfg, &t.bin_factor, &t.gather_margin,
+                        &t.ms, &t.default_ms) == 10 &&
+            t.cfg >= 0 && t.cfg < vt::kNumCfg && t.bin_factor >= 0.125 && t.bin_factor <= 16.0)
             got.push_back(t);
     }
     std::fclose(f);
@@ -1339,61 +1358,121 @@ vt_status vt_load_tuning(vt_ctx* ctx, const char* cache_path)
     return VT_OK;
 }
 
-vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char* cache_path)
+}  // extern "C"
+
+namespace {
+
+// One tuning round over the samples of a class: each sample alone
+// (vt_tessellate), then all of them in one vt_tessellate_batch call, so that
+// the plan is judged on the single-job and the batch kernels; the best of
+// three rounds after a warm-up.
+vt_status time_round(vt_ctx* ctx, const std::vector<vt_job>& js, hipEvent_t e0, hipEvent_t e1, double* ms)
 {
-    if (!ctx || !samples || n < 1)
-        return fail(VT_ERR_INVALID, "need a context and at least one sample job");
-    VT_HIP(hipSetDevice(ctx->device));
-    const int saved_cfg = ctx->force_cfg;
-    const double saved_bin = ctx->force_bin;
-    const double factors[] = {0.7, 1.0, 1.4, 2.0};
+    vt_status st;
+    for (const vt_job& j : js)
+        if ((st = vt_tessellate(ctx, &j, nullptr, nullptr)) != VT_OK)
+            return st;
+    if ((st = vt_tessellate_batch(ctx, js.data(), (int32_t)js.size(), nullptr, nullptr)) != VT_OK)
+        return st;
+    float best = 1e30f;
+    for (int r = 0; r < 3; ++r) {
+        VT_HIP(hipEventRecord(e0, nullptr));
+        for (const vt_job& j : js)
+            if ((st = vt_tessellate(ctx, &j, nullptr, nullptr)) != VT_OK)
+                return st;
+        if ((st = vt_tessellate_batch(ctx, js.data(), (int32_t)js.size(), nullptr, nullptr)) != VT_OK)
+            return st;
+        VT_HIP(hipEventRecord(e1, nullptr));
+        VT_HIP(hipEventSynchronize(e1));
+        float t = 0.0f;
+        VT_HIP(hipEventElapsedTime(&t, e0, e1));
+        best = std::min(best, t);
+    }
+    *ms = best;
+    return VT_OK;
+}
+
+vt_status tune_classes(vt_ctx* ctx, const vt_job* samples, int32_t n)
+{
+    // samples by class (dimension, kind, boundary, size class, density class)
+    std::vector<std::vector<vt_job>> cls;
+    std::vector<TuneEntry> keys;
+    for (int i = 0; i < n; ++i) {
+        JobDev d;
+        vt_status st = plan_job(ctx, &samples[i], &d);
+        if (st != VT_OK)
+            return st;
+        TuneEntry k{};
+        k.ndim = samples[i].ndim;
+        k.kind = samples[i].kind;
+        k.bc = samples[i].bc ? 1 : 0;
+        k.size_cls = size_class(d.nvox);
+        k.dens_cls = dens_class(d.nvox, samples[i].nsites);
+        size_t c = 0;
+        while (c < keys.size() && !(keys[c].ndim == k.ndim && keys[c].kind == k.kind && keys[c].bc == k.bc &&
+                                    keys[c].size_cls == k.size_cls && keys[c].dens_cls == k.dens_cls))
+            ++c;
+        if (c == keys.size()) {
+            keys.push_back(k);
+            cls.emplace_back();
+        }
+        cls[c].push_back(samples[i]);
+    }
     hipEvent_t e0, e1;
     VT_HIP(hipEventCreate(&e0));
-    VT_HIP(hipEventCreate(&e1));
-    vt_status result = VT_OK;
-    for (int i = 0; i < n && result == VT_OK; ++i) {
-        const vt_job* j = &samples[i];
-        JobDev d;
-        if ((result = plan_job(ctx, j, &d)) != VT_OK)
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(VT_ERR_HIP, "event creation failed");
+    }
+    // Tile configurations 0-3, bins of 1.0 to 2.0 mean spacings (every factor
+    // the built-in plans use), and for Laguerre the first gather margin.
+    const double factors[] = {1.0, 1.2, 1.4, 1.6, 2.0};
+    vt_status st = VT_OK;
+    for (size_t c = 0; c < cls.size() && st == VT_OK; ++c) {
+        TuneEntry best = keys[c];
+        // the built-in plan of this class, without the tuning table
+        ctx->skip_tune = true;
+        ctx->force_cfg = -1;
+        ctx->force_bin = 0.0;
+        ctx->force_margin = 0;
+        double t_def = 0.0;
+        if ((st = time_round(ctx, cls[c], e0, e1, &t_def)) != VT_OK)
             break;
-        TuneEntry best{};
-        best.ms = 1e300;
-        for (int cfg = 0; cfg < vt::kNumCfg && result == VT_OK; ++cfg) {
-            for (double bf : factors) {
-                ctx->force_cfg = cfg;
-                ctx->force_bin = bf;
-                // one warm-up, then the best of three
-                if ((result = vt_tessellate(ctx, j, nullptr, nullptr)) != VT_OK)
-                    break;
-                float tbest = 1e30f;
-                for (int r = 0; r < 3 && result == VT_OK; ++r) {
-                    float ms = 0;
-                    if (hipEventRecord(e0, nullptr) != hipSuccess ||
-                        (result = vt_tessellate(ctx, j, nullptr, nullptr)) != VT_OK ||
-                        hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        if (result == VT_OK)
-                            result = fail(VT_ERR_HIP, "autotune timing failed");
-                        break;
-                    }
-                    tbest = std::min(tbest, ms);
-                }
-                if (result != VT_OK)
-                    break;
-                if (tbest < best.ms) {
-                    best.ms = tbest;
-                    best.cfg = cfg;
-                    best.bin_factor = bf;
-                }
-            }
+        {
+            JobDev d;
+            if ((st = plan_job(ctx, &cls[c][0], &d)) != VT_OK)
+                break;
+            int cfg, margin;
+            double bf;
+            choose_params(ctx, &cls[c][0], d.nvox, &cfg, &bf, &margin);
+            best.cfg = cfg;
+            best.bin_factor = bf;
+            best.gather_margin = margin;
         }
-        if (result != VT_OK)
+        best.ms = t_def;
+        best.default_ms = t_def;
+        const int nmargin = keys[c].kind == VT_LAGUERRE ? 2 : 1;
+        for (int cfg = 0; cfg < vt::kNumCfg && st == VT_OK; ++cfg)
+            for (double bf : factors)
+                for (int m = 1; m <= nmargin && st == VT_OK; ++m) {
+                    ctx->force_cfg = cfg;
+                    ctx->force_bin = bf;
+                    ctx->force_margin = nmargin > 1 ? m : 0;
+                    double t = 0.0;
+                    if ((st = time_round(ctx, cls[c], e0, e1, &t)) != VT_OK)
+                        break;
+                    // a candidate replaces the current best only when clearly
+                    // faster, so that timing noise never trades a measured
+                    // default for an equal plan
+                    if (t < best.ms * 0.97) {
+                        best.ms = t;
+                        best.cfg = cfg;
+                        best.bin_factor = bf;
+                        best.gather_margin = nmargin > 1 ? m : 0;
+                    }
+                }
+        if (st != VT_OK)
             break;
-        best.ndim = j->ndim;
-        best.kind = j->kind;
-        best.bc = j->bc ? 1 : 0;
-        best.size_cls = size_class(d.nvox);
-        best.dens_cls = dens_class(d.nvox, j->nsites);
         bool replaced = false;
         for (TuneEntry& o : ctx->tune)
             if (o.ndim == best.ndim && o.kind == best.kind && o.bc == best.bc && o.size_cls == best.size_cls &&
@@ -1406,8 +1485,25 @@ vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char*
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char* cache_path)
+{
+    if (!ctx || !samples || n < 1)
+        return fail(VT_ERR_INVALID, "need a context and at least one sample job");
+    VT_HIP(hipSetDevice(ctx->device));
+    const int saved_cfg = ctx->force_cfg;
+    const double saved_bin = ctx->force_bin;
+    vt_status result = tune_classes(ctx, samples, n);
     ctx->force_cfg = saved_cfg;
     ctx->force_bin = saved_bin;
+    ctx->force_margin = 0;
+    ctx->skip_tune = false;
     if (result != VT_OK)
         return result;
     if (cache_path) {
@@ -1419,9 +1515,10 @@ vt_status vt_autotune(vt_ctx* ctx, const vt_job* samples, int32_t n, const char*
             const TuneEntry& t = ctx->tune[k];
             std::fprintf(f,
                          " {\"ndim\": %d, \"kind\": %d, \"bc\": %d, \"size_class\": %d, \"density_class\": %d, "
-                         "\"tile_cfg\": %d, \"bin_factor\": %.3f, \"ms\": %.6f}%s\n",
-                         t.ndim, t.kind, t.bc, t.size_cls, t.dens_cls, t.cfg, t.bin_factor, t.ms,
-                         k + 1 < ctx->tune.size() ? "," : "");
+                         "\"tile_cfg\": %d, \"bin_factor\": %.3f, \"gather_margin\": %d, \"ms\": %.6f, "
+                         "\"default_ms\": %.6f}%s\n",
+                         t.ndim, t.kind, t.bc, t.size_cls, t.dens_cls, t.cfg, t.bin_factor, t.gather_margin, t.ms,
+                         t.default_ms, k + 1 < ctx->tune.size() ? "," : "");
         }
         std::fprintf(f, "]\n");
         std::fclose(f);

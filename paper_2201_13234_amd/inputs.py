@@ -56,6 +56,22 @@ def uniform_sites(rng, nsites, L):
     return np.minimum(u, top)
 
 
+def clustered_sites(rng, nsites, L, nclusters, sigma, periodic=True):
+    """Sites in Gaussian clusters: centres uniform in the box, each site a
+    centre plus N(0, sigma^2) per axis, wrapped into [0, L) (periodic) or
+    redrawn uniformly when it falls outside (non-periodic)."""
+    L = np.asarray(L, dtype=np.float64)
+    centres = rng.random((int(nclusters), L.shape[0])) * L
+    pick = rng.integers(0, int(nclusters), int(nsites))
+    c = centres[pick] + sigma * rng.standard_normal((int(nsites), L.shape[0]))
+    if periodic:
+        c = np.mod(c, L)
+    else:
+        out = (c < 0.0) | (c >= L)
+        c = np.where(out, rng.random(c.shape) * L, c)
+    return np.minimum(c, np.nextafter(L, 0.0))
+
+
 def spacing(n_vox, nsites, ndim):
     """Mean site spacing (V / N_s)^(1/d) for unit voxels."""
     return (float(n_vox) / float(nsites)) ** (1.0 / ndim)
@@ -112,6 +128,18 @@ def m4():
 
 
 CONFIGS = {"M1": m1, "M2": m2, "M3": m3, "M4": m4}
+
+
+def clustered(seed, n=(256, 256, 256), nsites=40_000, nclusters=200, sigma=6.0):
+    """Non-uniform class for the autotuner: 3D Voronoi, periodic, sites in
+    Gaussian clusters (default 200 clusters of sigma 6 voxels on 256^3)."""
+    n = tuple(int(v) for v in n)
+    L = tuple(float(v) for v in n)
+    rng = np.random.default_rng(seed)
+    coords = clustered_sites(rng, nsites, L, nclusters, sigma, periodic=True)
+    return Workload(name=f"clustered_voronoi_{'x'.join(map(str, n))}_{nsites}_seed{seed}", n=n, L=L,
+                    kind=VORONOI, periodic=True, coords=coords, meta=dict(seed=seed, nclusters=nclusters,
+                                                                          sigma=sigma))
 
 
 def stream_job(j, side_scale=1.0):

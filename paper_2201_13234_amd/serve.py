@@ -452,14 +452,17 @@ def make_stream(n_jobs, rate, side_scale=0.25, first_job=0):
 
 
 def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, lanes=2, calib_jobs=0,
-              max_batch=64, extra_loads=(0.95,), log=None, keep=None):
+              max_batch=64, extra_loads=(0.95, 1.5), burst=True, log=None, keep=None):
     """Replays a request stream twice on the GPU -- continuous batching and one
     by one -- with the same arrival times.  The arrival rate is `load` times
     the one-by-one service rate, measured on all jobs (or the first
     `calib_jobs`) run back to back.  Returns p50/p99 latency and throughput of both modes, and
     whether every job's labels (device checksums) are the same in both.  Each
     of `extra_loads` repeats the comparison at that load (reported under
-    "other_loads").  keep (a dict, optional) receives the jobs and the
+    "other_loads"); a load above 1 saturates the one-by-one server.  burst
+    adds a replay with every job arriving at once (reported under "burst"):
+    the throughput of each mode when the queue never empties.  keep (a dict,
+    optional) receives the jobs and the
     batched replay's per-job label checksums at `load`, so that a caller
     can check a sample of them against another implementation."""
     say = log or (lambda msg: None)
@@ -480,20 +483,25 @@ def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, l
     last_digests = {}
 
     def replay(ld):
-        rate = ld / service
-        t = inputs.arrivals(n_jobs, rate)
-        stream = [Request(r.rid, r.workload, float(t[k])) for k, r in enumerate(jobs)]
-        say(f"load {ld}: batched replay at {rate:.1f} jobs/s")
+        if ld is None:  # burst: every job arrives at once
+            rate = math.inf
+            stream = [Request(r.rid, r.workload, 0.0) for r in jobs]
+        else:
+            rate = ld / service
+            t = inputs.arrivals(n_jobs, rate)
+            stream = [Request(r.rid, r.workload, float(t[k])) for k, r in enumerate(jobs)]
+        say(f"load {ld if ld is not None else 'burst'}: batched replay at {rate:.1f} jobs/s")
         srv = Server(ex, mem_budget=mem_budget, max_batch=max_batch)
         batched = srv.run(copy(stream))
         db = ex.collect_digests()
         last_digests.clear()
         last_digests.update(db)
-        say(f"load {ld}: one-by-one replay")
+        say(f"load {ld if ld is not None else 'burst'}: one-by-one replay")
         alone = Server(ex, mem_budget=mem_budget).run_one_by_one(copy(stream))
         da = ex.collect_digests()
         same = all(a.status == b.status and db.get(a.rid) == da.get(b.rid) for a, b in zip(batched, alone))
-        return {"load": ld, "rate_per_s": round(rate, 2), "batched": summarize(batched),
+        return {"load": ld if ld is not None else "burst",
+                "rate_per_s": round(rate, 2) if math.isfinite(rate) else None, "batched": summarize(batched),
                 "one_by_one": summarize(alone),
                 "mean_batch": round(float(np.mean(srv.batches)), 2) if srv.batches else 0,
                 "peak_mem_gb": round(srv.peak_mem / 2 ** 30, 2),
@@ -508,4 +516,6 @@ def benchmark(ctx, n_jobs=2000, side_scale=1.0, load=0.8, mem_budget=64 << 30, l
                 "lanes": lanes, "max_batch": max_batch, "voxels_total": int(sum(nvox)),
                 "voxels_p50": int(np.percentile(nvox, 50))})
     out["other_loads"] = [replay(ld) for ld in extra_loads]
+    if burst:
+        out["burst"] = replay(None)
     return out

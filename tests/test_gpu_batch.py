@@ -140,7 +140,7 @@ def test_autotune_roundtrip(ctx, tmp_path):
     path = str(tmp_path / "tune.json")
     ctx.autotune([to_dev(w)], cache_path=path)
     text = open(path).read()
-    assert '"tile_cfg"' in text and '"bin_factor"' in text
+    assert '"tile_cfg"' in text and '"bin_factor"' in text and '"default_ms"' in text
     c2 = vtess.Context(0)
     c2.load_tuning(path)
     plan = c2.plan(to_dev(w))
@@ -150,3 +150,57 @@ def test_autotune_roundtrip(ctx, tmp_path):
     torch.cuda.synchronize()
     assert np.array_equal(job.labels.cpu().numpy(), run_oracle(w))
     c2.close()
+
+
+def _median_ms(c, job, reps=7):
+    import torch
+    times = []
+    for _ in range(reps + 2):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c.tessellate(job)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times[2:]))
+
+
+def test_autotune_clustered_class_not_slower_than_default(tmp_path):
+    """The tuner keeps the built-in plan unless a candidate is faster on its
+    samples; on a held-out job of the same non-uniform class the tuned plan
+    is not slower than the built-in one (timing allowance 10 %), and its labels
+    equal the oracle."""
+    import json
+    from paper_2201_13234_amd import vtess
+    small = dict(n=(128, 128, 128), nsites=8000, nclusters=60, sigma=4.0)
+    samples = [I.clustered(s, **small) for s in (31, 32)]
+    held = I.clustered(33, **small)
+    tuned = vtess.Context(0)
+    plain = vtess.Context(0)
+    try:
+        path = str(tmp_path / "tune.json")
+        tuned.autotune([to_dev(w) for w in samples], cache_path=path)
+        entries = json.load(open(path))
+        assert len(entries) == 1
+        e = entries[0]
+        assert e["ms"] <= e["default_ms"]
+        job = to_dev(held)
+        t_tuned = _median_ms(tuned, job)
+        job_d = to_dev(held)
+        t_def = _median_ms(plain, job_d)
+        print(f"clustered class: plan {tuned.plan(job)} tuned {t_tuned:.4f} ms, default plan "
+              f"{plain.plan(job_d)} {t_def:.4f} ms; tuning rounds {e['ms']:.4f} vs {e['default_ms']:.4f} ms")
+        assert t_tuned <= 1.10 * t_def
+        got = job.labels.cpu().numpy()
+        # the whole image equals the built-in plan's, and the oracle at
+        # sampled voxels (its two-step algorithm is slow on clustered sites:
+        # the voids between clusters fall to brute force)
+        assert np.array_equal(got, job_d.labels.cpu().numpy())
+        rng = np.random.default_rng(5)
+        vox = np.stack([rng.integers(0, v, 20000) for v in held.n], axis=1)
+        p = oracle.problem(held.n, held.L, held.kind, held.periodic, held.growth)
+        ref, _ = oracle.label_points(p, held.coords, held.param, vox)
+        assert np.array_equal(got[tuple(vox[:, a] for a in reversed(range(3)))], ref)
+    finally:
+        tuned.close()
+        plain.close()
