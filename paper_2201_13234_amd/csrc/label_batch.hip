@@ -38,20 +38,36 @@ __global__ __launch_bounds__(NT) void k_label_batch(const JobDev* __restrict__ j
     region_cfg<KIND, DIM, CFG>(J, g - J.region_begin, g, sm, threadIdx.x);
 }
 
-// Fallback over a group's overflow list (entries are group-wide region * 4 + tile).
+// The overflow list of a group, as k_label_fallback: regions queued whole
+// (-(g + 1), group-wide region g) first, one workgroup each, then tiles
+// (g * 4 + tile), one wavefront each.
 template <int KIND, int DIM, int CFG>
-__global__ __launch_bounds__(WAVE) void k_label_batch_fallback(const JobDev* __restrict__ jobs, int njobs,
-                                                               const int32_t* list, const int32_t* count)
+__global__ __launch_bounds__(NT) void k_label_batch_fallback(const JobDev* __restrict__ jobs, int njobs,
+                                                             const int32_t* list, const int32_t* count)
 {
-    __shared__ FallbackLds S;
+    __shared__ Smem sm;
+    __shared__ FallbackLds fb[NW];
     const int n = *(volatile const int32_t*)count;
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int id = list[i];
-        const int64_t g = id / NW;
-        const int j = job_of_region(jobs, njobs, g);
-        const JobDev& J = job_ref(jobs, j);
-        alone_cfg<KIND, DIM, CFG>(J, g - J.region_begin, id % NW, S, threadIdx.x);
-        __syncthreads();
+        if (id < 0) {
+            const int64_t g = -(int64_t)id - 1;
+            const int j = job_of_region(jobs, njobs, g);
+            const JobDev& J = job_ref(jobs, j);
+            if (region_dense_cfg<KIND, DIM, CFG>(J, g - J.region_begin, sm, threadIdx.x))
+                alone_cfg<KIND, DIM, CFG>(J, g - J.region_begin, w, fb[w], lane);
+            __syncthreads();
+        }
+    }
+    for (int i = blockIdx.x * NW + w; i < n; i += gridDim.x * NW) {
+        const int id = list[i];
+        if (id >= 0) {
+            const int64_t g = id / NW;
+            const int j = job_of_region(jobs, njobs, g);
+            const JobDev& J = job_ref(jobs, j);
+            alone_cfg<KIND, DIM, CFG>(J, g - J.region_begin, id % NW, fb[w], lane);
+        }
     }
 }
 
@@ -60,7 +76,7 @@ hipError_t launch_group_cfg(const JobDev* jobs, int njobs, int64_t total, int32_
                             hipStream_t s)
 {
     k_label_batch<KIND, DIM, CFG><<<(unsigned)total, NT, 0, s>>>(jobs, njobs);
-    k_label_batch_fallback<KIND, DIM, CFG><<<kFallbackGrid, WAVE, 0, s>>>(jobs, njobs, ovf_list, ovf_count);
+    k_label_batch_fallback<KIND, DIM, CFG><<<kFallbackGrid, NT, 0, s>>>(jobs, njobs, ovf_list, ovf_count);
     return hipGetLastError();
 }
 

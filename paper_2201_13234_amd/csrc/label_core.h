@@ -520,6 +520,22 @@ __device__ inline double outside_lower_bound(const JobConst& C, double G)
     return C.pmin + G * C.rv;
 }
 
+// Whether a site whose squared gap to the region's box of voxel centres is g2
+// (parameter p) can still have a key <= cut somewhere in the region: Voronoi
+// g2 <= cut, Laguerre g2 - w <= cut, Johnson-Mehl t + sqrt(g2) / v <= cut,
+// tested on squares with a relative 2^-40 widening (the cut carries the
+// margin M).
+template <int KIND>
+__device__ inline bool may_win_region(const JobConst& C, double g2, double p, double cut)
+{
+    if (KIND == KV)
+        return g2 <= cut;
+    if (KIND == KL)
+        return g2 - p <= cut;
+    const double r = (cut - p) * C.v;
+    return r >= 0.0 && g2 <= (r * r) * (1.0 + 0x1p-40);
+}
+
 template <typename T>
 __device__ inline T sel3(int a, T v0, T v1, T v2)
 {
@@ -1174,8 +1190,16 @@ __device__ inline LaneGeo lane_geometry(const JobDev& J, int64_t r, int w, int l
 // Region `r` of job J: NW tiles of shape T (tile w of the region is processed
 // by wavefront w), RX x RY x RZ tiles.  `unit` numbers the region in the
 // launch (job-local, or batch-wide) for the overflow list.
-template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int ROWS, int RX, int RY, int RZ>
-__device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm, const int tid)
+//
+// DENSE false (main kernels): a region whose gather overflows the region list
+// is queued whole on the overflow list (as -(unit + 1)), a tile whose
+// candidate list overflows as unit * NW + w.  DENSE true (overflow kernels):
+// a first box too dense for the list starts over from the region's own bins
+// and the later rounds load only sites that can still win (every kind); the
+// return value tells the wavefront whose tile still overflows (its labels are
+// not stored) to label it with the per-tile walk.
+template <int KIND, int DIM, int RUN, int LX, int LY, int LZ, int ROWS, int RX, int RY, int RZ, bool DENSE>
+__device__ bool label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm, const int tid)
 {
     constexpr int TX = RUN * LX, TY = LY * ROWS, TZ = (DIM == 3) ? LZ : 1;
     static_assert(LX * LY * LZ == WAVE, "64 lanes per tile");
@@ -1201,19 +1225,22 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
         lab[q] = -1;
 
     const bool bad = *(volatile int32_t*)J.status != 0;
-    bool tile_ovf = false;
+    bool tile_ovf = false, region_ovf = false;
     if (!bad) {
         const JobConst C = job_const<KIND>(J, DIM);
         RegionLds& R = sm.r.reg;
 
         // ======== 1. region gather (whole workgroup)
-        int blo[3], bhi[3], olo[3], ohi[3];
+        int blo[3], bhi[3], olo[3], ohi[3], own_lo[3], own_hi[3];
         for (int a = 0; a < 3; ++a) {
+            own_lo[a] = own_hi[a] = 0;
             if (a < DIM) {
                 const int nb = J.nb[a];
                 int l = (int)(BR.lo[a] * J.inv_bs[a]), h = (int)(BR.hi[a] * J.inv_bs[a]);
                 l = max(0, min(l, nb - 1));
                 h = max(l, min(h, nb - 1));
+                own_lo[a] = l;
+                own_hi[a] = h;
                 // first box: the region's bins and GM more on each side.
                 // Johnson-Mehl reaches farther: its gather would almost
                 // always need a second round from one.  Laguerre takes the
@@ -1239,8 +1266,8 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             ohi[a] = 0;
         }
         int nR = 0, nDone = 0;
-        bool overflow = false;
-        double skip_cut = __builtin_inf();  // UB + M of the previous round (Laguerre load test)
+        bool overflow = false, dense = false, restart = false;
+        double skip_cut = __builtin_inf();  // UB + M of the previous round (load test)
         double ubT = __builtin_inf();  // this tile's upper bound (wave-uniform)
         int ubPos = -1;                // region-list position of a site attaining it
         for (int round = 0;; ++round) {
@@ -1281,17 +1308,19 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                 }
                 int total;
                 int off = block_excl_scan(cnt, total, R.wsum, tid);
-                // Laguerre, from the second round on, when the round's bins
-                // would overflow the list: a site whose own lower bound over
-                // the region (gap to its nearest periodic image, squared,
-                // minus its weight) exceeds UB + M loses at every voxel, so
-                // it is not loaded.  The reach follows the largest weight of
-                // all sites, and this keeps one heavy site from overflowing
-                // the lists of every region near it.  (The condition is the
-                // same for the whole workgroup; bins of more than 64 sites
-                // load whole.)
+                // From the second round on, when the round's bins would
+                // overflow the list: a site whose own lower bound over the
+                // region (from the gap to its nearest periodic image; for
+                // Laguerre the gap squared minus its weight, for Johnson-Mehl
+                // its time plus the gap over v) exceeds UB + M loses at every
+                // voxel, so it is not loaded.  This keeps the list within
+                // LDS where sites are dense (clusters), and keeps one heavy
+                // Laguerre site, whose weight sets everyone's reach, from
+                // overflowing the lists of every region near it.  (The
+                // condition is the same for the whole workgroup; bins of more
+                // than 64 sites load whole.)
                 unsigned long long keep = ~0ull;
-                const bool filtered = KIND == KL && nR + total > CAP_R && skip_cut < __builtin_inf();
+                const bool filtered = (DENSE || KIND == KL) && nR + total > CAP_R && skip_cut < __builtin_inf();
                 if (filtered) {
                     int nload = cnt;
                     if (cnt > 0 && cnt <= 64) {
@@ -1311,7 +1340,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                                 }
                                 g2 += gap > 0.0 ? gap * gap : 0.0;
                             }
-                            if (g2 - sv.w <= skip_cut) {
+                            if (may_win_region<KIND>(C, g2, sv.w, skip_cut)) {
                                 keep |= 1ull << k;
                                 ++nload;
                             }
@@ -1320,7 +1349,13 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     off = block_excl_scan(nload, total, R.wsum, tid);
                 }
                 if (nR + total > CAP_R) {
-                    overflow = true;
+                    // (Overflow kernels) a first box too dense for the list
+                    // starts over from the region's own bins; the rounds
+                    // after it load through the test above.
+                    if (DENSE && round == 0 && !dense)
+                        restart = true;
+                    else
+                        overflow = true;
                     break;
                 }
                 // Each bin first writes the sorted position and wrap code of
@@ -1351,6 +1386,20 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
                     R.ri[nR + p] = J.sidx[sp];
                 }
                 nR += total;
+            }
+            if (DENSE && restart) {
+                restart = false;
+                dense = true;
+                for (int a = 0; a < 3; ++a) {
+                    blo[a] = own_lo[a];
+                    bhi[a] = own_hi[a];
+                    olo[a] = 1;
+                    ohi[a] = 0;
+                }
+                nR = 0;
+                round = -1;
+                __syncthreads();
+                continue;
             }
             if (overflow)
                 break;
@@ -1474,6 +1523,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             }
         }
         tile_ovf = overflow;
+        region_ovf = overflow;
         if (!overflow && G.live) {
             TileLds& S = sm.r.tile[w];
             const double thr = ubT + C.M;
@@ -1653,10 +1703,18 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             }
         }
     }
-    if (G.live) {
+    if (!DENSE && region_ovf) {
+        // leave the whole region to the overflow kernel
+        if (tid == 0) {
+            const int pos = atomicAdd(J.ovf_count, 1);
+            J.ovf_list[pos] = (int32_t)(-unit - 1);
+        }
+    } else if (G.live) {
         if (tile_ovf) {
-            // leave this tile to the fallback kernel
-            if (lane == 0) {
+            if (DENSE) {
+                return true;
+            } else if (lane == 0) {
+                // leave this tile to the overflow kernel
                 const int pos = atomicAdd(J.ovf_count, 1);
                 J.ovf_list[pos] = (int32_t)(unit * NW + w);
             }
@@ -1671,6 +1729,7 @@ __device__ void label_region(const JobDev& J, int64_t r, int64_t unit, Smem& sm,
             }
         }
     }
+    return false;
 }
 
 // One tile of the overflow list, alone (fallback path, one wavefront).
@@ -1719,7 +1778,17 @@ template <int KIND, int DIM, int CFG>
 __device__ inline void region_cfg(const JobDev& J, int64_t r, int64_t unit, Smem& sm, int tid)
 {
     constexpr TileShape T = (DIM == 3) ? kShape3[CFG] : kShape2[CFG];
-    label_region<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rows, T.rx, T.ry, T.rz>(J, r, unit, sm, tid);
+    label_region<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rows, T.rx, T.ry, T.rz, false>(J, r, unit, sm, tid);
+}
+
+// A region the main kernel queued whole (its gather overflowed), with the
+// dense-capable gather (overflow kernels); true for a wavefront whose tile is
+// left to the per-tile walk.
+template <int KIND, int DIM, int CFG>
+__device__ inline bool region_dense_cfg(const JobDev& J, int64_t r, Smem& sm, int tid)
+{
+    constexpr TileShape T = (DIM == 3) ? kShape3[CFG] : kShape2[CFG];
+    return label_region<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rows, T.rx, T.ry, T.rz, true>(J, r, r, sm, tid);
 }
 
 template <int KIND, int DIM, int CFG>

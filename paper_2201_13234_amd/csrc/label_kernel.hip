@@ -45,17 +45,30 @@ __global__ __launch_bounds__(NT) void k_label_single(const JobDev* __restrict__ 
     region_cfg<KIND, DIM, CFG>(J, r, r, sm, threadIdx.x);
 }
 
-// Tiles the main kernel left over, one wavefront each.
+// What the main kernel left over: first the regions it queued whole (their
+// gather overflowed the region list; one workgroup each, with the dense-capable
+// gather), then the tiles whose candidate list overflowed (one wavefront each).
 template <int KIND, int DIM, int CFG>
-__global__ __launch_bounds__(WAVE) void k_label_fallback(const JobDev* __restrict__ jp)
+__global__ __launch_bounds__(NT) void k_label_fallback(const JobDev* __restrict__ jp)
 {
-    __shared__ FallbackLds S;
+    __shared__ Smem sm;
+    __shared__ FallbackLds fb[NW];
     const JobDev& J = job_ref(jp, 0);
     const int n = *(volatile int32_t*)J.ovf_count;
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int id = J.ovf_list[i];
-        alone_cfg<KIND, DIM, CFG>(J, id / NW, id % NW, S, threadIdx.x);
-        __syncthreads();
+        if (id < 0) {
+            const int64_t r = -(int64_t)id - 1;
+            if (region_dense_cfg<KIND, DIM, CFG>(J, r, sm, threadIdx.x))
+                alone_cfg<KIND, DIM, CFG>(J, r, w, fb[w], lane);
+            __syncthreads();
+        }
+    }
+    for (int i = blockIdx.x * NW + w; i < n; i += gridDim.x * NW) {
+        const int id = J.ovf_list[i];
+        if (id >= 0)
+            alone_cfg<KIND, DIM, CFG>(J, id / NW, id % NW, fb[w], lane);
     }
 }
 
@@ -65,10 +78,10 @@ hipError_t launch_single_cfg(const JobDev& job, const JobDev* jd, hipStream_t s,
     const unsigned grid = fallback ? kFallbackGrid : (unsigned)job.nregions;
     if (fallback) {
         switch (job.cfg) {
-        case 0: k_label_fallback<KIND, DIM, 0><<<grid, WAVE, 0, s>>>(jd); break;
-        case 1: k_label_fallback<KIND, DIM, 1><<<grid, WAVE, 0, s>>>(jd); break;
-        case 2: k_label_fallback<KIND, DIM, 2><<<grid, WAVE, 0, s>>>(jd); break;
-        default: k_label_fallback<KIND, DIM, 3><<<grid, WAVE, 0, s>>>(jd); break;
+        case 0: k_label_fallback<KIND, DIM, 0><<<grid, NT, 0, s>>>(jd); break;
+        case 1: k_label_fallback<KIND, DIM, 1><<<grid, NT, 0, s>>>(jd); break;
+        case 2: k_label_fallback<KIND, DIM, 2><<<grid, NT, 0, s>>>(jd); break;
+        default: k_label_fallback<KIND, DIM, 3><<<grid, NT, 0, s>>>(jd); break;
         }
     } else {
         switch (job.cfg) {
