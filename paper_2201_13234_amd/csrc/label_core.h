@@ -1798,7 +1798,7 @@ __device__ inline void alone_cfg(const JobDev& J, int64_t r, int w, FallbackLds&
     label_tile_alone<KIND, DIM, T.run, T.lx, T.ly, T.lz, T.rows, T.rx, T.ry, T.rz>(J, r, w, S, lane);
 }
 
-constexpr int kFallbackGrid = 512;
+constexpr int kFallbackGrid = 256;  // workgroups of the overflow kernels (each holds 68 KB of LDS)
 
 }  // namespace
 }  // namespace vt
