@@ -42,6 +42,11 @@ namespace {
 
 constexpr int NDT = 256;    // threads per workgroup, one voxel each
 constexpr int ND_CAP = 512; // candidates staged in LDS per evaluation round
+// Per-axis squared differences of staged candidates over the tile's
+// coordinates (orthogonal periods or none): TABN doubles, a chunk of
+// TABN / W candidates at a time for W = the sum of the tile's sides.
+constexpr int TABN = 2048;
+constexpr int TABW = 64;    // largest W that uses the table
 constexpr int kNdGrid = 8192;
 
 __device__ inline unsigned long long nd_ordered(double v)
@@ -188,6 +193,7 @@ struct NdLds {
     double p[ND_CAP];
     int32_t idx[ND_CAP];
     int32_t dead[ND_CAP];    // beaten on the whole tile by the reference site
+    double tab[LAT || D < 2 ? 1 : TABN];  // [candidate of the chunk][row]: d_a * d_a
     int32_t count;
     double red[NDT / WAVE];
     int32_t ired[NDT / WAVE];
@@ -652,6 +658,78 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
     }
 }
 
+// Where a thread builds and reads the per-axis table (orthogonal periods or
+// none, 2 to 6 axes): row r = offset of axis a + tile-local coordinate i holds
+// d_a * d_a for the voxel coordinate x_a = (v0_a + i + 1/2) h_a, d_a the
+// (minimum-image) difference s_a - x_a of each candidate of the chunk.  The
+// key then sums the rows of the thread's voxel in the definition's order,
+// q = d0*d0 + T with T = d1*d1, T + d2*d2, ...: the same operations as
+// nd_evaluate, each difference and square computed once per tile instead of
+// once per voxel.
+struct NdTab {
+    bool on;        // the table is used for this tile
+    int W;          // rows: the sum of the tile's sides
+    int row[kMaxDim];  // the thread's rows (its first voxel)
+    int brow;       // the row this thread builds, and its axis
+    int baxis;
+    int bk0, bkstep;   // first candidate of the chunk it builds, stride
+    double bx;      // the voxel coordinate of its row
+};
+
+template <int KIND, int DIM, bool LAT>
+__device__ inline void nd_eval_round(const NdDev& J, NdLds<DIM, LAT>& S, int cnt, const NdTab& tb, int tx0,
+                                     const double* x, const double* x1, bool two, bool live_any, double& best,
+                                     int& blab, double& best1, int& blab1)
+{
+    if (LAT || DIM < 2 || !tb.on) {
+        if (live_any && cnt > 0)
+            nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, x1, two, best, blab, best1, blab1);
+        return;
+    }
+    const int W = tb.W;
+    const int chunk = TABN / W;
+    for (int c0 = 0; c0 < cnt; c0 += chunk) {
+        const int nk = min(chunk, cnt - c0);
+        if (tb.bk0 >= 0) {
+            const double Ha = J.H[tb.baxis], La = J.L[tb.baxis];
+            for (int k = tb.bk0; k < nk; k += tb.bkstep) {
+                double e = S.c[tb.baxis][c0 + k] - tb.bx;
+                if (J.bc)
+                    e = e >= Ha ? e - La : (e < -Ha ? e + La : e);
+                S.tab[LAT || DIM < 2 ? 0 : k * W + tb.brow] = e * e;
+            }
+        }
+        __syncthreads();
+        if (live_any) {
+            for (int k = 0; k < nk; ++k) {
+                const int g = c0 + k;
+                if (KIND != KIND_JM && S.dead[g])  // the same for every thread
+                    continue;
+                const double* t = &S.tab[LAT || DIM < 2 ? 0 : k * W];
+                double T = t[tb.row[1]];
+#pragma unroll
+                for (int a = 2; a < DIM; ++a)
+                    T = T + t[tb.row[a]];
+                const double p = S.p[g];
+                const int id = S.idx[g];
+                const double key = nd_key_q<KIND>(J, t[tb.row[0]] + T, p);
+                if (key < best || (key == best && id < blab)) {
+                    best = key;
+                    blab = id;
+                }
+                if (two) {
+                    const double key1 = nd_key_q<KIND>(J, t[tb.row[0] + tx0] + T, p);
+                    if (key1 < best1 || (key1 == best1 && id < blab1)) {
+                        best1 = key1;
+                        blab1 = id;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // General periods: the box of translations k that can bring sorted site
 // `pos` within key `cut` of the tile.  Returns false when none can.
 template <int KIND, int DIM>
@@ -831,6 +909,48 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
         }
         live = live && l == 0;
         live1 = live1 && l == 0;
+        NdTab tb;
+        tb.on = false;
+        tb.W = 0;
+        tb.bk0 = -1;
+        tb.bkstep = 1;
+        tb.brow = tb.baxis = 0;
+        tb.bx = 0.0;
+        if (!LAT && DIM >= 2) {
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                tb.row[a] = tb.W + (int)(vi[a] - v0[a]);
+                tb.W += J.T[a];
+            }
+            tb.on = tb.W <= TABW;
+            if (tb.on) {
+                // this thread builds row tid % W for candidates tid / W,
+                // + 256 / W, ... of each chunk
+                const int r = tid % tb.W;
+                tb.bkstep = NDT / tb.W;
+                tb.bk0 = tid < tb.bkstep * tb.W ? tid / tb.W : -1;
+                int i = r, ax = 0;
+#pragma unroll
+                for (int a = 0; a < DIM - 1; ++a) {
+                    if (ax == a && i >= J.T[a]) {
+                        i -= J.T[a];
+                        ax = a + 1;
+                    }
+                }
+                int64_t va = 0;
+                double ha = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    if (ax == a) {
+                        va = v0[a];
+                        ha = J.h[a];
+                    }
+                }
+                tb.brow = r;
+                tb.baxis = ax;
+                tb.bx = ((double)(va + i) + 0.5) * ha;
+            }
+        }
         double best = __builtin_inf(), best1 = __builtin_inf();
         int blab = 0x7fffffff, blab1 = 0x7fffffff;
         if (!bad) {
@@ -979,8 +1099,8 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
                         mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
-                        if (live || live1)
-                            nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, x1, two, best, blab, best1, blab1);
+                        nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab,
+                                                      best1, blab1);
                         __syncthreads();
                         if (tid == 0)
                             S.count = 0;
@@ -990,8 +1110,8 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
             }
             const int cnt = S.count;
             mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
-            if ((live || live1) && cnt > 0)
-                nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, x1, two, best, blab, best1, blab1);
+            nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab, best1,
+                                          blab1);
             __syncthreads();
         }
         if (live || live1) {
