@@ -47,6 +47,9 @@ constexpr int ND_CAP = 512; // candidates staged in LDS per evaluation round
 // TABN / W candidates at a time for W = the sum of the tile's sides.
 constexpr int TABN = 2048;
 constexpr int TABW = 64;    // largest W that uses the table
+// Orthogonal search: the sorted positions of one batch of bins' sites, one
+// per slot, SLOTCAP at a time (one site per thread and pass).
+constexpr int SLOTCAP = 1024;
 constexpr int kNdGrid = 8192;
 
 __device__ inline unsigned long long nd_ordered(double v)
@@ -194,7 +197,10 @@ struct NdLds {
     int32_t idx[ND_CAP];
     int32_t dead[ND_CAP];    // beaten on the whole tile by the reference site
     double tab[LAT || D < 2 ? 1 : TABN];  // [candidate of the chunk][row]: d_a * d_a
+    double kl[LAT ? 1 : ND_CAP];          // lower bound of each staged candidate's key over the tile
+    int32_t slot[LAT ? 1 : SLOTCAP];      // sorted site positions of the current batch
     int32_t count;
+    int32_t sovf;                         // the search staged more than ND_CAP candidates
     double red[NDT / WAVE];
     int32_t ired[NDT / WAVE];
 };
@@ -240,6 +246,31 @@ __device__ inline double block_argmin(double v, int pos, L& S, int& at)
             at = S.ired[w];
         }
     return r;
+}
+
+// Exclusive prefix sum of v over the workgroup; total = the sum.
+template <class L>
+__device__ inline int block_excl_scan(int v, int& total, L& S)
+{
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    int x = v;
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1)
+        S.ired[w] = x;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+    for (int k = 0; k < NDT / WAVE; ++k) {
+        const int t = S.ired[k];
+        off += k < w ? t : 0;
+        total += t;
+    }
+    return off + x - v;
 }
 
 template <class L>
@@ -417,6 +448,38 @@ __device__ inline int64_t box_bin(const NdDev& J, const NdBox& B, int64_t j, con
     return lin;
 }
 
+// box_bin in 32-bit arithmetic, for the orthogonal search.  A box that does
+// not cover an axis is narrower than the bin grid and starts above -nb, so
+// its bins lie in (-nb, 2 nb) before wrapping; a box that covers an axis
+// starts at 0.  (The bin count fits in 32 bits.)
+template <int DIM>
+__device__ inline int box_bin32(const NdDev& J, const NdBox& B, int j, const NdBox& P, bool has_prev,
+                                bool& inside_prev)
+{
+    int lin = 0, stride = 1;
+    bool in = has_prev;
+    unsigned u = (unsigned)j;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const unsigned w = (unsigned)B.width[a];
+        const unsigned q = u / w;
+        const int o = (int)(u - q * w);
+        u = q;
+        const int nb = J.nb[a];
+        int b = B.first[a] + o;
+        b = b < 0 ? b + nb : (b >= nb ? b - nb : b);
+        if (in && !P.full[a]) {
+            int rel = b - P.first[a];
+            rel = rel < 0 ? rel + nb : (rel >= nb ? rel - nb : rel);
+            in = rel < P.width[a];
+        }
+        lin += b * stride;
+        stride *= nb;
+    }
+    inside_prev = in;
+    return lin;
+}
+
 // General periods grow whole rings: the box of ring r, and the smallest
 // Cartesian distance from the tile to a site outside it (infinite once every
 // site has been visited): a fractional gap gamma along axis a is at least
@@ -507,25 +570,31 @@ __device__ inline bool beaten_on_tile(const NdDev& J, const NdConst& C, const Nd
     return acc > C.M;
 }
 
-// Marks the staged candidates [0, cnt) that the reference site beats on the
-// whole tile (Voronoi and Laguerre with orthogonal periods or none).
+// Marks the staged candidates [0, cnt) that cannot win (orthogonal periods
+// or none): with use_cut, those whose lower bound exceeds cut (staged while
+// the search's UB was larger); for Voronoi and Laguerre, those that the
+// reference site beats on the whole tile.
 template <int KIND, int DIM, bool LAT>
 __device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTile<DIM>& G, NdLds<DIM, LAT>& S,
-                                   int cnt, int ref)
+                                   int cnt, int ref, bool use_cut, double cut)
 {
-    if (LAT || KIND == KIND_JM)
+    if (LAT)
         return;  // nothing to mark: the evaluation does not look at the marks
     double cr[DIM];
     double pr = 0.0;
-    const bool use = ref >= 0;
+    const bool use = KIND != KIND_JM && ref >= 0;
     if (use) {
 #pragma unroll
         for (int a = 0; a < DIM; ++a)
             cr[a] = J.sc[(int64_t)ref * DIM + a];
         pr = J.sp[ref];
     }
-    for (int k = threadIdx.x; k < cnt; k += NDT)
-        S.dead[k] = use ? beaten_on_tile<KIND, DIM, LAT>(J, C, G, S, k, cr, pr) : 0;
+    for (int k = threadIdx.x; k < cnt; k += NDT) {
+        bool d = use_cut && S.kl[LAT ? 0 : k] > cut;
+        if (!d && use)
+            d = beaten_on_tile<KIND, DIM, LAT>(J, C, G, S, k, cr, pr);
+        S.dead[k] = d;
+    }
     __syncthreads();
 }
 
@@ -618,7 +687,7 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
                                    const double* x1, bool two, double& best, int& blab, double& best1, int& blab1)
 {
     for (int k = 0; k < count; ++k) {
-        if (!LAT && KIND != KIND_JM && S.dead[k])  // the same for every thread
+        if (!LAT && S.dead[k])  // the same for every thread
             continue;
         const int id = S.idx[k];
         double key, key1 = 0.0;
@@ -703,7 +772,7 @@ __device__ inline void nd_eval_round(const NdDev& J, NdLds<DIM, LAT>& S, int cnt
         if (live_any) {
             for (int k = 0; k < nk; ++k) {
                 const int g = c0 + k;
-                if (KIND != KIND_JM && S.dead[g])  // the same for every thread
+                if (S.dead[g])  // the same for every thread
                     continue;
                 const double* t = &S.tab[LAT || DIM < 2 ? 0 : k * W];
                 double T = t[tb.row[1]];
@@ -993,7 +1062,12 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
             } else {
                 // orthogonal periods or none: start from the first ring of
                 // neighbour bins, which makes UB tight, then move only the
-                // faces whose sites might still win
+                // faces whose sites might still win.  Each round's new bins
+                // go in batches of NDT: their sites' sorted positions are
+                // listed in LDS, then one thread per site takes its bounds,
+                // UB is reduced, and the sites with a lower bound within
+                // UB + M are staged right away (UB only decreases, so the
+                // final cut is applied to them afterwards).
                 int elo[DIM], ehi[DIM];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a)
@@ -1001,29 +1075,78 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                 B = grown_box<DIM>(J, bl, bh, elo, ehi);
                 P = B;
                 bool grown = false;
+                if (tid == 0) {
+                    S.count = 0;
+                    S.sovf = 0;
+                }
                 for (;;) {
-                    double my = __builtin_inf();
-                    int mypos = -1;
-                    for (int64_t j = tid; j < B.count; j += NDT) {
-                        bool in_prev;
-                        const int64_t lin = box_bin<DIM>(J, B, j, P, grown, in_prev);
-                        if (in_prev)
-                            continue;
-                        const int s1 = J.bin_start[lin + 1];
-                        for (int s = J.bin_start[lin]; s < s1; ++s) {
-                            double kl, ku;
-                            site_bounds<KIND, DIM>(J, C, s, G, kl, ku);
-                            if (ku < my) {
-                                my = ku;
-                                mypos = s;
+                    const int nbox = (int)B.count;
+                    for (int jb = 0; jb < nbox; jb += NDT) {
+                        const int j = jb + tid;
+                        int s0 = 0, n = 0;
+                        if (j < nbox) {
+                            bool in_prev;
+                            const int lin = box_bin32<DIM>(J, B, j, P, grown, in_prev);
+                            if (!in_prev) {
+                                s0 = J.bin_start[lin];
+                                n = J.bin_start[lin + 1] - s0;
                             }
                         }
-                    }
-                    int at;
-                    const double m = block_argmin(my, mypos, S, at);
-                    if (m < UB) {
-                        UB = m;
-                        ubpos = at;
+                        int total;
+                        const int pre = block_excl_scan(n, total, S);
+                        for (int w0 = 0; w0 < total; w0 += SLOTCAP) {
+                            const int k0 = max(0, w0 - pre), k1 = min(n, w0 + SLOTCAP - pre);
+                            for (int k = k0; k < k1; ++k)
+                                S.slot[LAT ? 0 : pre + k - w0] = s0 + k;
+                            __syncthreads();
+                            const int wn = min(SLOTCAP, total - w0);
+                            double kls[SLOTCAP / NDT];
+                            int ps[SLOTCAP / NDT];
+                            double my = __builtin_inf();
+                            int mypos = -1;
+#pragma unroll
+                            for (int r = 0; r < SLOTCAP / NDT; ++r) {
+                                const int i = tid + r * NDT;
+                                kls[r] = __builtin_inf();
+                                ps[r] = -1;
+                                if (i < wn) {
+                                    const int pos = S.slot[LAT ? 0 : i];
+                                    double kl, ku;
+                                    site_bounds<KIND, DIM>(J, C, pos, G, kl, ku);
+                                    kls[r] = kl;
+                                    ps[r] = pos;
+                                    if (ku < my) {
+                                        my = ku;
+                                        mypos = pos;
+                                    }
+                                }
+                            }
+                            int at;
+                            const double m = block_argmin(my, mypos, S, at);
+                            if (m < UB) {
+                                UB = m;
+                                ubpos = at;
+                            }
+                            const double cutr = UB + C.M;
+#pragma unroll
+                            for (int r = 0; r < SLOTCAP / NDT; ++r) {
+                                if (ps[r] >= 0 && kls[r] <= cutr) {
+                                    const int slot = atomicAdd(&S.count, 1);
+                                    if (slot < ND_CAP) {
+                                        const int64_t pos = ps[r];
+#pragma unroll
+                                        for (int a = 0; a < DIM; ++a)
+                                            S.c[a][slot] = J.sc[pos * DIM + a];
+                                        S.p[slot] = J.sp[pos];
+                                        S.idx[slot] = J.sidx[pos];
+                                        S.kl[LAT ? 0 : slot] = kls[r];
+                                    } else {
+                                        S.sovf = 1;
+                                    }
+                                }
+                            }
+                            __syncthreads();  // the slot list is rewritten next
+                        }
                     }
                     bool grow = false;
 #pragma unroll
@@ -1050,12 +1173,15 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                     grown = true;
                 }
             }
-            // 2. stage the candidates and take the lexicographic minimum
-            if (tid == 0)
+            // 2. stage the candidates (general periods, or an orthogonal search
+            //    that staged more than ND_CAP) and take the lexicographic minimum
+            const double cut = UB + C.M;
+            const bool staged = !LAT && !S.sovf;  // uniform: read after the search's last barrier
+            __syncthreads();
+            if (!staged && tid == 0)
                 S.count = 0;
             __syncthreads();
-            const double cut = UB + C.M;
-            for (int64_t base = 0; base < B.count; base += NDT) {
+            for (int64_t base = 0; base < (staged ? 0 : B.count); base += NDT) {
                 const int64_t j = base + tid;
                 int s0 = 0, s1 = 0;
                 if (j < B.count) {
@@ -1098,7 +1224,7 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                     const int cnt = S.count;
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
-                        mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
+                        mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, false, cut);
                         nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab,
                                                       best1, blab1);
                         __syncthreads();
@@ -1109,7 +1235,7 @@ __global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
                 }
             }
             const int cnt = S.count;
-            mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos);
+            mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, staged, cut);
             nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab, best1,
                                           blab1);
             __syncthreads();
