@@ -17,20 +17,25 @@
 // fractional coordinates for general periods).
 //
 // Labelling: one workgroup of 256 threads per tile of at most 256 voxels
-// (powers of two per axis), one voxel per thread.
+// (powers of two per axis), one voxel per thread (two along axis 0 on large
+// grids with orthogonal periods in 2 to 4 axes).
 //   1. The box of visited bins around the tile grows (face by face, or by
 //      whole rings for general periods) until the sites beyond it provably
 //      lose: UB = the smallest upper bound of a visited site's key over the
 //      tile's voxel centres, and the sites beyond a face are at least its
 //      `gap` away, so their keys exceed gap^2 (Voronoi), gap^2 - max w
-//      (Laguerre), min t + gap / v (Johnson-Mehl).
+//      (Laguerre), min t + gap / v (Johnson-Mehl).  With orthogonal periods
+//      each round lists its new bins' sites in LDS, one site per thread, and
+//      stages the sites whose lower bound is within the current UB + M.
 //   2. The visited sites whose lower bound over the tile is <= UB + M are
-//      staged in LDS (for general periods with the box of translations that
-//      can bring them within reach).  Voronoi and Laguerre with orthogonal
-//      periods drop those that the site attaining UB beats on the whole tile
-//      (linear key difference).  Every thread takes the lexicographic minimum
-//      of (key, site index) over the rest: the brute-force result with ties
-//      to the lowest index, whatever the order of the candidates.
+//      kept in LDS (for general periods, staged after the search with the
+//      box of translations that can bring them within reach).  Voronoi and
+//      Laguerre with orthogonal periods drop those that the site attaining UB
+//      beats on the whole tile (linear key difference).  Every thread takes
+//      the lexicographic minimum of (key, site index) over the rest: the
+//      brute-force result with ties to the lowest index, whatever the order
+//      of the candidates.  With orthogonal periods the per-axis squared
+//      differences come from a table formed once per tile.
 // M = 2^-36 of the key scale, far above the rounding error of any bound or
 // key, so a dropped site's (or translation's) computed key is strictly
 // above the winner's.
@@ -41,7 +46,7 @@ namespace vt {
 namespace {
 
 constexpr int NDT = 256;    // threads per workgroup, one voxel each
-constexpr int ND_CAP = 512; // candidates staged in LDS per evaluation round
+constexpr int ND_CAP = 256; // candidates staged in LDS per evaluation round
 // Per-axis squared differences of staged candidates over the tile's
 // coordinates (orthogonal periods or none): TABN doubles, a chunk of
 // TABN / W candidates at a time for W = the sum of the tile's sides.
@@ -881,7 +886,7 @@ __device__ inline bool lattice_reach(const NdDev& J, const NdConst& C, int64_t p
 }
 
 template <int KIND, int DIM, bool LAT>
-__global__ __launch_bounds__(NDT, 3) void k_nd_label(NdDev J)
+__global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
 {
     __shared__ NdLds<DIM, LAT> S;
     const int tid = threadIdx.x;
