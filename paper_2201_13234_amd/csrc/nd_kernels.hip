@@ -293,6 +293,21 @@ __device__ inline int block_max_int(int v, L& S)
     return r;
 }
 
+// The next mixed-radix digit of rem in base d (rem becomes rem / d), in
+// 32-bit arithmetic whenever both fit (always, for tile indices below 2^32).
+__device__ inline int64_t take_digit(int64_t& rem, int64_t d)
+{
+    if (rem < 0x100000000LL && d < 0x100000000LL) {
+        const unsigned r = (unsigned)rem, dd = (unsigned)d;
+        const unsigned q = r / dd;
+        rem = q;
+        return (int64_t)(r - q * dd);
+    }
+    const int64_t q = rem / d, o = rem - q * d;
+    rem = q;
+    return o;
+}
+
 // Key of a squared distance q (bounds only: Johnson-Mehl through 1/v).
 template <int KIND>
 __device__ inline double key_of_q(double q, double p, const NdConst& C)
@@ -929,8 +944,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
         bool live = true, live1 = two;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
-            const int64_t tc = rem % J.nt[a];
-            rem /= J.nt[a];
+            const int64_t tc = take_digit(rem, J.nt[a]);
             v0[a] = tc * J.T[a];
             ve[a] = (v0[a] + J.T[a] < J.n[a] ? v0[a] + J.T[a] : J.n[a]) - 1;
             const int ta = a == 0 ? tx0 : J.T[a];
