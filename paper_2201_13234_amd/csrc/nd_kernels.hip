@@ -191,6 +191,14 @@ struct NdConst {
     double rv;         // 1 / v
 };
 
+// What the bounds need of a tile.
+template <int D>
+struct NdTile {
+    double lo[D], hi[D];     // orthogonal: box of voxel centres; lattice: fractional box
+    double blo[D], bhi[D];   // lattice: Cartesian bounding box of the voxel centres
+    double cen[D];           // lattice: fractional centre
+};
+
 // Staged candidates.  For general periods each carries the box of
 // translations k (first value and count per axis) to evaluate.
 template <int D, bool LAT>
@@ -206,6 +214,8 @@ struct NdLds {
     int32_t slot[LAT ? 1 : SLOTCAP];      // sorted site positions of the current batch
     int32_t count;
     int32_t sovf;                         // the search staged more than ND_CAP candidates
+    double geo[LAT ? D * (D + 2) + 1 : 1]; // general periods: reference image, tile centre, half edges, parameter
+    NdTile<D> tile;                       // general periods: the current tile's geometry
     double red[NDT / WAVE];
     int32_t ired[NDT / WAVE];
 };
@@ -319,13 +329,6 @@ __device__ inline double key_of_q(double q, double p, const NdConst& C)
     return p + sqrt(q) * C.rv;
 }
 
-// What the bounds need of a tile.
-template <int D>
-struct NdTile {
-    double lo[D], hi[D];     // orthogonal: box of voxel centres; lattice: fractional box
-    double blo[D], bhi[D];   // lattice: Cartesian bounding box of the voxel centres
-    double cen[D];           // lattice: fractional centre
-};
 
 // Bounds of the key of the sorted site `pos` over the tile (orthogonal
 // periods or none): per axis the smallest and largest (minimum-image)
@@ -590,16 +593,87 @@ __device__ inline bool beaten_on_tile(const NdDev& J, const NdConst& C, const Nd
     return acc > C.M;
 }
 
-// Marks the staged candidates [0, cnt) that cannot win (orthogonal periods
-// or none): with use_cut, those whose lower bound exceeds cut (staged while
+// Marks the staged candidates [0, cnt) that cannot win.  Orthogonal periods
+// or none: with use_cut, those whose lower bound exceeds cut (staged while
 // the search's UB was larger); for Voronoi and Laguerre, those that the
-// reference site beats on the whole tile.
+// reference site beats on the whole tile.  General periods (Voronoi and
+// Laguerre): candidates with a single translation that the reference's image
+// nearest the tile beats on the whole parallelepiped of voxel centres (centre
+// c, half edges u_i); for images e and r, |x - e|^2 - |x - r|^2 =
+// (r - e) . (2x - e - r) is linear in x, so its minimum there is
+// (r - e) . (2c - e - r) - 2 sum_i |(r - e) . u_i|.  The reference is staged
+// with that translation (its lower bound is below UB), so the winner's
+// computed key is at most that image's.
 template <int KIND, int DIM, bool LAT>
 __device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTile<DIM>& G, NdLds<DIM, LAT>& S,
-                                   int cnt, int ref, bool use_cut, double cut)
+                                   int cnt, int ref, bool use_cut, double cut, const int64_t* v0, const int64_t* ve)
 {
-    if (LAT)
-        return;  // nothing to mark: the evaluation does not look at the marks
+    if (LAT) {
+        // the reference's image r, the centre c and the half edges u_i of the
+        // tile go to LDS (geo: r, c, u_0, u_1, ..., parameter of r)
+        const bool use = KIND != KIND_JM && ref >= 0;
+        double* g = S.geo;
+        __syncthreads();
+        if (use && threadIdx.x == 0) {
+            double kr[DIM], r[DIM];
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+                kr[i] = rint(G.cen[i] - J.sf[(int64_t)ref * DIM + i]);
+            lattice_image<DIM>(J, ref, kr, r);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) {
+                g[a] = r[a];
+                g[DIM + a] = 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+                const double mid = 0.5 * ((double)v0[i] + (double)ve[i]) + 0.5;
+                const double half = 0.5 * (double)(ve[i] - v0[i]);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    g[DIM + a] += mid * J.hv[i][a];
+                    g[(2 + i) * DIM + a] = half * J.hv[i][a];
+                }
+            }
+            g[DIM * (DIM + 2)] = J.sp[ref];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < cnt; k += NDT) {
+            bool d = false;
+            bool single = use;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+                single = single && S.kn[LAT ? i : 0][LAT ? k : 0] == 1;
+            if (single) {
+                double dl[DIM], lin = 0.0, slope = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    double o = 0.0;
+#pragma unroll
+                    for (int i = 0; i < DIM; ++i)
+                        o += S.klo[LAT ? i : 0][LAT ? k : 0] * J.P[i][a];
+                    const double e = S.c[a][k] + o;
+                    dl[a] = g[a] - e;
+                    lin += dl[a] * (2.0 * g[DIM + a] - e - g[a]);
+                }
+#pragma unroll
+                for (int i = 0; i < DIM; ++i) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a)
+                        t += dl[a] * g[(2 + i) * DIM + a];
+                    slope += fabs(t);
+                }
+                double acc = lin - 2.0 * slope;
+                if (KIND == KIND_LAGUERRE)
+                    acc -= S.p[k] - g[DIM * (DIM + 2)];
+                d = acc > C.M;
+            }
+            S.dead[k] = d;
+        }
+        __syncthreads();
+        return;
+    }
     double cr[DIM];
     double pr = 0.0;
     const bool use = KIND != KIND_JM && ref >= 0;
@@ -707,7 +781,7 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
                                    const double* x1, bool two, double& best, int& blab, double& best1, int& blab1)
 {
     for (int k = 0; k < count; ++k) {
-        if (!LAT && S.dead[k])  // the same for every thread
+        if (S.dead[k])  // the same for every thread
             continue;
         const int id = S.idx[k];
         double key, key1 = 0.0;
@@ -934,13 +1008,13 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
         int64_t v0[DIM], ve[DIM], vi[DIM];
         double x[DIM];
         int bl[DIM], bh[DIM];
-        NdTile<DIM> G;
+        NdTile<DIM> G0;
         int64_t rem = t;
         int l = tid;
         // threads along axis 0; with two voxels per thread the second is tx0
         // voxels further along axis 0
         const int tx0 = J.T[0] / J.vpt;
-        const bool two = J.vpt > 1;
+        const bool two = !LAT && J.vpt > 1;  // general periods: one voxel per thread
         bool live = true, live1 = two;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -954,15 +1028,15 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             live = live && vi[a] <= ve[a];
             live1 = live1 && vi[a] + (a == 0 ? tx0 : 0) <= ve[a];
             if (LAT) {
-                G.lo[a] = ((double)v0[a] + 0.5) / (double)J.n[a];
-                G.hi[a] = ((double)ve[a] + 0.5) / (double)J.n[a];
-                G.cen[a] = 0.5 * (G.lo[a] + G.hi[a]);
+                G0.lo[a] = ((double)v0[a] + 0.5) / (double)J.n[a];
+                G0.hi[a] = ((double)ve[a] + 0.5) / (double)J.n[a];
+                G0.cen[a] = 0.5 * (G0.lo[a] + G0.hi[a]);
             } else {
-                G.lo[a] = ((double)v0[a] + 0.5) * J.h[a];
-                G.hi[a] = ((double)ve[a] + 0.5) * J.h[a];
+                G0.lo[a] = ((double)v0[a] + 0.5) * J.h[a];
+                G0.hi[a] = ((double)ve[a] + 0.5) * J.h[a];
                 x[a] = ((double)vi[a] + 0.5) * J.h[a];
             }
-            const int b0 = (int)(G.lo[a] * J.inv_bs[a]), b1 = (int)(G.hi[a] * J.inv_bs[a]);
+            const int b0 = (int)(G0.lo[a] * J.inv_bs[a]), b1 = (int)(G0.hi[a] * J.inv_bs[a]);
             bl[a] = min(max(b0, 0), J.nb[a] - 1);
             bh[a] = min(max(b1, 0), J.nb[a] - 1);
         }
@@ -991,12 +1065,20 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                     b0 += fmin(t0, t1);
                     b1 += fmax(t0, t1);
                 }
-                G.blo[a] = b0;
-                G.bhi[a] = b1;
+                G0.blo[a] = b0;
+                G0.bhi[a] = b1;
             }
         }
         live = live && l == 0;
         live1 = live1 && l == 0;
+        // general periods: the tile's geometry lives in LDS (read where the
+        // bounds need it) rather than in registers
+        if (LAT) {
+            if (tid == 0)
+                S.tile = G0;
+            __syncthreads();
+        }
+        const NdTile<DIM>& G = LAT ? S.tile : G0;
         NdTab tb;
         tb.on = false;
         tb.W = 0;
@@ -1046,7 +1128,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             //    provably lose; their keys are at least gap^2, gap^2 - max w
             //    or min t + gap / v for the gap to the box
             double UB = __builtin_inf();
-            int ubpos = -1;  // a sorted site attaining UB (orthogonal periods or none)
+            int ubpos = -1;  // a sorted site attaining UB
             NdBox B, P;
             if (LAT) {
                 // general periods: whole rings from the tile's own bins (their
@@ -1056,16 +1138,27 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                 P = B;
                 for (;;) {
                     double my = __builtin_inf();
+                    int mypos = -1;
                     for (int64_t j = tid; j < B.count; j += NDT) {
                         bool in_prev;
                         const int64_t lin = box_bin<DIM>(J, B, j, P, r > 0, in_prev);
                         if (in_prev)
                             continue;
                         const int s1 = J.bin_start[lin + 1];
-                        for (int s = J.bin_start[lin]; s < s1; ++s)
-                            my = fmin(my, lattice_upper<KIND, DIM>(J, C, s, G));
+                        for (int s = J.bin_start[lin]; s < s1; ++s) {
+                            const double u = lattice_upper<KIND, DIM>(J, C, s, G);
+                            if (u < my) {
+                                my = u;
+                                mypos = s;
+                            }
+                        }
                     }
-                    UB = fmin(UB, block_min(my, S));
+                    int at;
+                    const double m = block_argmin(my, mypos, S, at);
+                    if (m < UB) {
+                        UB = m;
+                        ubpos = at;
+                    }
                     const double g = ring_gap<DIM>(J, B, G);
                     if (g == __builtin_inf())
                         break;
@@ -1243,7 +1336,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                     const int cnt = S.count;
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
-                        mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, false, cut);
+                        mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, false, cut, v0, ve);
                         nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab,
                                                       best1, blab1);
                         __syncthreads();
@@ -1254,7 +1347,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                 }
             }
             const int cnt = S.count;
-            mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, staged, cut);
+            mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, staged, cut, v0, ve);
             nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab, best1,
                                           blab1);
             __syncthreads();
