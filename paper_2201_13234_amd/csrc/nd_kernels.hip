@@ -210,8 +210,8 @@ struct NdLds {
     int32_t idx[ND_CAP];
     int32_t dead[ND_CAP];    // beaten on the whole tile by the reference site
     double tab[LAT || D < 2 ? 1 : TABN];  // [candidate of the chunk][row]: d_a * d_a
-    double kl[LAT ? 1 : ND_CAP];          // lower bound of each staged candidate's key over the tile
-    int32_t slot[LAT ? 1 : SLOTCAP];      // sorted site positions of the current batch
+    double kl[ND_CAP];                    // lower bound of each staged candidate's key over the tile
+    int32_t slot[SLOTCAP];                // sorted site positions of the current batch
     int32_t count;
     int32_t sovf;                         // the search staged more than ND_CAP candidates
     double geo[LAT ? D * (D + 2) + 1 : 1]; // general periods: reference image, tile centre, half edges, parameter
@@ -639,8 +639,8 @@ __device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTil
         }
         __syncthreads();
         for (int k = threadIdx.x; k < cnt; k += NDT) {
-            bool d = false;
-            bool single = use;
+            bool d = use_cut && S.kl[k] > cut;
+            bool single = use && !d;
 #pragma unroll
             for (int i = 0; i < DIM; ++i)
                 single = single && S.kn[LAT ? i : 0][LAT ? k : 0] == 1;
@@ -684,7 +684,7 @@ __device__ inline void mark_beaten(const NdDev& J, const NdConst& C, const NdTil
         pr = J.sp[ref];
     }
     for (int k = threadIdx.x; k < cnt; k += NDT) {
-        bool d = use_cut && S.kl[LAT ? 0 : k] > cut;
+        bool d = use_cut && S.kl[k] > cut;
         if (!d && use)
             d = beaten_on_tile<KIND, DIM, LAT>(J, C, G, S, k, cr, pr);
         S.dead[k] = d;
@@ -897,8 +897,9 @@ __device__ inline void nd_eval_round(const NdDev& J, NdLds<DIM, LAT>& S, int cnt
 // `pos` within key `cut` of the tile.  Returns false when none can.
 template <int KIND, int DIM>
 __device__ inline bool lattice_reach(const NdDev& J, const NdConst& C, int64_t pos, const NdTile<DIM>& G,
-                                     double cut, double* klo, int* kn)
+                                     double cut, double* klo, int* kn, double& klow)
 {
+    klow = -__builtin_inf();  // unknown unless the box is trimmed below
     const double p = J.sp[pos];
     double qmax;  // largest squared distance at which the key stays <= cut
     if (KIND == KIND_VORONOI)
@@ -940,8 +941,10 @@ __device__ inline bool lattice_reach(const NdDev& J, const NdConst& C, int64_t p
             double img[DIM], lq, uq;
             lattice_image<DIM>(J, pos, k, img);
             box_q<DIM>(G, img, lq, uq);
-            if (key_of_q<KIND>(lq, p, C) <= cut + C.M) {
+            const double kq = key_of_q<KIND>(lq, p, C);
+            if (kq <= cut + C.M) {
                 any = true;
+                klow = klow == -__builtin_inf() ? kq : fmin(klow, kq);
 #pragma unroll
                 for (int i = 0; i < DIM; ++i) {
                     nlo[i] = fmin(nlo[i], k[i]);
@@ -972,6 +975,107 @@ __device__ inline bool lattice_reach(const NdDev& J, const NdConst& C, int64_t p
     for (int i = 0; i < DIM; ++i)
         klo[i] = lo[i];
     return true;
+}
+
+// One round of the search for general periods (the orthogonal search
+// inlines the same steps): the bins of box B that are not in P (when
+// `grown`) go in batches of NDT; their sites' sorted positions are listed in
+// LDS, one thread per site takes the site's upper bound over the tile, UB and
+// a site attaining it are reduced, and the sites that can come within
+// UB + M are staged right away with their lower bound (and, for general
+// periods, their box of translations).  UB only decreases, so the final cut
+// is applied to the staged sites afterwards.  More than ND_CAP staged sets
+// S.sovf.
+template <int KIND, int DIM, bool LAT>
+__device__ inline void search_round(const NdDev& J, const NdConst& C, const NdTile<DIM>& G, NdLds<DIM, LAT>& S,
+                                    const NdBox& B, const NdBox& P, bool grown, double& UB, int& ubpos)
+{
+    const int tid = threadIdx.x;
+    const int nbox = (int)B.count;
+    for (int jb = 0; jb < nbox; jb += NDT) {
+        const int j = jb + tid;
+        int s0 = 0, n = 0;
+        if (j < nbox) {
+            bool in_prev;
+            const int lin = box_bin32<DIM>(J, B, j, P, grown, in_prev);
+            if (!in_prev) {
+                s0 = J.bin_start[lin];
+                n = J.bin_start[lin + 1] - s0;
+            }
+        }
+        int total;
+        const int pre = block_excl_scan(n, total, S);
+        for (int w0 = 0; w0 < total; w0 += SLOTCAP) {
+            const int k0 = max(0, w0 - pre), k1 = min(n, w0 + SLOTCAP - pre);
+            for (int k = k0; k < k1; ++k)
+                S.slot[pre + k - w0] = s0 + k;
+            __syncthreads();
+            const int wn = min(SLOTCAP, total - w0);
+            double kls[SLOTCAP / NDT];
+            int ps[SLOTCAP / NDT];
+            double my = __builtin_inf();
+            int mypos = -1;
+#pragma unroll
+            for (int r = 0; r < SLOTCAP / NDT; ++r) {
+                const int i = tid + r * NDT;
+                kls[r] = __builtin_inf();
+                ps[r] = -1;
+                if (i < wn) {
+                    const int pos = S.slot[i];
+                    double ku;
+                    if (LAT) {
+                        ku = lattice_upper<KIND, DIM>(J, C, pos, G);
+                    } else {
+                        double kl;
+                        site_bounds<KIND, DIM>(J, C, pos, G, kl, ku);
+                        kls[r] = kl;
+                    }
+                    ps[r] = pos;
+                    if (ku < my) {
+                        my = ku;
+                        mypos = pos;
+                    }
+                }
+            }
+            int at;
+            const double m = block_argmin(my, mypos, S, at);
+            if (m < UB) {
+                UB = m;
+                ubpos = at;
+            }
+            const double cutr = UB + C.M;
+#pragma unroll
+            for (int r = 0; r < SLOTCAP / NDT; ++r) {
+                if (ps[r] < 0)
+                    continue;
+                const int64_t pos = ps[r];
+                double klo[DIM], klw = kls[r];
+                int kn[DIM];
+                const bool keep = LAT ? lattice_reach<KIND, DIM>(J, C, pos, G, cutr, klo, kn, klw) : klw <= cutr;
+                if (keep) {
+                    const int slot = atomicAdd(&S.count, 1);
+                    if (slot < ND_CAP) {
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a)
+                            S.c[a][slot] = J.sc[pos * DIM + a];
+                        if (LAT) {
+#pragma unroll
+                            for (int a = 0; a < DIM; ++a) {
+                                S.klo[LAT ? a : 0][LAT ? slot : 0] = klo[a];
+                                S.kn[LAT ? a : 0][LAT ? slot : 0] = kn[a];
+                            }
+                        }
+                        S.p[slot] = J.sp[pos];
+                        S.idx[slot] = J.sidx[pos];
+                        S.kl[slot] = klw;
+                    } else {
+                        S.sovf = 1;
+                    }
+                }
+            }
+            __syncthreads();  // the slot list is rewritten next
+        }
+    }
 }
 
 template <int KIND, int DIM, bool LAT>
@@ -1136,29 +1240,12 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                 int r = 0;
                 B = ring_box<DIM>(J, bl, bh, 0);
                 P = B;
+                if (tid == 0) {
+                    S.count = 0;
+                    S.sovf = 0;
+                }
                 for (;;) {
-                    double my = __builtin_inf();
-                    int mypos = -1;
-                    for (int64_t j = tid; j < B.count; j += NDT) {
-                        bool in_prev;
-                        const int64_t lin = box_bin<DIM>(J, B, j, P, r > 0, in_prev);
-                        if (in_prev)
-                            continue;
-                        const int s1 = J.bin_start[lin + 1];
-                        for (int s = J.bin_start[lin]; s < s1; ++s) {
-                            const double u = lattice_upper<KIND, DIM>(J, C, s, G);
-                            if (u < my) {
-                                my = u;
-                                mypos = s;
-                            }
-                        }
-                    }
-                    int at;
-                    const double m = block_argmin(my, mypos, S, at);
-                    if (m < UB) {
-                        UB = m;
-                        ubpos = at;
-                    }
+                    search_round<KIND, DIM, LAT>(J, C, G, S, B, P, r > 0, UB, ubpos);
                     const double g = ring_gap<DIM>(J, B, G);
                     if (g == __builtin_inf())
                         break;
@@ -1209,7 +1296,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                         for (int w0 = 0; w0 < total; w0 += SLOTCAP) {
                             const int k0 = max(0, w0 - pre), k1 = min(n, w0 + SLOTCAP - pre);
                             for (int k = k0; k < k1; ++k)
-                                S.slot[LAT ? 0 : pre + k - w0] = s0 + k;
+                                S.slot[pre + k - w0] = s0 + k;
                             __syncthreads();
                             const int wn = min(SLOTCAP, total - w0);
                             double kls[SLOTCAP / NDT];
@@ -1222,7 +1309,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                                 kls[r] = __builtin_inf();
                                 ps[r] = -1;
                                 if (i < wn) {
-                                    const int pos = S.slot[LAT ? 0 : i];
+                                    const int pos = S.slot[i];
                                     double kl, ku;
                                     site_bounds<KIND, DIM>(J, C, pos, G, kl, ku);
                                     kls[r] = kl;
@@ -1251,7 +1338,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                                             S.c[a][slot] = J.sc[pos * DIM + a];
                                         S.p[slot] = J.sp[pos];
                                         S.idx[slot] = J.sidx[pos];
-                                        S.kl[LAT ? 0 : slot] = kls[r];
+                                        S.kl[slot] = kls[r];
                                     } else {
                                         S.sovf = 1;
                                     }
@@ -1288,7 +1375,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             // 2. stage the candidates (general periods, or an orthogonal search
             //    that staged more than ND_CAP) and take the lexicographic minimum
             const double cut = UB + C.M;
-            const bool staged = !LAT && !S.sovf;  // uniform: read after the search's last barrier
+            const bool staged = !S.sovf;  // uniform: read after the search's last barrier
             __syncthreads();
             if (!staged && tid == 0)
                 S.count = 0;
@@ -1310,7 +1397,8 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                         double klo[DIM];
                         int kn[DIM];
                         if (LAT) {
-                            keep = lattice_reach<KIND, DIM>(J, C, s, G, cut, klo, kn);
+                            double klw;
+                            keep = lattice_reach<KIND, DIM>(J, C, s, G, cut, klo, kn, klw);
                         } else {
                             double kl, ku;
                             site_bounds<KIND, DIM>(J, C, s, G, kl, ku);
