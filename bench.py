@@ -21,7 +21,7 @@ in HBM.  The line printed at the end also carries
     configurations, the device labels of every timed configuration checked
     against the oracle at sampled voxels, and every 125th served job's labels
     (checksums) against the oracle's;
-  - general_path (with --nd): the general-dimension kernel on a 4D Voronoi
+  - general_path (unless --no-nd): the general-dimension kernel on a 4D Voronoi
     diagram, 64^4 voxels and 16,384 sites, and on a 3D Voronoi diagram of
     20,000 sites in a triclinic periodic cell (128^3 voxels);
   - serving: the request stream replayed through the continuous-batching
@@ -448,7 +448,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream replay")
     ap.add_argument("--no-others", action="store_true", help="time only --config (not M1-M4)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner run on the clustered class")
-    ap.add_argument("--nd", action="store_true", help="also time the general-dimension kernel (4D)")
+    ap.add_argument("--nd", action="store_true", help="(default) time the general-dimension kernel")
+    ap.add_argument("--no-nd", action="store_true", help="skip the general-dimension kernel (4D, triclinic)")
     ap.add_argument("--serving-jobs", type=int, default=2000,
                     help="request-stream length (the stream of 2,000 seeded jobs by default)")
     ap.add_argument("--serving-scale", type=float, default=1.0,
@@ -549,8 +550,8 @@ def main():
         log("autotuner on the clustered class")
         tuned = autotune_clustered(log)
         out["autotune"] = {k: v for k, v in tuned.items() if not k.startswith("_")}
-    if args.nd:
-        log("general-dimension kernel (4D)")
+    if not args.no_nd:
+        log("general-dimension kernel (4D, triclinic)")
         g = general_path(ctx, max(args.steps // 4, 2), 1)
         nd_labels = g.pop("labels")
         lat_labels = g.pop("lattice_labels")
@@ -577,7 +578,7 @@ def main():
         if keep:
             log("CPU oracle on a sample of the served jobs")
             out["cpu_baseline"]["serving_sampled_parity"] = serving_sampled_parity(keep)
-        if args.nd:
+        if not args.no_nd:
             out["cpu_baseline"]["general_path_sampled_parity"] = nd_sampled_parity(nd_labels, lat_labels)
     ctx.close()
     print(json.dumps(out), flush=True)
