@@ -771,24 +771,22 @@ __device__ inline double nd_key(const NdDev& J, const NdLds<DIM, LAT>& S, int k,
     return nd_key_q<KIND>(J, q, S.p[k]);
 }
 
-// Evaluates the staged candidates [0, count) at the thread's voxel x and,
-// when `two`, at its second voxel, which differs from x on axis 0 only
-// (orthogonal periods: x1[0]; general periods: x1 in full).  With orthogonal
-// periods the terms of axes 1 .. DIM-1 are the same for both voxels and are
-// summed once, in the order of the definition.
-template <int KIND, int DIM, bool LAT>
+// Evaluates the staged candidates [0, count) at the thread's VPT voxels
+// (orthogonal periods: voxel j is x moved by j * tx0 voxels along axis 0,
+// with axis-0 coordinate x0s[j]; general periods: one voxel, x).  With
+// orthogonal periods the terms of axes 1 .. DIM-1 are the same for every
+// voxel of the thread and are summed once, in the order of the definition.
+template <int KIND, int DIM, bool LAT, int VPT>
 __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int count, const double* x,
-                                   const double* x1, bool two, double& best, int& blab, double& best1, int& blab1)
+                                   const double* x0s, double* best, int* blab)
 {
     for (int k = 0; k < count; ++k) {
         if (S.dead[k])  // the same for every thread
             continue;
         const int id = S.idx[k];
-        double key, key1 = 0.0;
+        double key[VPT];
         if (LAT) {
-            key = nd_key<KIND, DIM, LAT>(J, S, k, x);
-            if (two)
-                key1 = nd_key<KIND, DIM, LAT>(J, S, k, x1);
+            key[0] = nd_key<KIND, DIM, LAT>(J, S, k, x);
         } else {
             double T = 0.0;
 #pragma unroll
@@ -799,24 +797,20 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
                 T = a == 1 ? e * e : T + e * e;
             }
             const double p = S.p[k];
-            double e = S.c[0][k] - x[0];
-            if (J.bc)
-                e = e >= J.H[0] ? e - J.L[0] : (e < -J.H[0] ? e + J.L[0] : e);
-            key = nd_key_q<KIND>(J, DIM > 1 ? e * e + T : e * e, p);
-            if (two) {
-                double e1 = S.c[0][k] - x1[0];
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                double e = S.c[0][k] - x0s[j];
                 if (J.bc)
-                    e1 = e1 >= J.H[0] ? e1 - J.L[0] : (e1 < -J.H[0] ? e1 + J.L[0] : e1);
-                key1 = nd_key_q<KIND>(J, DIM > 1 ? e1 * e1 + T : e1 * e1, p);
+                    e = e >= J.H[0] ? e - J.L[0] : (e < -J.H[0] ? e + J.L[0] : e);
+                key[j] = nd_key_q<KIND>(J, DIM > 1 ? e * e + T : e * e, p);
             }
         }
-        if (key < best || (key == best && id < blab)) {
-            best = key;
-            blab = id;
-        }
-        if (two && (key1 < best1 || (key1 == best1 && id < blab1))) {
-            best1 = key1;
-            blab1 = id;
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            if (key[j] < best[j] || (key[j] == best[j] && id < blab[j])) {
+                best[j] = key[j];
+                blab[j] = id;
+            }
         }
     }
 }
@@ -839,14 +833,13 @@ struct NdTab {
     double bx;      // the voxel coordinate of its row
 };
 
-template <int KIND, int DIM, bool LAT>
+template <int KIND, int DIM, bool LAT, int VPT>
 __device__ inline void nd_eval_round(const NdDev& J, NdLds<DIM, LAT>& S, int cnt, const NdTab& tb, int tx0,
-                                     const double* x, const double* x1, bool two, bool live_any, double& best,
-                                     int& blab, double& best1, int& blab1)
+                                     const double* x, const double* x0s, bool live_any, double* best, int* blab)
 {
     if (LAT || DIM < 2 || !tb.on) {
         if (live_any && cnt > 0)
-            nd_evaluate<KIND, DIM, LAT>(J, S, cnt, x, x1, two, best, blab, best1, blab1);
+            nd_evaluate<KIND, DIM, LAT, VPT>(J, S, cnt, x, x0s, best, blab);
         return;
     }
     const int W = tb.W;
@@ -875,16 +868,12 @@ __device__ inline void nd_eval_round(const NdDev& J, NdLds<DIM, LAT>& S, int cnt
                     T = T + t[tb.row[a]];
                 const double p = S.p[g];
                 const int id = S.idx[g];
-                const double key = nd_key_q<KIND>(J, t[tb.row[0]] + T, p);
-                if (key < best || (key == best && id < blab)) {
-                    best = key;
-                    blab = id;
-                }
-                if (two) {
-                    const double key1 = nd_key_q<KIND>(J, t[tb.row[0] + tx0] + T, p);
-                    if (key1 < best1 || (key1 == best1 && id < blab1)) {
-                        best1 = key1;
-                        blab1 = id;
+#pragma unroll
+                for (int j = 0; j < VPT; ++j) {
+                    const double key = nd_key_q<KIND>(J, t[tb.row[0] + j * tx0] + T, p);
+                    if (key < best[j] || (key == best[j] && id < blab[j])) {
+                        best[j] = key;
+                        blab[j] = id;
                     }
                 }
             }
@@ -1078,7 +1067,7 @@ __device__ inline void search_round(const NdDev& J, const NdConst& C, const NdTi
     }
 }
 
-template <int KIND, int DIM, bool LAT>
+template <int KIND, int DIM, bool LAT, int VPT>
 __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
 {
     __shared__ NdLds<DIM, LAT> S;
@@ -1115,11 +1104,13 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
         NdTile<DIM> G0;
         int64_t rem = t;
         int l = tid;
-        // threads along axis 0; with two voxels per thread the second is tx0
-        // voxels further along axis 0
-        const int tx0 = J.T[0] / J.vpt;
-        const bool two = !LAT && J.vpt > 1;  // general periods: one voxel per thread
-        bool live = true, live1 = two;
+        // threads along axis 0; with VPT voxels per thread (orthogonal
+        // periods only) voxel j is j * tx0 voxels further along axis 0
+        const int tx0 = J.T[0] / VPT;
+        bool live = true, livev[VPT];
+#pragma unroll
+        for (int j = 0; j < VPT; ++j)
+            livev[j] = true;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             const int64_t tc = take_digit(rem, J.nt[a]);
@@ -1130,7 +1121,9 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             l /= ta;
             vi[a] = v0[a] + off;
             live = live && vi[a] <= ve[a];
-            live1 = live1 && vi[a] + (a == 0 ? tx0 : 0) <= ve[a];
+#pragma unroll
+            for (int j = 0; j < VPT; ++j)
+                livev[j] = livev[j] && vi[a] + (a == 0 ? j * tx0 : 0) <= ve[a];
             if (LAT) {
                 G0.lo[a] = ((double)v0[a] + 0.5) / (double)J.n[a];
                 G0.hi[a] = ((double)ve[a] + 0.5) / (double)J.n[a];
@@ -1144,22 +1137,19 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             bl[a] = min(max(b0, 0), J.nb[a] - 1);
             bh[a] = min(max(b1, 0), J.nb[a] - 1);
         }
-        double x1[LAT ? DIM : 1];
-        if (!LAT)
-            x1[0] = ((double)(vi[0] + tx0) + 0.5) * J.h[0];
+        double x0s[VPT];  // axis-0 coordinates of the thread's voxels (orthogonal periods)
+#pragma unroll
+        for (int j = 0; j < VPT; ++j)
+            x0s[j] = LAT ? 0.0 : ((double)(vi[0] + j * tx0) + 0.5) * J.h[0];
         if (LAT) {
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                // the voxel centres, summed as the definition sums them
+                // the voxel centre, summed as the definition sums it
                 double acc = ((double)vi[0] + 0.5) * J.hv[0][a];
-                double acc1 = ((double)(vi[0] + tx0) + 0.5) * J.hv[0][a];
 #pragma unroll
-                for (int i = 1; i < DIM; ++i) {
+                for (int i = 1; i < DIM; ++i)
                     acc = acc + ((double)vi[i] + 0.5) * J.hv[i][a];
-                    acc1 = acc1 + ((double)vi[i] + 0.5) * J.hv[i][a];
-                }
                 x[a] = acc;
-                x1[LAT ? a : 0] = acc1;
                 // bounding box of the tile's centres, term by term
                 double b0 = 0.0, b1 = 0.0;
 #pragma unroll
@@ -1174,7 +1164,12 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             }
         }
         live = live && l == 0;
-        live1 = live1 && l == 0;
+        bool live_any = false;
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            livev[j] = livev[j] && l == 0;
+            live_any = live_any || livev[j];
+        }
         // general periods: the tile's geometry lives in LDS (read where the
         // bounds need it) rather than in registers
         if (LAT) {
@@ -1225,8 +1220,13 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                 tb.bx = ((double)(va + i) + 0.5) * ha;
             }
         }
-        double best = __builtin_inf(), best1 = __builtin_inf();
-        int blab = 0x7fffffff, blab1 = 0x7fffffff;
+        double best[VPT];
+        int blab[VPT];
+#pragma unroll
+        for (int j = 0; j < VPT; ++j) {
+            best[j] = __builtin_inf();
+            blab[j] = 0x7fffffff;
+        }
         if (!bad) {
             // 1. grow the box of visited bins until the sites beyond it
             //    provably lose; their keys are at least gap^2, gap^2 - max w
@@ -1425,8 +1425,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                     __syncthreads();  // every thread has read the count before the next appends
                     if (cnt > ND_CAP - NDT) {
                         mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, false, cut, v0, ve);
-                        nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab,
-                                                      best1, blab1);
+                        nd_eval_round<KIND, DIM, LAT, VPT>(J, S, cnt, tb, tx0, x, x0s, live_any, best, blab);
                         __syncthreads();
                         if (tid == 0)
                             S.count = 0;
@@ -1436,40 +1435,49 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
             }
             const int cnt = S.count;
             mark_beaten<KIND, DIM, LAT>(J, C, G, S, cnt, ubpos, staged, cut, v0, ve);
-            nd_eval_round<KIND, DIM, LAT>(J, S, cnt, tb, tx0, x, x1, two, live || live1, best, blab, best1,
-                                          blab1);
+            nd_eval_round<KIND, DIM, LAT, VPT>(J, S, cnt, tb, tx0, x, x0s, live_any, best, blab);
             __syncthreads();
         }
-        if (live || live1) {
+        if (live_any) {
             int64_t lin = 0, stride = 1;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) {
                 lin += vi[a] * stride;
                 stride *= J.n[a];
             }
-            if (live) {
-                J.labels[lin] = bad ? -1 : blab;
-                if (J.keys)
-                    J.keys[lin] = bad ? __builtin_nan("") : best;
-            }
-            if (live1) {
-                J.labels[lin + tx0] = bad ? -1 : blab1;
-                if (J.keys)
-                    J.keys[lin + tx0] = bad ? __builtin_nan("") : best1;
+#pragma unroll
+            for (int j = 0; j < VPT; ++j) {
+                if (livev[j]) {
+                    J.labels[lin + j * tx0] = bad ? -1 : blab[j];
+                    if (J.keys)
+                        J.keys[lin + j * tx0] = bad ? __builtin_nan("") : best[j];
+                }
             }
         }
     }
+}
+
+// Two voxels per thread only with orthogonal periods in 2 to 4 axes (the
+// plan never asks for them elsewhere), so only those kernels are built.
+template <int KIND, int DIM, bool LAT>
+void launch_nd_kind(const NdDev& J, unsigned g, hipStream_t s)
+{
+    constexpr bool multi = !LAT && DIM >= 2 && DIM <= 4;
+    if (multi && J.vpt == 2)
+        k_nd_label<KIND, DIM, LAT, multi ? 2 : 1><<<g, NDT, 0, s>>>(J);
+    else
+        k_nd_label<KIND, DIM, LAT, 1><<<g, NDT, 0, s>>>(J);
 }
 
 template <int DIM, bool LAT>
 void launch_nd_dim(const NdDev& J, unsigned g, hipStream_t s)
 {
     if (J.kind == KIND_VORONOI)
-        k_nd_label<KIND_VORONOI, DIM, LAT><<<g, NDT, 0, s>>>(J);
+        launch_nd_kind<KIND_VORONOI, DIM, LAT>(J, g, s);
     else if (J.kind == KIND_LAGUERRE)
-        k_nd_label<KIND_LAGUERRE, DIM, LAT><<<g, NDT, 0, s>>>(J);
+        launch_nd_kind<KIND_LAGUERRE, DIM, LAT>(J, g, s);
     else
-        k_nd_label<KIND_JM, DIM, LAT><<<g, NDT, 0, s>>>(J);
+        launch_nd_kind<KIND_JM, DIM, LAT>(J, g, s);
 }
 
 template <bool LAT>
@@ -1505,6 +1513,9 @@ hipError_t launch_nd_bin_scatter(const NdDev& J, hipStream_t s)
 
 hipError_t launch_nd_label(const NdDev& J, hipStream_t s)
 {
+    const bool multi_ok = !J.lattice && J.ndim >= 2 && J.ndim <= 4;
+    if (!(J.vpt == 1 || (multi_ok && J.vpt == 2)) || J.T[0] % J.vpt != 0)
+        return hipErrorInvalidValue;
     const unsigned g = (unsigned)(J.ntiles < kNdGrid ? J.ntiles : kNdGrid);
     return J.lattice ? launch_nd_lat<true>(J, g, s) : launch_nd_lat<false>(J, g, s);
 }
