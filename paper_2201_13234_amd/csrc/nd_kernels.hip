@@ -205,6 +205,8 @@ template <int D, bool LAT>
 struct NdLds {
     double c[D][ND_CAP];
     double klo[LAT ? D : 1][LAT ? ND_CAP : 1];
+    double off[LAT ? D : 1][LAT ? ND_CAP : 1];  // single-translation candidates: k_0 L_0a + k_1 L_1a + ...
+    int32_t sgl[LAT ? ND_CAP : 1];              // the candidate's box holds one translation
     int32_t kn[LAT ? D : 1][LAT ? ND_CAP : 1];
     double p[ND_CAP];
     int32_t idx[ND_CAP];
@@ -704,6 +706,30 @@ __device__ inline double nd_key_q(const NdDev& J, double q, double p)
     return J.jm_div ? p + key_sqrt(q) / J.growth : p + key_sqrt(q) * J.rgrowth;
 }
 
+// General periods: for a staged candidate whose box holds one translation k,
+// the offset k_0 L_0a + k_1 L_1a + ... of every axis, formed as nd_key forms
+// it (same operations, same order), so that the evaluation adds it instead
+// of forming it at every voxel.
+template <int DIM, bool LAT>
+__device__ inline void lattice_offsets(const NdDev& J, NdLds<DIM, LAT>& S, int slot, const double* klo, const int* kn)
+{
+    if (!LAT)
+        return;
+    bool one = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        one = one && kn[a] == 1;
+    S.sgl[LAT ? slot : 0] = one;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double o = klo[0] * J.P[0][a];
+#pragma unroll
+        for (int i = 1; i < DIM; ++i)
+            o = o + klo[i] * J.P[i][a];
+        S.off[LAT ? a : 0][LAT ? slot : 0] = o;
+    }
+}
+
 template <int KIND, int DIM, bool LAT>
 __device__ inline double nd_key(const NdDev& J, const NdLds<DIM, LAT>& S, int k, const double* x)
 {
@@ -786,7 +812,24 @@ __device__ inline void nd_evaluate(const NdDev& J, const NdLds<DIM, LAT>& S, int
         const int id = S.idx[k];
         double key[VPT];
         if (LAT) {
-            key[0] = nd_key<KIND, DIM, LAT>(J, S, k, x);
+            if (S.sgl[LAT ? k : 0]) {
+                // one translation: d_a = (s_a - x_a) + offset_a, folded as in nd_key
+                double d[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a)
+                    d[a] = (S.c[a][k] - x[a]) + S.off[LAT ? a : 0][LAT ? k : 0];
+                double q = d[0] * d[0];
+                if (DIM > 1) {
+                    double T = d[1] * d[1];
+#pragma unroll
+                    for (int a = 2; a < DIM; ++a)
+                        T = T + d[a] * d[a];
+                    q = q + T;
+                }
+                key[0] = nd_key_q<KIND>(J, q, S.p[k]);
+            } else {
+                key[0] = nd_key<KIND, DIM, LAT>(J, S, k, x);
+            }
         } else {
             double T = 0.0;
 #pragma unroll
@@ -1053,6 +1096,7 @@ __device__ inline void search_round(const NdDev& J, const NdConst& C, const NdTi
                                 S.klo[LAT ? a : 0][LAT ? slot : 0] = klo[a];
                                 S.kn[LAT ? a : 0][LAT ? slot : 0] = kn[a];
                             }
+                            lattice_offsets<DIM, LAT>(J, S, slot, klo, kn);
                         }
                         S.p[slot] = J.sp[pos];
                         S.idx[slot] = J.sidx[pos];
@@ -1415,6 +1459,7 @@ __global__ __launch_bounds__(NDT, 4) void k_nd_label(NdDev J)
                                     S.klo[LAT ? a : 0][LAT ? slot : 0] = klo[a];
                                     S.kn[LAT ? a : 0][LAT ? slot : 0] = kn[a];
                                 }
+                                lattice_offsets<DIM, LAT>(J, S, slot, klo, kn);
                             }
                             S.p[slot] = J.sp[s];
                             S.idx[slot] = J.sidx[s];
