@@ -170,9 +170,9 @@ vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_
 vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_dev, void* stream);
 
 /* Many diagrams, of any sizes, kinds and boundaries: one segmented binning
- * pass over all of them, then one persistent labelling launch per group of
- * jobs that share kind, dimension and tile configuration (each group runs a
- * kernel compiled for it).  status_dev (nullable): njobs device int32, one
+ * pass over all of them, then one labelling launch per group of jobs that
+ * share kind, dimension and tile configuration (each group runs a kernel
+ * compiled for it, one workgroup per region of the group's jobs).  status_dev (nullable): njobs device int32, one
  * per job, in the order of `jobs`.  A job with bad sites gets -1 labels and
  * VT_ERR_INPUT without affecting the others.  Johnson-Mehl jobs first drop
  * from their bins the sites that provably never win (a site s whose
@@ -188,8 +188,8 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs,
 vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out,
                         int32_t* status_dev, void* stream);
 
-/* Labels the jobs behind n resident bin objects (one persistent launch per
- * group, as for vt_tessellate_batch), writing each into the labels buffer
+/* Labels the jobs behind n resident bin objects (one launch per group, as
+ * for vt_tessellate_batch), writing each into the labels buffer
  * given at vt_bins_build.  status_dev
  * (nullable): n device int32 (VT_ERR_INPUT for jobs whose binning flagged bad
  * input, else VT_OK). */

@@ -1,4 +1,4 @@
-// label_batch.hip -- persistent labelling kernels over a batch of diagrams.
+// label_batch.hip -- labelling kernels over a batch of diagrams.
 //
 // The host sorts a batch into groups of one kind, dimension and tile
 // configuration (contiguous in the device job table) and launches one kernel

@@ -127,8 +127,8 @@ class GpuExecutor(Executor):
     batch can be uploaded and binned while the previous one is still
     labelling.  Two modes:
       resident_bins=False  each launch is one vt_tessellate_batch call:
-                           segmented binning of the batch plus one persistent
-                           labelling launch per kind/shape group (a launch of
+                           segmented binning of the batch plus one labelling
+                           launch per kind/shape group (a launch of
                            a single request is a plain vt_tessellate call);
       resident_bins=True   every request is binned on arrival (vt_bins_build,
                            bins stay on the device) and a launch is one

@@ -1,4 +1,4 @@
-"""Batched persistent launches, resident bins, the serving loop and the
+"""Batched launches, resident bins, the serving loop and the
 autotuner: every job's labels must equal the same job run alone and the
 oracle, bit for bit."""
 import os
