@@ -1,6 +1,6 @@
 // label_core.h -- device code of the labelling kernels, shared by the
-// single-diagram kernels (label_kernel.hip) and the batch kernels
-// (label_batch.hip).  What is computed and how is described at the
+// single-diagram kernels (label_kernel.hip) and the persistent batch
+// kernels (label_batch.hip).  What is computed and how is described at the
 // top of label_kernel.hip.
 #pragma once
 
