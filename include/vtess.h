@@ -135,9 +135,12 @@ void vt_destroy(vt_ctx* ctx);
  * loops.  VT_ERR_NOMEM if the allocation fails. */
 vt_status vt_reserve(vt_ctx* ctx, size_t bytes);
 
-/* Plain single-diagram path: bins the sites (counting sort into a uniform
- * bin grid; for Johnson-Mehl also drops the sites that never win, as for
- * vt_tessellate_batch) and labels every voxel.  status_dev (nullable): one
+/* Plain single-diagram path: labels every voxel of job with the lowest
+ * index of the sites that minimise its key (the problem of Sec. 3, keys of
+ * Sec. 2 and App. A as above; the ineffective Johnson-Mehl sites of Sec. 3.3
+ * are dropped first, labels unchanged).  Bins the sites (counting sort into a
+ * uniform bin grid), then labels voxel tiles with bound-based pruning and an
+ * exact evaluation of the survivors.  status_dev (nullable): one
  * device int32, set to VT_OK or VT_ERR_INPUT by the kernels.  May grow the
  * context's scratch, which synchronises the device. */
 vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
@@ -169,8 +172,8 @@ vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_
  * (n_a in [1, 2^30], at most 2^40 voxels, else VT_ERR_INVALID). */
 vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_dev, void* stream);
 
-/* Many diagrams, of any sizes, kinds and boundaries: one segmented binning
- * pass over all of them, then one labelling launch per group of jobs that
+/* Many diagrams (each the problem of Sec. 3, as for vt_tessellate), of any
+ * sizes, kinds and boundaries: one segmented binning pass over all of them, then one labelling launch per group of jobs that
  * share kind, dimension and tile configuration (each group runs a kernel
  * compiled for it, one workgroup per region of the group's jobs).  status_dev (nullable): njobs device int32, one
  * per job, in the order of `jobs`.  A job with bad sites gets -1 labels and
