@@ -15,7 +15,6 @@ constexpr int NT = NW * WAVE;  // threads per workgroup
 constexpr int CAP_R = 576;     // region candidate capacity (LDS)
 constexpr int CAP_S = 64;      // tile candidate capacity (LDS, per wavefront)
 constexpr int CAP_F = 64;      // fallback per-tile capacity (LDS, per wavefront)
-constexpr int R_DOM = 8;       // dominance references: the candidates with the smallest upper bounds
 
 // flags: wrap code per axis in bits 2a..2a+1 (0 none, 1 subtract L, 2 add L),
 // bit 6 = some axis needs a per-voxel minimum-image test.
@@ -25,6 +24,11 @@ constexpr int FL_GENERIC = 64;
 constexpr int FL_SQRT_FAST = 256;
 
 enum { KV = 0, KL = 1, KJM = 2, KJD = 3 };  // Johnson-Mehl: multiply by exact 1/v, or divide
+
+// Dominance references (the candidates with the smallest upper bounds): six
+// for Voronoi, four for Laguerre and Johnson-Mehl (measured against 4 to 12;
+// each reference costs a test per candidate).
+constexpr int r_dom(int kind) { return kind == KV ? 6 : 4; }
 
 // A tile list entry refers to its site record in the region list through the
 // position stored above the flags (cm.y >> 8).
@@ -642,8 +646,8 @@ __device__ inline unsigned ub_key(double u, int pos)
 }
 
 // Drops dominated entries of a wavefront's list (one entry per lane, nc <= 64),
-// then sorts the rest by site index.  Each entry is tested against the R_DOM
-// entries with the smallest upper bounds (the sites nearest the tile, which
+// then sorts the rest by site index.  Each entry is tested against the
+// r_dom(KIND) entries with the smallest upper bounds (the sites nearest the tile, which
 // beat far sites on the whole tile); a dropped entry is always beaten by a
 // listed site, so the winner of every voxel stays.  Returns the new count.
 // IND false: the list holds the site records (cs, permuted with the list);
@@ -667,7 +671,7 @@ __device__ inline int prune_and_sort(const double4* base, double4* cs, double4* 
             const uint4 k4 = *(const uint4*)(ck + t);
             ru += (int)(k4.x < key) + (int)(k4.y < key) + (int)(k4.z < key) + (int)(k4.w < key);
         }
-        const unsigned long long refs = __ballot(mine && ru < R_DOM);
+        const unsigned long long refs = __ballot(mine && ru < r_dom(KIND));
         keep = !dominated<KIND, DIM, IND>(base, cg, cm, cq, mine ? lane : 0, refs, C, B) && mine;
     }
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
