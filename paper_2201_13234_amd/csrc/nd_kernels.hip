@@ -222,21 +222,6 @@ struct NdLds {
     int32_t ired[NDT / WAVE];
 };
 
-template <class L>
-__device__ inline double block_min(double v, L& S)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmin(v, __shfl_xor(v, o));
-    __syncthreads();
-    if ((threadIdx.x & (WAVE - 1)) == 0)
-        S.red[threadIdx.x / WAVE] = v;
-    __syncthreads();
-    double r = S.red[0];
-    for (int w = 1; w < NDT / WAVE; ++w)
-        r = fmin(r, S.red[w]);
-    return r;
-}
-
 // Smallest v over the workgroup and a `pos` that attains it.
 template <class L>
 __device__ inline double block_argmin(double v, int pos, L& S, int& at)
