@@ -888,12 +888,16 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
         V = std::fabs(det);
     }
 
-    // Bins: side ~ 1.2 mean site spacings (V / N)^(1/d), or the bin factor
+    // Bins: side ~ 1.4 mean site spacings (V / N)^(1/d) with orthogonal
+    // periods (or none) in 2 to 4 axes, else 1.2, or the bin factor
     // vt_set_params forces; at most 2^20 per axis and about 4 N + 64 in total.
-    // 1.2 measured fastest or level from 2 to 6 axes and in a triclinic cell
-    // (4D 64^4: 2.04 -> 1.93 ms against one spacing; 5D 24^5, 8,000 sites:
-    // 4.34 -> 3.28 ms).
-    const double bin_factor = ctx && ctx->force_bin > 0.0 ? ctx->force_bin : 1.2;
+    // Measured against 1.0 to 1.6 with the balanced search: 1.4 is 6-8 %
+    // faster than 1.2 in 4D (64^4 Voronoi 1.04 -> 0.95 ms; Laguerre and
+    // Johnson-Mehl 48^4) and for 3D through the general kernel; 5D is best
+    // at 1.2 (1.62 against 1.73 ms), 6D and the triclinic cell are level.
+    const double bin_factor = ctx && ctx->force_bin > 0.0       ? ctx->force_bin
+                              : (!d->lattice && j->ndim >= 2 && j->ndim <= 4) ? 1.4
+                                                                              : 1.2;
     const double spacing = std::pow(V / (double)j->nsites, 1.0 / j->ndim) * bin_factor;
     int64_t nbins = 1;
     for (int a = 0; a < j->ndim; ++a) {
