@@ -142,7 +142,11 @@ vt_status vt_reserve(vt_ctx* ctx, size_t bytes);
  * uniform bin grid), then labels voxel tiles with bound-based pruning and an
  * exact evaluation of the survivors.  status_dev (nullable): one
  * device int32, set to VT_OK or VT_ERR_INPUT by the kernels.  May grow the
- * context's scratch, which synchronises the device. */
+ * context's scratch, which synchronises the device.  Calls on one context
+ * share its scratch (each call's kernels also clear words for the next call),
+ * so order them: one stream, or synchronise between streams.  A call captured
+ * into a graph clears its own words; its replays are valid while no later
+ * call has grown the context's scratch. */
 vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "vt_internal.h"
+#include "bin_internal.h"
 #include "nd_internal.h"
 #include "vtess.h"
 
@@ -99,6 +99,14 @@ struct vt_ctx {
     int force_margin = 0;      // Laguerre gather margin forced by the autotuner (0: none)
     bool skip_tune = false;    // plan without the tuning table (the autotuner's default rounds)
     std::vector<TuneEntry> tune;
+    // The plain path keeps two slots of zeroed scratch (bin counts, bounds,
+    // counters) at the start of the arena: a call uses one and its count
+    // kernel clears the other for the next call.  slot_clean[k]: bytes of
+    // slot k known to be zero (0 after any other use of the arena).  Calls
+    // captured into a graph use a third slot, which they clear themselves.
+    size_t slot_cap = 0;
+    size_t slot_clean[2] = {0, 0};
+    int slot_next = 0;
     // this device's copy of the static scratch (vt_tessellate_noalloc)
     void* noalloc = nullptr;
     // phase timing: three events per recorded call
@@ -330,6 +338,7 @@ vt_status ensure_scratch(vt_ctx* ctx, size_t bytes)
         return VT_OK;
     // Growing replaces memory that queued work may still use.
     VT_HIP(hipDeviceSynchronize());
+    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;
     if (ctx->arena)
         VT_HIP(hipFree(ctx->arena));
     ctx->arena = nullptr;
@@ -363,29 +372,50 @@ vt_status ensure_pinned(vt_ctx* ctx, size_t bytes)
     return VT_OK;
 }
 
-// Binning arrays of one job carved from `base` (device memory).
-struct SingleLayout {
-    size_t job, pbound, status, ovf_count, bin_count, bin_start, site_bin, site_rank, sites, sidx, partial,
-        ovf_list, total;
+// The words of one job that must start at zero: parameter bounds, the
+// count's status accumulator, the overflow count, the bin counts (padded
+// with zeros for the one-workgroup scan) and the flags of the multi-workgroup
+// scan.
+struct SlotLayout {
+    size_t pbound, sacc, ovf_count, bin_count, partial, bytes;
     int64_t partial_cap;
 };
 
-SingleLayout single_layout(const JobDev& d)
+SlotLayout slot_layout(const JobDev& d)
+{
+    SlotLayout Z;
+    Carver c;
+    Z.pbound = c.take<unsigned long long>(2);
+    Z.sacc = c.take<int32_t>(1, 4);
+    Z.ovf_count = c.take<int32_t>(1, 4);
+    Z.bin_count = c.take<int32_t>(vt::count_words(d.nbins));
+    Z.partial_cap = vt::scan_flags_needed((int64_t)d.nbins);
+    Z.partial = c.take<unsigned long long>(Z.partial_cap, 8);
+    Z.bytes = align_up(c.off, 256);
+    return Z;
+}
+
+// Binning arrays of one job carved from `base` (device memory): the job's
+// record, one or three slots of slot_bytes each for the words that start at
+// zero (slot_layout), then the rest.
+struct SingleLayout {
+    SlotLayout z;
+    size_t job, slot[3], status, bin_start, site_bin, site_rank, sites, sidx, ovf_list, total;
+};
+
+SingleLayout single_layout(const JobDev& d, size_t slot_bytes, int nslots)
 {
     SingleLayout L;
     Carver c;
-    // the job's record, written by the first binning kernel and read by the
-    // labelling kernels
+    L.z = slot_layout(d);
+    // written by the count kernel, read by the labelling kernels
     L.job = c.take<JobDev>(1);
-    // pbound, status, overflow count and bin counts are zeroed together
-    L.pbound = c.take<unsigned long long>(2);
+    for (int k = 0; k < 3; ++k)
+        L.slot[k] = k == 0 || nslots == 3 ? c.take<char>((int64_t)slot_bytes) : L.slot[0];
+    // the job's status when the caller gives no word of its own
     L.status = c.take<int32_t>(1, 4);
-    L.ovf_count = c.take<int32_t>(1, 4);
-    L.bin_count = c.take<int32_t>(d.nbins, 4);
-    // the scan's flag words, cleared together with the counts
-    L.partial_cap = vt::scan_flags_needed((int64_t)d.nbins);
-    L.partial = c.take<unsigned long long>(L.partial_cap, 8);
-    L.bin_start = c.take<int32_t>((int64_t)d.nbins + 1);
+    // (the one-workgroup scan writes whole rows: count_words(nbins) + 1 words)
+    L.bin_start = c.take<int32_t>(vt::count_words(d.nbins) + 1);
     L.site_bin = c.take<int32_t>(d.nsites);
     L.site_rank = c.take<int32_t>(d.nsites);
     L.sites = c.take<double4>(d.nsites);
@@ -395,23 +425,23 @@ SingleLayout single_layout(const JobDev& d)
     return L;
 }
 
-void bind_single(JobDev& d, char* base, const SingleLayout& L, int32_t* status_dev)
+void bind_single(JobDev& d, char* base, const SingleLayout& L, int slot, int32_t* status_dev)
 {
-    d.pbound = (unsigned long long*)(base + L.pbound);
+    char* z = base + L.slot[slot];
+    d.pbound = (unsigned long long*)(z + L.z.pbound);
     d.status = status_dev ? status_dev : (int32_t*)(base + L.status);
-    d.bin_count = (int32_t*)(base + L.bin_count);
+    d.bin_count = (int32_t*)(z + L.z.bin_count);
     d.bin_start = (int32_t*)(base + L.bin_start);
     d.site_bin = (int32_t*)(base + L.site_bin);
     d.site_rank = (int32_t*)(base + L.site_rank);
     d.sites = (double4*)(base + L.sites);
     d.sidx = (int32_t*)(base + L.sidx);
-    d.ovf_count = (int32_t*)(base + L.ovf_count);
+    d.ovf_count = (int32_t*)(z + L.z.ovf_count);
     d.ovf_list = (int32_t*)(base + L.ovf_list);
 }
 
-// Clears nwords words from zero_begin and the word *extra (if given), and
-// stores the job's record at job_dst (if given).
-__global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, JobDev job, JobDev* job_dst)
+// Clears nwords words from zero_begin and the word *extra (if given).
+__global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -419,36 +449,40 @@ __global__ void k_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, J
         zero_begin[k] = 0;
     if (i == 0 && extra)
         *extra = 0;
-    if (i == 0 && job_dst)
-        *job_dst = job;
 }
 
-hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, hipStream_t s,
-                          const JobDev* job = nullptr, JobDev* job_dst = nullptr)
+hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, hipStream_t s)
 {
     int64_t g = (nwords + 255) / 256;
     g = std::min<int64_t>(std::max<int64_t>(g, 1), 4096);
-    JobDev j;
-    if (job)
-        j = *job;
-    else
-        std::memset(&j, 0, sizeof j);
-    k_prepare<<<(unsigned)g, 256, 0, s>>>(zero_begin, nwords, extra, j, job ? job_dst : nullptr);
+    k_prepare<<<(unsigned)g, 256, 0, s>>>(zero_begin, nwords, extra);
     return hipGetLastError();
 }
 
-// Count, scan and scatter the sites of one job (its arrays already bound).
-vt_status bin_single(const JobDev& d, char* base, const SingleLayout& L, hipStream_t s)
+// Count, scan and scatter the sites of one job (its arrays bound to `slot`).
+// Unless `zeroed`, the slot is cleared first; with clear_other, the count
+// kernel clears the other slot (its first L.z.bytes) for the next call.
+// The count also stores the job's record and accumulates the input status in
+// the slot; the scatter publishes that status in *d.status.  Small bin grids
+// are scanned by one workgroup, larger ones by the multi-workgroup scan.
+vt_status bin_single(const JobDev& d, char* base, const SingleLayout& L, int slot, bool zeroed, bool clear_other,
+                     hipStream_t s)
 {
-    // pbound, internal status, bin counts and scan flags are contiguous from
-    // L.pbound.
-    const int64_t words = (int64_t)((L.partial - L.pbound) / 4) + 2 * L.partial_cap;
-    int32_t* extra = (d.status != (int32_t*)(base + L.status)) ? d.status : nullptr;
-    VT_HIP(launch_prepare((int32_t*)(base + L.pbound), words, extra, s, &d, (JobDev*)(base + L.job)));
-    VT_HIP(vt::launch_bin_count(d, nullptr, 1, nullptr, d.nsites, s));
-    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(base + L.partial), L.partial_cap,
-                           s));
-    VT_HIP(vt::launch_bin_scatter(d, nullptr, 1, nullptr, d.nsites, s));
+    char* z = base + L.slot[slot];
+    if (!zeroed)
+        VT_HIP(launch_prepare((int32_t*)z, (int64_t)(L.z.bytes / 4), nullptr, s));
+    vt::CountTail t;
+    t.status_acc = (int32_t*)(z + L.z.sacc);
+    t.job_dst = (JobDev*)(base + L.job);
+    t.clear = clear_other ? (int32_t*)(base + L.slot[slot ^ 1]) : nullptr;
+    t.clear_words = clear_other ? (int64_t)(L.z.bytes / 4) : 0;
+    VT_HIP(vt::launch_bin_count_single(d, t, s));
+    if (d.nbins <= vt::kSmallScanMax)
+        VT_HIP(vt::launch_scan_small(d.bin_count, d.bin_start, d.nbins, s));
+    else
+        VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(z + L.z.partial),
+                               L.z.partial_cap, s));
+    VT_HIP(vt::launch_bin_scatter_single(d, t.status_acc, s));
     if (d.kind == vt::KIND_JM)
         VT_HIP(vt::launch_jm_prune(d, nullptr, 1, nullptr, d.nsites, d.nbins, s));
     return VT_OK;
@@ -665,11 +699,28 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     if (st != VT_OK)
         return st;
     VT_HIP(hipSetDevice(ctx->device));
-    const SingleLayout L = single_layout(d);
+    const size_t zbytes = slot_layout(d).bytes;
+    if (zbytes > ctx->slot_cap) {
+        ctx->slot_cap = zbytes;
+        ctx->slot_clean[0] = ctx->slot_clean[1] = 0;
+    }
+    const SingleLayout L = single_layout(d, ctx->slot_cap, 3);
     if ((st = ensure_scratch(ctx, L.total)) != VT_OK)
         return st;
+    // A call captured into a graph may be replayed in any order with other
+    // calls: it takes the third slot and clears it itself.  (A stream whose
+    // capture state cannot be read is treated as capturing.)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    bool capturing = true;
+    if (hipStreamIsCapturing(s, &cap) == hipSuccess)
+        capturing = cap != hipStreamCaptureStatusNone;
+    else
+        (void)hipGetLastError();
+    const int slot = capturing ? 2 : ctx->slot_next;
+    const bool zeroed = !capturing && ctx->slot_clean[slot] >= zbytes;
+    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;  // until every launch below is queued
     char* base = (char*)ctx->arena;
-    bind_single(d, base, L, status_dev);
+    bind_single(d, base, L, slot, status_dev);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (ctx->profile) {
         while (ctx->prof_events.size() < ctx->prof_used + 4) {
@@ -682,7 +733,7 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
         ctx->prof_used += 4;
         VT_HIP(hipEventRecord(ev[0], s));
     }
-    if ((st = bin_single(d, base, L, s)) != VT_OK)
+    if ((st = bin_single(d, base, L, slot, zeroed, !capturing, s)) != VT_OK)
         return st;
     if (ev[1])
         VT_HIP(hipEventRecord(ev[1], s));
@@ -693,6 +744,10 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     VT_HIP(vt::launch_label_fallback(d, jd, s));
     if (ev[3])
         VT_HIP(hipEventRecord(ev[3], s));
+    if (!capturing) {
+        ctx->slot_clean[slot ^ 1] = zbytes;
+        ctx->slot_next = slot ^ 1;
+    }
     return VT_OK;
 }
 
@@ -707,7 +762,7 @@ vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_
     vt_status st = plan_job(ctx, job, &d);
     if (st != VT_OK)
         return st;
-    const SingleLayout L = single_layout(d);
+    const SingleLayout L = single_layout(d, slot_layout(d).bytes, 1);
     if (L.total > kNoallocBytes)
         return fail(VT_ERR_BUSY, "job needs " + std::to_string(L.total) +
                                      " bytes of scratch; vt_tessellate_noalloc has " +
@@ -716,8 +771,8 @@ vt_status vt_tessellate_noalloc(vt_ctx* ctx, const vt_job* job, int32_t* status_
     // The same kernels as vt_tessellate on the device's static scratch; the
     // first binning kernel clears the counters and bounds that start at zero.
     char* base = (char*)ctx->noalloc;
-    bind_single(d, base, L, status_dev);
-    if ((st = bin_single(d, base, L, s)) != VT_OK)
+    bind_single(d, base, L, 0, status_dev);
+    if ((st = bin_single(d, base, L, 0, false, false, s)) != VT_OK)
         return st;
     VT_HIP(vt::launch_label_single(d, (const JobDev*)(base + L.job), s));
     VT_HIP(vt::launch_label_fallback(d, (const JobDev*)(base + L.job), s));
@@ -1012,6 +1067,7 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     const size_t o_sidx = c.take<int32_t>(d.nsites);
     if ((st = ensure_scratch(ctx, align_up(c.off, 256))) != VT_OK)
         return st;
+    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;  // the arena's words are reused below
     char* base = (char*)ctx->arena;
     d.pbound = (unsigned long long*)(base + o_pbound);
     d.status = status_dev ? status_dev : (int32_t*)(base + o_status);
@@ -1128,6 +1184,7 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     vt_status st = ensure_scratch(ctx, align_up(c.off, 256));
     if (st != VT_OK)
         return st;
+    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;  // the arena's words are reused below
     char* base = (char*)ctx->arena;
     for (int k = 0; k < njobs; ++k) {
         JobDev& d = host[k];
@@ -1178,13 +1235,13 @@ vt_status vt_bins_build(vt_ctx* ctx, const vt_job* job, vt_bins** out, int32_t* 
     if (st != VT_OK)
         return st;
     VT_HIP(hipSetDevice(ctx->device));
-    const SingleLayout L = single_layout(d);
+    const SingleLayout L = single_layout(d, slot_layout(d).bytes, 1);
     void* mem = nullptr;
     if (hipMallocAsync(&mem, L.total, s) != hipSuccess)
         return fail(VT_ERR_NOMEM, "bins allocation failed");
     char* base = (char*)mem;
-    bind_single(d, base, L, nullptr);
-    if ((st = bin_single(d, base, L, s)) != VT_OK) {
+    bind_single(d, base, L, 0, nullptr);
+    if ((st = bin_single(d, base, L, 0, false, false, s)) != VT_OK) {
         (void)hipFreeAsync(mem, s);
         return st;
     }

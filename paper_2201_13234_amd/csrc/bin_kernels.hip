@@ -10,7 +10,9 @@
 // max(-param) for the labelling kernel's lower bounds.  Periodic coordinates
 // are brought into the unit cell (cell_coord) by both passes, so the sorted
 // sites always lie in [0, L_a).
-#include "vt_internal.h"
+#include "bin_internal.h"
+
+#include <cstring>
 
 namespace vt {
 
@@ -55,9 +57,11 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
         p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDev* __restrict__ jobs,
-                                                      int njobs, const int64_t* __restrict__ prefix,
-                                                      int64_t total)
+// The counting pass proper: thread g counts site g (of the batch enumeration)
+// into its bin.  Invalid sites are ORed into status_acc when it is given,
+// else into their job's status word.
+__device__ inline void count_sites(const JobDev& single, const JobDev* __restrict__ jobs, int njobs,
+                                   const int64_t* __restrict__ prefix, int64_t total, int32_t* status_acc)
 {
     const int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     const bool live = g < total;
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDe
         }
         if (!ok) {
             b[0] = b[1] = b[2] = 0;
-            atomicOr(J.status, ST_INPUT);
+            atomicOr(status_acc ? status_acc : J.status, ST_INPUT);
         }
         int lin = b[0] + J.nb[0] * (b[1] + J.nb[1] * b[2]);
         int rank = atomicAdd(&J.bin_count[lin], 1);
@@ -166,9 +170,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDe
     }
 }
 
+// With status_acc given (one job), thread 0 also publishes the status the
+// count accumulated there: the labelling kernels read it from *J.status.
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const JobDev* __restrict__ jobs,
                                                         int njobs, const int64_t* __restrict__ prefix,
-                                                        int64_t total)
+                                                        int64_t total, const int32_t* __restrict__ status_acc)
 {
     int64_t g = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     if (g >= total)
@@ -180,6 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const Job
         i = g - prefix[j];
     }
     const JobDev& J = jobs ? jobs[j] : single;
+    if (status_acc && g == 0)
+        *J.status = *status_acc;
     const int nd = J.ndim;
     int lin = J.site_bin[i];
     int pos = J.bin_start[lin] + J.site_rank[i];
@@ -430,6 +438,74 @@ __device__ inline int block_exclusive_add(int v, int& total)
     return off + inc - v;
 }
 
+// Exclusive scan out[0..n] of cnt[0..n) (n <= kSmallScanMax) by one
+// workgroup of ceil(n / 2048) wavefronts: wavefront w takes 8 consecutive rows
+// of 256 counts, each lane four adjacent counts of a row, so that every load
+// moves 1 KiB of contiguous words.  cnt must be padded with zeros to a
+// multiple of 2048 words and out sized for as many plus one: whole rows are
+// written.  The code is straight-line: all loads are issued before the first
+// is used, and the 8 row scans before the first store.
+constexpr int kSmallRows = 8;
+constexpr int kSmallWaveCounts = kSmallRows * 256;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const int32_t* __restrict__ cnt, int32_t* __restrict__ out,
+                                                     int n)
+{
+    __shared__ int wtot[1024 / WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    const int seg = w * kSmallWaveCounts;
+    int4 v[kSmallRows];
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r)
+        v[r] = *(const int4*)(cnt + seg + r * 256 + lane * 4);
+    int inc[kSmallRows];
+    int lsum = 0;
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r) {
+        const int s4 = (v[r].x + v[r].y) + (v[r].z + v[r].w);
+        inc[r] = wave_inclusive_add(s4, lane);
+        lsum += s4;
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        lsum += __shfl_xor(lsum, o);
+    if (lane == 0)
+        wtot[w] = lsum;
+    __syncthreads();
+    int carry = 0, grand = 0;
+    for (int k = 0; k < nw; ++k) {
+        carry += k < w ? wtot[k] : 0;
+        grand += wtot[k];
+    }
+#pragma unroll
+    for (int r = 0; r < kSmallRows; ++r) {
+        const int s4 = (v[r].x + v[r].y) + (v[r].z + v[r].w);
+        const int e0 = carry + inc[r] - s4, e1 = e0 + v[r].x, e2 = e1 + v[r].y, e3 = e2 + v[r].z;
+        *(int4*)(out + seg + r * 256 + lane * 4) = make_int4(e0, e1, e2, e3);
+        carry += __builtin_amdgcn_readlane(inc[r], WAVE - 1);
+    }
+    // out[n], the total, is the row value at index n unless the rows end there
+    if (n == nw * kSmallWaveCounts && threadIdx.x == 0)
+        out[n] = grand;
+}
+
+// The counting kernel.  For one job it can also store the job's record and
+// clear the next call's zeroed scratch (see CountTail).  Batches pass an empty
+// tail.
+__global__ __launch_bounds__(kBlock) void k_bin_count(JobDev single, const JobDev* __restrict__ jobs, int njobs,
+                                                      const int64_t* __restrict__ prefix, int64_t total,
+                                                      CountTail tail)
+{
+    if (tail.clear) {
+        const int64_t stride = (int64_t)gridDim.x * kBlock, nq = tail.clear_words / 4;
+        int4* q = (int4*)tail.clear;
+        for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nq; k += stride)
+            q[k] = make_int4(0, 0, 0, 0);
+    }
+    if (tail.job_dst && blockIdx.x == 0 && threadIdx.x == 0)
+        *tail.job_dst = single;
+    count_sites(single, jobs, njobs, prefix, total, tail.status_acc);
+}
+
 // One-pass exclusive scan of the bin counts (a chained scan with decoupled
 // look-back: Merrill and Garland, Single-pass Parallel Prefix Scan with
 // Decoupled Look-back, 2016).  Each workgroup scans one tile of kScanTile
@@ -530,8 +606,18 @@ hipError_t launch_bin_count(const JobDev& single, const JobDev* jobs_dev, int nj
 {
     if (total_sites <= 0)
         return hipSuccess;
-    k_bin_count<<<grid_for(total_sites, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs,
-                                                                site_prefix_dev, total_sites);
+    CountTail none;
+    std::memset(&none, 0, sizeof none);
+    k_bin_count<<<grid_for(total_sites, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs, site_prefix_dev,
+                                                                total_sites, none);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_count_single(const JobDev& job, const CountTail& tail, hipStream_t s)
+{
+    if (job.nsites <= 0 || (tail.clear_words & 3) != 0 || ((uintptr_t)tail.clear & 15) != 0)
+        return hipErrorInvalidValue;
+    k_bin_count<<<grid_for(job.nsites, kBlock), kBlock, 0, s>>>(job, nullptr, 1, nullptr, job.nsites, tail);
     return hipGetLastError();
 }
 
@@ -541,7 +627,25 @@ hipError_t launch_bin_scatter(const JobDev& single, const JobDev* jobs_dev, int 
     if (total_sites <= 0)
         return hipSuccess;
     k_bin_scatter<<<grid_for(total_sites, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs,
-                                                                  site_prefix_dev, total_sites);
+                                                                  site_prefix_dev, total_sites, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_small(const int32_t* cnt, int32_t* out, int64_t n, hipStream_t s)
+{
+    if (n <= 0 || n > kSmallScanMax || ((uintptr_t)cnt & 15) != 0 || ((uintptr_t)out & 15) != 0)
+        return hipErrorInvalidValue;
+    const int waves = (int)((n + kSmallWaveCounts - 1) / kSmallWaveCounts);
+    k_scan_small<<<1, waves * WAVE, 0, s>>>(cnt, out, (int)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter_single(const JobDev& job, const int32_t* status_acc, hipStream_t s)
+{
+    if (job.nsites <= 0)
+        return hipErrorInvalidValue;
+    k_bin_scatter<<<grid_for(job.nsites, kBlock), kBlock, 0, s>>>(job, nullptr, 1, nullptr, job.nsites,
+                                                                 status_acc);
     return hipGetLastError();
 }
 

@@ -1,0 +1,141 @@
+"""The plain path's scratch across calls on one context.
+
+A call of vt_tessellate uses one of two slots of words that must start at
+zero (bin counts, bounds, counters) and its count kernel clears the other
+slot for the next call; the scan of the counts runs in the count kernel's
+last workgroup when the bins are few (at most 32,768), else in a launch of
+its own.  These tests run sequences of jobs of different sizes, kinds and
+bin counts on one context, with invalid jobs and the other entry points in
+between, and compare every result with the oracle, voxel by voxel.
+"""
+import numpy as np
+import pytest
+
+from paper_2201_13234_amd import inputs as I
+from gpu_util import describe_mismatch, run_device, run_oracle, to_dev, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs():
+    rng = np.random.default_rng(2024)
+    out = []
+    # 3D Voronoi, periodic: a few thousand bins (scan in the count kernel)
+    out.append(("v3", workload((64, 64, 64), I.VORONOI, True, I.uniform_sites(rng, 3000, [64.0] * 3)), None))
+    # 2D Laguerre, few sites and bins (fewer bins than one row of the scan)
+    pts = I.uniform_sites(rng, 20, [50.0, 37.0])
+    out.append(("l2", workload((50, 37), I.LAGUERRE, False, pts, rng.uniform(-20.0, 40.0, 20)), None))
+    # one site
+    out.append(("one", workload((9, 7, 5), I.VORONOI, False, I.uniform_sites(rng, 1, [9.0, 7.0, 5.0])), None))
+    # 3D Johnson-Mehl (pruning rewrites the counts), non-periodic
+    pts = I.uniform_sites(rng, 2500, [48.0] * 3)
+    out.append(("jm3", workload((48, 48, 48), I.JOHNSON_MEHL, False, pts, rng.uniform(0.0, 3.0, 2500)), None))
+    # more than 32,768 bins (separate scan launch): 20,000 sites, bin factor 0.7
+    out.append(("many_bins", workload((64, 64, 64), I.VORONOI, True, I.uniform_sites(rng, 20000, [64.0] * 3)),
+                (-1, 0.7)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return [(name, w, params, run_oracle(w)) for name, w, params in _jobs()]
+
+
+def _run(ctx, w, params):
+    if params is not None:
+        ctx.set_params(*params)
+    try:
+        return run_device(ctx, w, status=True)
+    finally:
+        if params is not None:
+            ctx.set_params(-1, 0.0)
+
+
+def _check(ctx, case, where):
+    name, w, params, ref = case
+    got, st = _run(ctx, w, params)
+    assert st == 0, f"{where}: {name} status {st}"
+    assert np.array_equal(got, ref), f"{where}: {name}: " + describe_mismatch(got, ref)
+
+
+def test_many_bins_case_exceeds_the_folded_scan(cases):
+    from paper_2201_13234_amd import vtess
+    ctx = vtess.Context(0)
+    try:
+        name, w, params, _ = cases[-1]
+        ctx.set_params(*params)
+        assert int(np.prod(ctx.plan(to_dev(w))["bins"])) > 32768
+    finally:
+        ctx.close()
+
+
+def test_sizes_kinds_and_bin_counts_in_sequence(cases):
+    """Every order of growing and shrinking jobs, twice round so that each
+    job meets both slots."""
+    from paper_2201_13234_amd import vtess
+    ctx = vtess.Context(0)
+    try:
+        order = [0, 1, 0, 2, 3, 4, 1, 4, 0, 3, 2, 3, 1, 4, 4, 0]
+        for step, k in enumerate(order):
+            _check(ctx, cases[k], f"step {step}")
+    finally:
+        ctx.close()
+
+
+def test_status_is_reset_by_the_next_call(cases):
+    import torch
+    from paper_2201_13234_amd import vtess
+    ctx = vtess.Context(0)
+    try:
+        rng = np.random.default_rng(7)
+        pts = I.uniform_sites(rng, 40, [24.0] * 3)
+        pts[5, 2] = float("nan")
+        bad = workload((24, 24, 24), I.VORONOI, False, pts)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+        for rep in range(3):
+            job = to_dev(bad)
+            ctx.tessellate(job, status=st)
+            torch.cuda.synchronize()
+            assert int(st.item()) == 5 and bool((job.labels == -1).all())
+            name, w, params, ref = cases[rep % 2]
+            job = to_dev(w)
+            ctx.tessellate(job, status=st)  # the same status word, not cleared by the caller
+            torch.cuda.synchronize()
+            assert int(st.item()) == 0
+            got = job.labels.cpu().numpy()
+            assert np.array_equal(got, ref), f"after a bad job: {name}: " + describe_mismatch(got, ref)
+    finally:
+        ctx.close()
+
+
+def test_other_entry_points_between_plain_calls(cases):
+    """Batches, the general kernel and the static-scratch entry point reuse
+    or bypass the context's scratch; the plain path stays exact around them."""
+    import torch
+    from paper_2201_13234_amd import vtess
+    ctx = vtess.Context(0)
+    try:
+        a, b = cases[0], cases[3]
+        _check(ctx, a, "first")
+        jobs = [to_dev(cases[1][1]), to_dev(cases[2][1])]
+        ctx.tessellate_batch(jobs)
+        torch.cuda.synchronize()
+        for j, c in zip(jobs, (cases[1], cases[2])):
+            assert np.array_equal(j.labels.cpu().numpy(), c[3])
+        _check(ctx, b, "after a batch")
+        _check(ctx, a, "after a batch, second")
+        g = to_dev(a[1])
+        ctx.tessellate_nd(g, generic=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.labels.cpu().numpy(), a[3])
+        _check(ctx, b, "after the general kernel")
+        nj = to_dev(cases[1][1])
+        nj._check_tensors()  # allocates the label image before the call
+        ctx.tessellate_noalloc(nj)
+        torch.cuda.synchronize()
+        assert np.array_equal(nj.labels.cpu().numpy(), cases[1][3])
+        _check(ctx, a, "after the static-scratch entry point")
+        _check(ctx, cases[4], "many bins after all")
+        _check(ctx, a, "last")
+    finally:
+        ctx.close()
