@@ -17,11 +17,18 @@ struct CountTail {
 };
 
 // Largest bin grid scanned by one workgroup (launch_scan_small): 16
-// wavefronts of 2048 counts.  Its counts are padded with zeros to
-// count_words(nbins) words, and it writes count_words(nbins) + 1 words of the
-// output.
-constexpr int64_t kSmallScanMax = 32768;
-inline int64_t count_words(int64_t nbins) { return nbins <= kSmallScanMax ? (nbins + 2047) / 2048 * 2048 : nbins; }
+// wavefronts of 16 rows of 256 counts (8 rows up to 32,768 bins).  Its counts
+// are padded with zeros to count_words(nbins) words, whole wavefronts, and it
+// writes count_words(nbins) + 1 words of the output.
+constexpr int64_t kSmallScanMax = 65536;
+inline int64_t small_scan_wave_counts(int64_t nbins) { return nbins <= 32768 ? 8 * 256 : 16 * 256; }
+inline int64_t count_words(int64_t nbins)
+{
+    if (nbins > kSmallScanMax)
+        return nbins;
+    const int64_t w = small_scan_wave_counts(nbins);
+    return (nbins + w - 1) / w * w;
+}
 
 // Counting pass over one job's sites (`job` as bound for this call), with
 // the extra work of `tail`.

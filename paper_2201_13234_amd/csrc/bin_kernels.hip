@@ -439,29 +439,27 @@ __device__ inline int block_exclusive_add(int v, int& total)
 }
 
 // Exclusive scan out[0..n] of cnt[0..n) (n <= kSmallScanMax) by one
-// workgroup of ceil(n / 2048) wavefronts: wavefront w takes 8 consecutive rows
+// workgroup of at most 16 wavefronts: wavefront w takes ROWS consecutive rows
 // of 256 counts, each lane four adjacent counts of a row, so that every load
-// moves 1 KiB of contiguous words.  cnt must be padded with zeros to a
-// multiple of 2048 words and out sized for as many plus one: whole rows are
-// written.  The code is straight-line: all loads are issued before the first
-// is used, and the 8 row scans before the first store.
-constexpr int kSmallRows = 8;
-constexpr int kSmallWaveCounts = kSmallRows * 256;
-
+// moves 1 KiB of contiguous words.  cnt must be padded with zeros to whole
+// wavefronts (count_words) and out sized for as many words plus one: whole
+// rows are written.  The code is straight-line: all loads are issued before
+// the first is used, and the row scans before the first store.
+template <int ROWS>
 __global__ __launch_bounds__(1024) void k_scan_small(const int32_t* __restrict__ cnt, int32_t* __restrict__ out,
                                                      int n)
 {
     __shared__ int wtot[1024 / WAVE];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    const int seg = w * kSmallWaveCounts;
-    int4 v[kSmallRows];
+    const int seg = w * ROWS * 256;
+    int4 v[ROWS];
 #pragma unroll
-    for (int r = 0; r < kSmallRows; ++r)
+    for (int r = 0; r < ROWS; ++r)
         v[r] = *(const int4*)(cnt + seg + r * 256 + lane * 4);
-    int inc[kSmallRows];
+    int inc[ROWS];
     int lsum = 0;
 #pragma unroll
-    for (int r = 0; r < kSmallRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         const int s4 = (v[r].x + v[r].y) + (v[r].z + v[r].w);
         inc[r] = wave_inclusive_add(s4, lane);
         lsum += s4;
@@ -477,14 +475,14 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int32_t* __restrict__
         grand += wtot[k];
     }
 #pragma unroll
-    for (int r = 0; r < kSmallRows; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         const int s4 = (v[r].x + v[r].y) + (v[r].z + v[r].w);
         const int e0 = carry + inc[r] - s4, e1 = e0 + v[r].x, e2 = e1 + v[r].y, e3 = e2 + v[r].z;
         *(int4*)(out + seg + r * 256 + lane * 4) = make_int4(e0, e1, e2, e3);
         carry += __builtin_amdgcn_readlane(inc[r], WAVE - 1);
     }
     // out[n], the total, is the row value at index n unless the rows end there
-    if (n == nw * kSmallWaveCounts && threadIdx.x == 0)
+    if (n == nw * ROWS * 256 && threadIdx.x == 0)
         out[n] = grand;
 }
 
@@ -635,8 +633,12 @@ hipError_t launch_scan_small(const int32_t* cnt, int32_t* out, int64_t n, hipStr
 {
     if (n <= 0 || n > kSmallScanMax || ((uintptr_t)cnt & 15) != 0 || ((uintptr_t)out & 15) != 0)
         return hipErrorInvalidValue;
-    const int waves = (int)((n + kSmallWaveCounts - 1) / kSmallWaveCounts);
-    k_scan_small<<<1, waves * WAVE, 0, s>>>(cnt, out, (int)n);
+    const int64_t per_wave = small_scan_wave_counts(n);
+    const unsigned threads = (unsigned)((n + per_wave - 1) / per_wave) * WAVE;
+    if (per_wave == 8 * 256)
+        k_scan_small<8><<<1, threads, 0, s>>>(cnt, out, (int)n);
+    else
+        k_scan_small<16><<<1, threads, 0, s>>>(cnt, out, (int)n);
     return hipGetLastError();
 }
 

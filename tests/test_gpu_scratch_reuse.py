@@ -2,9 +2,8 @@
 
 A call of vt_tessellate uses one of two slots of words that must start at
 zero (bin counts, bounds, counters) and its count kernel clears the other
-slot for the next call; the scan of the counts runs in the count kernel's
-last workgroup when the bins are few (at most 32,768), else in a launch of
-its own.  These tests run sequences of jobs of different sizes, kinds and
+slot for the next call; the counts are scanned by one workgroup when the
+bins are few (at most 65,536), else by the multi-workgroup scan.  These tests run sequences of jobs of different sizes, kinds and
 bin counts on one context, with invalid jobs and the other entry points in
 between, and compare every result with the oracle, voxel by voxel.
 """
@@ -20,7 +19,7 @@ pytestmark = pytest.mark.gpu
 def _jobs():
     rng = np.random.default_rng(2024)
     out = []
-    # 3D Voronoi, periodic: a few thousand bins (scan in the count kernel)
+    # 3D Voronoi, periodic: a few thousand bins (one-workgroup scan)
     out.append(("v3", workload((64, 64, 64), I.VORONOI, True, I.uniform_sites(rng, 3000, [64.0] * 3)), None))
     # 2D Laguerre, few sites and bins (fewer bins than one row of the scan)
     pts = I.uniform_sites(rng, 20, [50.0, 37.0])
@@ -30,9 +29,12 @@ def _jobs():
     # 3D Johnson-Mehl (pruning rewrites the counts), non-periodic
     pts = I.uniform_sites(rng, 2500, [48.0] * 3)
     out.append(("jm3", workload((48, 48, 48), I.JOHNSON_MEHL, False, pts, rng.uniform(0.0, 3.0, 2500)), None))
-    # more than 32,768 bins (separate scan launch): 20,000 sites, bin factor 0.7
-    out.append(("many_bins", workload((64, 64, 64), I.VORONOI, True, I.uniform_sites(rng, 20000, [64.0] * 3)),
+    # more than 65,536 bins (multi-workgroup scan): 40,000 sites, bin factor 0.7
+    out.append(("many_bins", workload((64, 64, 64), I.VORONOI, True, I.uniform_sites(rng, 40000, [64.0] * 3)),
                 (-1, 0.7)))
+    # between 32,768 and 65,536 bins (one workgroup, 16 rows per wavefront)
+    out.append(("mid_bins", workload((64, 64, 64), I.LAGUERRE, True, I.uniform_sites(rng, 20000, [64.0] * 3),
+                                     rng.uniform(-0.5, 1.0, 20000)), (-1, 0.7)))
     return out
 
 
@@ -58,13 +60,17 @@ def _check(ctx, case, where):
     assert np.array_equal(got, ref), f"{where}: {name}: " + describe_mismatch(got, ref)
 
 
-def test_many_bins_case_exceeds_the_folded_scan(cases):
+def test_bin_counts_cover_both_scans(cases):
     from paper_2201_13234_amd import vtess
     ctx = vtess.Context(0)
     try:
-        name, w, params, _ = cases[-1]
-        ctx.set_params(*params)
-        assert int(np.prod(ctx.plan(to_dev(w))["bins"])) > 32768
+        nb = {}
+        for name, w, params, _ in cases:
+            ctx.set_params(*(params or (-1, 0.0)))
+            nb[name] = int(np.prod(ctx.plan(to_dev(w))["bins"]))
+        assert nb["many_bins"] > 65536
+        assert 32768 < nb["mid_bins"] <= 65536
+        assert nb["l2"] < 256
     finally:
         ctx.close()
 
@@ -75,7 +81,7 @@ def test_sizes_kinds_and_bin_counts_in_sequence(cases):
     from paper_2201_13234_amd import vtess
     ctx = vtess.Context(0)
     try:
-        order = [0, 1, 0, 2, 3, 4, 1, 4, 0, 3, 2, 3, 1, 4, 4, 0]
+        order = [0, 1, 0, 2, 3, 4, 1, 4, 0, 5, 3, 2, 3, 5, 1, 4, 4, 5, 0]
         for step, k in enumerate(order):
             _check(ctx, cases[k], f"step {step}")
     finally:
