@@ -855,6 +855,78 @@ void nd_tile_shape(const vt_job_nd* j, int32_t* T)
     }
 }
 
+// Squared length of the longest diagonal of the parallelepiped spanned by
+// T[i] voxel steps d.hv[i] (i < nd).
+double tile_diagonal2(const vt::NdDev& d, int nd, const int32_t* T)
+{
+    double worst = 0.0;
+    for (int m = 0; m < (1 << (nd - 1)); ++m) {
+        double q = 0.0;
+        for (int a = 0; a < nd; ++a) {
+            double x = 0.0;
+            for (int i = 0; i < nd; ++i)
+                x += ((i > 0 && ((m >> (i - 1)) & 1)) ? -1.0 : 1.0) * (double)T[i] * d.hv[i][a];
+            q += x * x;
+        }
+        worst = std::max(worst, q);
+    }
+    return worst;
+}
+
+void lattice_shapes(const vt::NdDev& d, int nd, int axis, int left, const int* cap, int32_t* cur, int32_t* best,
+                    double* bestd)
+{
+    if (axis == nd - 1) {
+        if (left > cap[axis])
+            return;
+        cur[axis] = 1 << left;
+        const double q = tile_diagonal2(d, nd, cur);
+        if (q < *bestd) {
+            *bestd = q;
+            for (int a = 0; a < nd; ++a)
+                best[a] = cur[a];
+        }
+        return;
+    }
+    for (int e = std::min(left, cap[axis]); e >= 0; --e) {
+        cur[axis] = 1 << e;
+        lattice_shapes(d, nd, axis + 1, left - e, cap, cur, best, bestd);
+    }
+}
+
+// Tile shape with general period vectors (d.hv set): the first axis keeps
+// the extent nd_tile_shape gives it; the others take, among the power-of-two
+// shapes with as many voxels (each at most the smallest power of two not
+// below its voxel count), the one whose tile parallelepiped has the shortest
+// longest diagonal, so that fewer sites lie near a tile.  Ties keep the
+// shape nd_tile_shape gives.  On the 3D triclinic benchmark cell this turns
+// 8x8x4 into 8x4x8 tiles: 2-4 % faster per call for every kind.
+void lattice_tile_shape(const vt_job_nd* j, const vt::NdDev& d, int32_t* T)
+{
+    nd_tile_shape(j, T);
+    const int nd = j->ndim;
+    if (nd < 3)
+        return;
+    int left = 0, cap[vt::kMaxDim] = {0};
+    for (int a = 1; a < nd; ++a) {
+        int e = 0;
+        while ((1 << e) < T[a])
+            ++e;
+        left += e;
+        int c = 0;
+        while ((int64_t)1 << c < j->n[a])
+            ++c;
+        cap[a] = c;
+    }
+    int32_t cur[vt::kMaxDim], best[vt::kMaxDim];
+    for (int a = 0; a < nd; ++a)
+        cur[a] = best[a] = T[a];
+    double bestd = tile_diagonal2(d, nd, T);
+    lattice_shapes(d, nd, 1, left, cap, cur, best, &bestd);
+    for (int a = 0; a < nd; ++a)
+        T[a] = best[a];
+}
+
 vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
 {
     if (!j)
@@ -973,7 +1045,10 @@ vt_status plan_nd(const vt_ctx* ctx, const vt_job_nd* j, vt::NdDev* d)
         d->bs[a] = d->L[a] / (double)d->nb[a];
         d->inv_bs[a] = (double)d->nb[a] / d->L[a];
     }
-    nd_tile_shape(j, d->T);
+    if (d->lattice)
+        lattice_tile_shape(j, *d, d->T);
+    else
+        nd_tile_shape(j, d->T);
     // Two voxels per thread along axis 0, so that a tile's search and staging
     // serve twice the voxels.  Measured to pay with orthogonal periods in 2 to
     // 4 axes when axis 0 holds at least eight thread widths (ragged tiles

@@ -157,3 +157,40 @@ def test_scale_bounds_refused_while_planning():
         with pytest.raises(vtess.VtError) as e:
             vtess.plan_scalars(nsites=10, **kw)
         assert e.value.code == vtess.ERR_INVALID, kw
+
+
+def test_lattice_tile_shape_minimises_the_tile_diagonal():
+    """General period vectors: the general kernel's tile keeps the first
+    axis's extent and, among the power-of-two shapes of the other axes with
+    as many voxels, takes the one whose parallelepiped has the shortest
+    longest diagonal (host planning only, no GPU).  Brute force over the
+    same shapes here."""
+    import itertools
+    import numpy as np
+    from paper_2201_13234_amd import vtess
+    cells = {
+        "triclinic": [[128.0, 0.0, 0.0], [40.0, 120.0, 0.0], [25.0, -18.0, 110.0]],
+        "tri3": [[6.0, 0.0, 0.0], [2.0, 5.0, 0.0], [1.5, -1.0, 4.5]],
+        "shear4": [[4.0, 0.0, 0.0, 0.0], [1.0, 3.5, 0.0, 0.0], [0.0, 1.2, 3.0, 0.5], [0.7, 0.0, -0.9, 3.2]],
+    }
+    for name, P in cells.items():
+        P = np.array(P)
+        d = len(P)
+        n = (128, 128, 128) if d == 3 else (24,) * 4
+        got = vtess.plan_scalars(n, (1.0,) * d, 0, True, 20000, periods=P.tolist(), nd=True)["tile"]
+        ortho = vtess.plan_scalars(n, (1.0,) * d, 0, True, 20000, nd=True)["tile"]
+        assert got[0] == ortho[0] and np.prod(got) == np.prod(ortho)
+        hv = P / np.array(n, dtype=float)[:, None]
+
+        def diag2(T):
+            return max(float(np.sum(((np.array(s) * np.array(T, dtype=float)) @ hv) ** 2))
+                       for s in itertools.product([1.0], *([[1.0, -1.0]] * (d - 1))))
+
+        shapes = [(got[0],) + tuple(2 ** e for e in es)
+                  for es in itertools.product(range(8), repeat=d - 1)
+                  if 2 ** sum(es) * got[0] == np.prod(ortho) and all(2 ** e <= 2 ** int(np.ceil(np.log2(m)))
+                                                                      for e, m in zip(es, n[1:]))]
+        best = min(diag2(T) for T in shapes)
+        assert diag2(got) == best, (name, got)
+    assert vtess.plan_scalars((128,) * 3, (1.0,) * 3, 0, True, 20000, periods=cells["triclinic"],
+                              nd=True)["tile"] == (8, 4, 8)
