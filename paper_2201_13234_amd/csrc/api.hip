@@ -107,6 +107,7 @@ struct vt_ctx {
     size_t slot_cap = 0;
     size_t slot_clean[2] = {0, 0};
     int slot_next = 0;
+    int slot_owner = -1;  // path whose layout the slots follow: 0 plain, 1 general, -1 none
     // this device's copy of the static scratch (vt_tessellate_noalloc)
     void* noalloc = nullptr;
     // phase timing: three events per recorded call
@@ -459,6 +460,59 @@ hipError_t launch_prepare(int32_t* zero_begin, int64_t nwords, int32_t* extra, h
     return hipGetLastError();
 }
 
+// ---- the zeroed slots of the plain and general paths ----
+//
+// Each path lays out three slots of ctx->slot_cap bytes for the words that
+// must start at zero: a call uses slot 0 or 1 and its count kernel clears
+// the other for the next call; a call captured into a graph uses slot 2 and
+// clears it itself, since its replays may come in any order with other calls.
+
+// Settles the slots' layout for a call of path `owner` whose zeroed words
+// take zbytes: another path's layout or a larger slot makes every slot
+// unknown.
+void slots_for(vt_ctx* ctx, int owner, size_t zbytes)
+{
+    if (ctx->slot_owner != owner || zbytes > ctx->slot_cap) {
+        ctx->slot_owner = owner;
+        ctx->slot_cap = std::max(ctx->slot_cap, zbytes);
+        ctx->slot_clean[0] = ctx->slot_clean[1] = 0;
+    }
+}
+
+struct SlotUse {
+    int slot;
+    bool zeroed, capturing;
+};
+
+// The slot of this call (after the arena is in place), whether it is known
+// to be zero, and whether the stream is capturing (a stream whose capture
+// state cannot be read is taken as capturing).  Nothing is known to be zero
+// until slot_end: a failed launch in between leaves the slots unknown.
+SlotUse slot_begin(vt_ctx* ctx, size_t zbytes, hipStream_t s)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    bool capturing = true;
+    if (hipStreamIsCapturing(s, &cap) == hipSuccess)
+        capturing = cap != hipStreamCaptureStatusNone;
+    else
+        (void)hipGetLastError();
+    SlotUse u;
+    u.capturing = capturing;
+    u.slot = capturing ? 2 : ctx->slot_next;
+    u.zeroed = !capturing && ctx->slot_clean[u.slot] >= zbytes;
+    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;
+    return u;
+}
+
+// Every launch of the call is queued: the other slot is zero for the next.
+void slot_end(vt_ctx* ctx, const SlotUse& u, size_t zbytes)
+{
+    if (u.capturing)
+        return;
+    ctx->slot_clean[u.slot ^ 1] = zbytes;
+    ctx->slot_next = u.slot ^ 1;
+}
+
 // Count, scan and scatter the sites of one job (its arrays bound to `slot`).
 // Unless `zeroed`, the slot is cleared first; with clear_other, the count
 // kernel clears the other slot (its first L.z.bytes) for the next call.
@@ -700,25 +754,13 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
         return st;
     VT_HIP(hipSetDevice(ctx->device));
     const size_t zbytes = slot_layout(d).bytes;
-    if (zbytes > ctx->slot_cap) {
-        ctx->slot_cap = zbytes;
-        ctx->slot_clean[0] = ctx->slot_clean[1] = 0;
-    }
+    slots_for(ctx, 0, zbytes);
     const SingleLayout L = single_layout(d, ctx->slot_cap, 3);
     if ((st = ensure_scratch(ctx, L.total)) != VT_OK)
         return st;
-    // A call captured into a graph may be replayed in any order with other
-    // calls: it takes the third slot and clears it itself.  (A stream whose
-    // capture state cannot be read is treated as capturing.)
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    bool capturing = true;
-    if (hipStreamIsCapturing(s, &cap) == hipSuccess)
-        capturing = cap != hipStreamCaptureStatusNone;
-    else
-        (void)hipGetLastError();
-    const int slot = capturing ? 2 : ctx->slot_next;
-    const bool zeroed = !capturing && ctx->slot_clean[slot] >= zbytes;
-    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;  // until every launch below is queued
+    const SlotUse u = slot_begin(ctx, zbytes, s);
+    const int slot = u.slot;
+    const bool zeroed = u.zeroed, capturing = u.capturing;
     char* base = (char*)ctx->arena;
     bind_single(d, base, L, slot, status_dev);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -744,10 +786,7 @@ vt_status vt_tessellate(vt_ctx* ctx, const vt_job* job, int32_t* status_dev, voi
     VT_HIP(vt::launch_label_fallback(d, jd, s));
     if (ev[3])
         VT_HIP(hipEventRecord(ev[3], s));
-    if (!capturing) {
-        ctx->slot_clean[slot ^ 1] = zbytes;
-        ctx->slot_next = slot ^ 1;
-    }
+    slot_end(ctx, u, zbytes);
     return VT_OK;
 }
 
@@ -1127,13 +1166,22 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     if (st != VT_OK)
         return st;
     VT_HIP(hipSetDevice(ctx->device));
-    Carver c;
-    const size_t o_pbound = c.take<unsigned long long>(3);
-    const size_t o_status = c.take<int32_t>(1, 4);
-    const size_t o_count = c.take<int32_t>(d.nbins, 4);
+    // the words that start at zero: bounds, status accumulator, bin counts
+    // (padded for the one-workgroup scan), flags of the multi-workgroup scan
+    Carver z;
+    const size_t z_pbound = z.take<unsigned long long>(3);
+    const size_t z_sacc = z.take<int32_t>(1, 4);
+    const size_t z_count = z.take<int32_t>(vt::count_words(d.nbins));
     const int64_t partial_cap = vt::scan_flags_needed((int64_t)d.nbins);
-    const size_t o_partial = c.take<unsigned long long>(partial_cap, 8);  // scan flags, cleared with the counts
-    const size_t o_start = c.take<int32_t>((int64_t)d.nbins + 1);
+    const size_t z_partial = z.take<unsigned long long>(partial_cap, 8);
+    const size_t zbytes = align_up(z.off, 256);
+    slots_for(ctx, 1, zbytes);
+    Carver c;
+    size_t o_slot[3];
+    for (int k = 0; k < 3; ++k)
+        o_slot[k] = c.take<char>((int64_t)ctx->slot_cap);
+    const size_t o_status = c.take<int32_t>(1, 4);
+    const size_t o_start = c.take<int32_t>(vt::count_words(d.nbins) + 1);
     const size_t o_bin = c.take<int32_t>(d.nsites);
     const size_t o_rank = c.take<int32_t>(d.nsites);
     const size_t o_sc = c.take<double>((int64_t)d.nsites * d.ndim);
@@ -1142,11 +1190,12 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     const size_t o_sidx = c.take<int32_t>(d.nsites);
     if ((st = ensure_scratch(ctx, align_up(c.off, 256))) != VT_OK)
         return st;
-    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;  // the arena's words are reused below
+    const SlotUse u = slot_begin(ctx, zbytes, s);
     char* base = (char*)ctx->arena;
-    d.pbound = (unsigned long long*)(base + o_pbound);
+    char* zs = base + o_slot[u.slot];
+    d.pbound = (unsigned long long*)(zs + z_pbound);
     d.status = status_dev ? status_dev : (int32_t*)(base + o_status);
-    d.bin_count = (int32_t*)(base + o_count);
+    d.bin_count = (int32_t*)(zs + z_count);
     d.bin_start = (int32_t*)(base + o_start);
     d.site_bin = (int32_t*)(base + o_bin);
     d.site_rank = (int32_t*)(base + o_rank);
@@ -1154,15 +1203,19 @@ vt_status vt_tessellate_nd(vt_ctx* ctx, const vt_job_nd* job, int32_t* status_de
     d.sf = d.lattice ? (double*)(base + o_sf) : nullptr;
     d.sp = (double*)(base + o_sp);
     d.sidx = (int32_t*)(base + o_sidx);
-    // pbound, internal status, bin counts and scan flags are contiguous: zero
-    // them together (and the caller's status word)
-    const int64_t words = (int64_t)((o_partial - o_pbound) / 4) + 2 * partial_cap;
-    VT_HIP(launch_prepare((int32_t*)(base + o_pbound), words, status_dev, s));
-    VT_HIP(vt::launch_nd_bin_count(d, s));
-    VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(base + o_partial), partial_cap,
-                           s));
-    VT_HIP(vt::launch_nd_bin_scatter(d, s));
+    int32_t* sacc = (int32_t*)(zs + z_sacc);
+    if (!u.zeroed)
+        VT_HIP(launch_prepare((int32_t*)zs, (int64_t)(zbytes / 4), nullptr, s));
+    int32_t* clear = u.capturing ? nullptr : (int32_t*)(base + o_slot[u.slot ^ 1]);
+    VT_HIP(vt::launch_nd_bin_count(d, sacc, clear, clear ? (int64_t)(zbytes / 4) : 0, s));
+    if (d.nbins <= vt::kSmallScanMax)
+        VT_HIP(vt::launch_scan_small(d.bin_count, d.bin_start, d.nbins, s));
+    else
+        VT_HIP(vt::launch_scan(d.bin_count, d.bin_start, d.nbins, (unsigned long long*)(zs + z_partial), partial_cap,
+                               s));
+    VT_HIP(vt::launch_nd_bin_scatter(d, sacc, s));
     VT_HIP(vt::launch_nd_label(d, s));
+    slot_end(ctx, u, zbytes);
     return VT_OK;
 }
 
@@ -1259,7 +1312,8 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     vt_status st = ensure_scratch(ctx, align_up(c.off, 256));
     if (st != VT_OK)
         return st;
-    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;  // the arena's words are reused below
+    ctx->slot_owner = -1;  // the arena's words are reused below
+    ctx->slot_clean[0] = ctx->slot_clean[1] = 0;
     char* base = (char*)ctx->arena;
     for (int k = 0; k < njobs; ++k) {
         JobDev& d = host[k];

@@ -47,8 +47,12 @@ struct NdDev {
     unsigned long long* pbound;    // [3]: ordered bits of max(param), max(-param), max |coordinate|
 };
 
-hipError_t launch_nd_bin_count(const NdDev& J, hipStream_t s);
-hipError_t launch_nd_bin_scatter(const NdDev& J, hipStream_t s);
+// Binning of the general path: status_acc is a zeroed word that collects
+// invalid sites and that the scatter stores into *J.status; the count also
+// clears clear_words words at `clear` (16-byte aligned; nullable).
+hipError_t launch_nd_bin_count(const NdDev& J, int32_t* status_acc, int32_t* clear, int64_t clear_words,
+                               hipStream_t s);
+hipError_t launch_nd_bin_scatter(const NdDev& J, const int32_t* status_acc, hipStream_t s);
 hipError_t launch_nd_label(const NdDev& J, hipStream_t s);
 
 }  // namespace vt

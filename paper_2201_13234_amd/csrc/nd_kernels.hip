@@ -89,9 +89,18 @@ __device__ inline double frac_coord(const NdDev& J, int nd, const double* s, int
 
 // ------------------------------------------------------------------ binning
 
-__global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
+// One thread per site.  Invalid sites are ORed into status_acc (a zeroed
+// word; k_nd_scatter publishes it).  The kernel also sets clear_words words
+// at `clear` to zero (the next call's zeroed scratch), if given.
+__global__ __launch_bounds__(NDT) void k_nd_count(NdDev J, int32_t* status_acc, int32_t* clear, int64_t clear_words)
 {
     const int64_t i = blockIdx.x * (int64_t)NDT + threadIdx.x;
+    if (clear) {
+        const int64_t stride = (int64_t)gridDim.x * NDT, nq = clear_words / 4;
+        int4* q = (int4*)clear;
+        for (int64_t k = i; k < nq; k += stride)
+            q[k] = make_int4(0, 0, 0, 0);
+    }
     const bool live = i < J.nsites;
     unsigned long long hi = 0ull, lo = 0ull, mag = 0ull;
     if (live) {
@@ -142,7 +151,7 @@ __global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
         if (!ok) {
             lin = 0;
             hi = lo = mag = 0ull;
-            atomicOr(J.status, ST_INPUT);
+            atomicOr(status_acc, ST_INPUT);
         }
         J.site_bin[i] = (int32_t)lin;
         J.site_rank[i] = atomicAdd(&J.bin_count[lin], 1);
@@ -161,11 +170,14 @@ __global__ __launch_bounds__(NDT) void k_nd_count(NdDev J)
     }
 }
 
-__global__ __launch_bounds__(NDT) void k_nd_scatter(NdDev J)
+// Thread 0 also publishes the status that k_nd_count accumulated.
+__global__ __launch_bounds__(NDT) void k_nd_scatter(NdDev J, const int32_t* __restrict__ status_acc)
 {
     const int64_t i = blockIdx.x * (int64_t)NDT + threadIdx.x;
     if (i >= J.nsites)
         return;
+    if (i == 0)
+        *J.status = *status_acc;
     const int nd = J.ndim;
     const int64_t pos = J.bin_start[J.site_bin[i]] + J.site_rank[i];
     double s[kMaxDim];
@@ -1530,17 +1542,22 @@ hipError_t launch_nd_lat(const NdDev& J, unsigned g, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_nd_bin_count(const NdDev& J, hipStream_t s)
+hipError_t launch_nd_bin_count(const NdDev& J, int32_t* status_acc, int32_t* clear, int64_t clear_words,
+                               hipStream_t s)
 {
+    if (!status_acc || (clear_words & 3) != 0 || ((uintptr_t)clear & 15) != 0)
+        return hipErrorInvalidValue;
     const int64_t g = (J.nsites + NDT - 1) / NDT;
-    k_nd_count<<<(unsigned)g, NDT, 0, s>>>(J);
+    k_nd_count<<<(unsigned)g, NDT, 0, s>>>(J, status_acc, clear, clear_words);
     return hipGetLastError();
 }
 
-hipError_t launch_nd_bin_scatter(const NdDev& J, hipStream_t s)
+hipError_t launch_nd_bin_scatter(const NdDev& J, const int32_t* status_acc, hipStream_t s)
 {
+    if (!status_acc)
+        return hipErrorInvalidValue;
     const int64_t g = (J.nsites + NDT - 1) / NDT;
-    k_nd_scatter<<<(unsigned)g, NDT, 0, s>>>(J);
+    k_nd_scatter<<<(unsigned)g, NDT, 0, s>>>(J, status_acc);
     return hipGetLastError();
 }
 

@@ -145,3 +145,64 @@ def test_other_entry_points_between_plain_calls(cases):
         _check(ctx, a, "last")
     finally:
         ctx.close()
+
+
+def _nd_cases():
+    import oracle
+    rng = np.random.default_rng(77)
+    out = []
+    # 4D Voronoi, periodic
+    w = workload((14, 12, 10, 9), I.VORONOI, True, I.uniform_sites(rng, 300, [14.0, 12.0, 10.0, 9.0]))
+    p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+    out.append(("nd4", w, None, oracle.tessellate(p, w.coords, w.param)[0]))
+    # 3D Laguerre through the general kernel, non-periodic
+    w = workload((30, 26, 22), I.LAGUERRE, False, I.uniform_sites(rng, 400, [30.0, 26.0, 22.0]),
+                 rng.uniform(-2.0, 4.0, 400))
+    p = oracle.problem(w.n, w.L, w.kind, w.periodic, w.growth)
+    out.append(("nd3g", w, None, oracle.tessellate(p, w.coords, w.param)[0]))
+    # triclinic cell, Johnson-Mehl
+    P = np.array([[6.0, 0.0, 0.0], [2.0, 5.0, 0.0], [1.5, -1.0, 4.5]])
+    coords = rng.random((120, 3)) @ P
+    w = workload((17, 15, 13), I.JOHNSON_MEHL, True, coords, rng.uniform(0.0, 2.0, 120), 0.8, L=[1.0] * 3)
+    p = oracle.problem(w.n, w.L, w.kind, True, w.growth, periods=P)
+    out.append(("lat3", w, P, oracle.brute(p, w.coords, w.param)))
+    return out
+
+
+def test_general_path_calls_between_plain_calls(cases):
+    """The general path keeps its own zeroed slots: its calls, plain calls and
+    invalid general-path jobs in any order, one status word throughout."""
+    import torch
+    from paper_2201_13234_amd import vtess
+    nd = _nd_cases()
+    ctx = vtess.Context(0)
+    st = torch.full((1,), 99, dtype=torch.int32, device="cuda:0")
+
+    def run_nd(case, bad=False):
+        name, w, P, ref = case
+        job = to_dev(w)
+        if P is not None:
+            job.periods = P.tolist()
+        if bad:
+            c = w.coords.copy()
+            c[3, 0] = float("nan")
+            job.coords = torch.from_numpy(c).to("cuda:0")
+        ctx.tessellate_nd(job, status=st, generic=True)
+        torch.cuda.synchronize()
+        got = job.labels.cpu().numpy()
+        if bad:
+            assert int(st.item()) == 5 and (got == -1).all(), name
+        else:
+            assert int(st.item()) == 0, name
+            assert np.array_equal(got, ref), f"{name}: " + describe_mismatch(got, ref)
+
+    try:
+        for step, (kind, k) in enumerate([("nd", 0), ("nd", 1), ("plain", 0), ("nd", 2), ("nd", 0),
+                                          ("bad", 1), ("nd", 1), ("plain", 4), ("nd", 2), ("plain", 1),
+                                          ("bad", 0), ("nd", 0), ("nd", 0), ("plain", 0)]):
+            if kind == "plain":
+                _check(ctx, cases[k], f"step {step}")
+            else:
+                run_nd(nd[k], bad=kind == "bad")
+    finally:
+        ctx.close()
