@@ -236,8 +236,9 @@ __device__ inline int find_bin_job(const JobDev* jobs, int n, int64_t g)
 
 // Whether another site swallows the site at sorted position g (see above).
 // The wavefront's lanes take the bins of the search box, 64 at a time, and
-// each lane reads its bin's sites four at a time so that their loads are in
-// flight together.  The test compares squares, (d / v)^2 < (t_s - M - t_r)^2
+// each lane reads its bin's sites two at a time so that their loads are in
+// flight together (bins hold about one site at the Johnson-Mehl bin size; four
+// at a time held more registers and fewer wavefronts per SIMD).  The test compares squares, (d / v)^2 < (t_s - M - t_r)^2
 // with t_s - M - t_r > 0: its rounding, a few units in the last place of the
 // key scale, is as far below M as that of the key itself.
 template <int ND>
@@ -306,13 +307,13 @@ __device__ inline bool jm_swallowed(const JobDev& J, int64_t g, int lane)
             }
             const int lin = w3[0] + J.nb[0] * (w3[1] + J.nb[1] * w3[2]);
             const int b0 = J.bin_start[lin], cnt = J.bin_count[lin];
-            for (int k = 0; k < cnt && !hit; k += 4) {
-                double4 q[4];
+            for (int k = 0; k < cnt && !hit; k += 2) {
+                double4 q[2];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 2; ++u)
                     q[u] = k + u < cnt ? J.sites[b0 + k + u] : s;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 2; ++u) {
                     const double qc[3] = {q[u].x, q[u].y, q[u].z};
                     double d2 = 0.0;
 #pragma unroll
