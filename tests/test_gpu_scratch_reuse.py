@@ -3,9 +3,11 @@
 A call of vt_tessellate uses one of two slots of words that must start at
 zero (bin counts, bounds, counters) and its count kernel clears the other
 slot for the next call; the counts are scanned by one workgroup when the
-bins are few (at most 65,536), else by the multi-workgroup scan.  These tests run sequences of jobs of different sizes, kinds and
-bin counts on one context, with invalid jobs and the other entry points in
-between, and compare every result with the oracle, voxel by voxel.
+bins are few (at most 65,536), else by the multi-workgroup scan.  These
+tests run sequences of jobs of different sizes, kinds and bin counts on one
+context, with invalid jobs and the other entry points in between, and compare
+every result with the oracle, voxel by voxel.  The general path keeps the
+same kind of slots; its calls are interleaved with plain ones at the end.
 """
 import numpy as np
 import pytest
