@@ -214,6 +214,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(JobDev single, const Job
 // close; a site whose search box exceeds kPruneMaxBins bins is kept.
 
 constexpr int kPruneMaxBins = 4096;
+// Lanes per site of a single job's search (WAVE / kJmLanes sites per wavefront).
+constexpr int kJmLanes = 16;
 
 __device__ inline double from_ordered_bits(unsigned long long u)
 {
@@ -234,17 +236,20 @@ __device__ inline int find_bin_job(const JobDev* jobs, int n, int64_t g)
     return lo;
 }
 
-// Whether another site swallows the site at sorted position g (see above).
-// The wavefront's lanes take the bins of the search box, 64 at a time, and
-// each lane reads its bin's sites two at a time so that their loads are in
-// flight together (bins hold about one site at the Johnson-Mehl bin size; four
-// at a time held more registers and fewer wavefronts per SIMD).  The test compares squares, (d / v)^2 < (t_s - M - t_r)^2
-// with t_s - M - t_r > 0: its rounding, a few units in the last place of the
-// key scale, is as far below M as that of the key itself.
-template <int ND>
-__device__ inline bool jm_swallowed(const JobDev& J, int64_t g, int lane)
+// Whether another site swallows the site at sorted position g (see above),
+// for a group of GL lanes of the wavefront (WAVE / GL sites per wavefront;
+// lane lig of group grp; valid false for a group past the last site).  The
+// group's lanes take the bins of the search box, GL at a time, and each lane
+// reads its bin's sites two at a time so that their loads are in flight
+// together (bins hold about one site at the Johnson-Mehl bin size).  The test
+// compares squares, (d / v)^2 < (t_s - M - t_r)^2 with t_s - M - t_r > 0: its
+// rounding, a few units in the last place of the key scale, is as far below M
+// as that of the key itself.  Every lane of the wavefront calls this (the
+// loop's ballots are wavefront-wide).
+template <int ND, int GL>
+__device__ inline bool jm_swallowed(const JobDev& J, int64_t g, bool valid, int lig, int grp)
 {
-    const double4 s = J.sites[g];
+    const double4 s = valid ? J.sites[g] : make_double4(0.0, 0.0, 0.0, 0.0);
     const double sc[3] = {s.x, s.y, s.z};
     const double tmin = -from_ordered_bits(J.pbound[1]), tmax = from_ordered_bits(J.pbound[0]);
     double sumL2 = 0.0;
@@ -259,32 +264,34 @@ __device__ inline bool jm_swallowed(const JobDev& J, int64_t g, int lane)
         inside = inside && sc[a] >= 0.0 && sc[a] < J.L[a];  // invalid input (reported by the count kernel): keep
     const double tcut = s.w - M;
     const double gap = tcut - tmin;
-    if (!(inside && gap > 0.0))
-        return false;
-    const double R = gap * J.growth * (1.0 + 0x1p-20) + J.L[0] * 0x1p-30;
+    bool active = valid && inside && gap > 0.0;
     int lo[3] = {0, 0, 0}, cnt3[3] = {1, 1, 1};
-    int64_t nbox = 1;
+    int nbox = 0;
+    if (active) {
+        const double R = gap * J.growth * (1.0 + 0x1p-20) + J.L[0] * 0x1p-30;
+        int64_t nb64 = 1;
 #pragma unroll
-    for (int a = 0; a < ND; ++a) {
-        const int nb = J.nb[a];
-        const double l = floor((sc[a] - R) * J.inv_bs[a]), h = floor((sc[a] + R) * J.inv_bs[a]);
-        int la, ha;
-        if (!(h - l + 1.0 < (double)nb)) {  // the whole axis (also catches a huge R)
-            la = 0;
-            ha = nb - 1;
-        } else if (periodic) {
-            la = (int)l;  // in (-nb, 2 nb): wrapped below
-            ha = (int)h;
-        } else {
-            la = max((int)l, 0);
-            ha = min((int)h, nb - 1);
+        for (int a = 0; a < ND; ++a) {
+            const int nb = J.nb[a];
+            const double l = floor((sc[a] - R) * J.inv_bs[a]), h = floor((sc[a] + R) * J.inv_bs[a]);
+            int la, ha;
+            if (!(h - l + 1.0 < (double)nb)) {  // the whole axis (also catches a huge R)
+                la = 0;
+                ha = nb - 1;
+            } else if (periodic) {
+                la = (int)l;  // in (-nb, 2 nb): wrapped below
+                ha = (int)h;
+            } else {
+                la = max((int)l, 0);
+                ha = min((int)h, nb - 1);
+            }
+            lo[a] = la;
+            cnt3[a] = ha - la + 1;
+            nb64 *= cnt3[a];
         }
-        lo[a] = la;
-        cnt3[a] = ha - la + 1;
-        nbox *= cnt3[a];
+        active = nb64 <= kPruneMaxBins;
+        nbox = active ? (int)nb64 : 0;
     }
-    if (nbox > kPruneMaxBins)
-        return false;
     const double rg2 = J.rgrowth * J.rgrowth;
     double Lh[3], La[3];
 #pragma unroll
@@ -293,10 +300,14 @@ __device__ inline bool jm_swallowed(const JobDev& J, int64_t g, int lane)
         Lh[a] = 0.5 * J.L[a];
     }
     const int nx = cnt3[0], nxy = cnt3[0] * cnt3[1];
-    for (int e0 = 0; e0 < (int)nbox; e0 += WAVE) {
-        const int e = e0 + lane;
+    bool found = false;
+    for (int e0 = 0;; e0 += GL) {
+        const bool act = active && !found && e0 < nbox;
+        if (__ballot(act) == 0)
+            break;
+        const int e = e0 + lig;
         bool hit = false;
-        if (e < (int)nbox) {
+        if (act && e < nbox) {
             const int ez = e / nxy, rem = e - ez * nxy, ey = rem / nx, ex = rem - ey * nx;
             const int bb[3] = {lo[0] + ex, lo[1] + ey, lo[2] + ez};
             int w3[3] = {0, 0, 0};
@@ -329,48 +340,51 @@ __device__ inline bool jm_swallowed(const JobDev& J, int64_t g, int lane)
                 }
             }
         }
-        if (__ballot(hit) != 0)
-            return true;
+        const unsigned long long b = __ballot(hit);
+        if constexpr (GL == WAVE)
+            found = found || b != 0;
+        else
+            found = found || ((b >> (grp * GL)) & ((1ull << GL) - 1)) != 0;
     }
-    return false;
-}
-
-template <int ND>
-__device__ inline void jm_mark_site(const JobDev& J, int64_t g, int lane)
-{
-    const bool dead = jm_swallowed<ND>(J, g, lane);
-    if (lane == 0)
-        J.site_bin[g - J.site_begin] = dead ? 1 : 0;
+    return found;
 }
 
 // Marks (in site_bin, indexed by the job's sorted position) the sites that
-// some other site swallows.  One wavefront per site.  The job's record is
-// copied into registers once (scalar loads), so that the search loops read
-// none of its fields through memory.
+// some other site swallows: WAVE / GL sites per wavefront, GL lanes each.
+// Batches take one site per wavefront (GL = WAVE), so that a wavefront's
+// sites belong to one job and its record sits in scalar registers, copied
+// once, and the search loops read none of its fields through memory.
+template <int GL>
 __global__ __launch_bounds__(kBlock) void k_jm_mark(JobDev single, const JobDev* __restrict__ jobs, int njobs,
                                                     const int64_t* __restrict__ prefix, int64_t total)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t g = blockIdx.x * (int64_t)(kBlock / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    if (g >= total)
+    constexpr int kSites = WAVE / GL;
+    const int lane = threadIdx.x & (WAVE - 1), grp = lane / GL, lig = lane % GL;
+    const int64_t w = blockIdx.x * (int64_t)(kBlock / WAVE) + __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int64_t g0 = w * kSites;
+    if (g0 >= total)
         return;
-    if (jobs) {
-        const int j = __builtin_amdgcn_readfirstlane(find_segment(prefix, njobs, g));
-        const JobDev J = jobs[j];
-        if (J.kind != KIND_JM)
+    const int64_t g = g0 + grp;
+    const bool valid = g < total;
+    if constexpr (GL == WAVE) {
+        if (jobs) {
+            const int j = __builtin_amdgcn_readfirstlane(find_segment(prefix, njobs, g));
+            const JobDev J = jobs[j];
+            if (J.kind != KIND_JM)
+                return;
+            const bool dead = J.ndim == 3 ? jm_swallowed<3, GL>(J, g, valid, lig, grp)
+                                          : jm_swallowed<2, GL>(J, g, valid, lig, grp);
+            if (lig == 0)
+                J.site_bin[g - J.site_begin] = dead ? 1 : 0;
             return;
-        if (J.ndim == 3)
-            jm_mark_site<3>(J, g, lane);
-        else
-            jm_mark_site<2>(J, g, lane);
-    } else {
-        if (single.kind != KIND_JM)
-            return;
-        if (single.ndim == 3)
-            jm_mark_site<3>(single, g, lane);
-        else
-            jm_mark_site<2>(single, g, lane);
+        }
     }
+    if (single.kind != KIND_JM)
+        return;
+    const bool dead = single.ndim == 3 ? jm_swallowed<3, GL>(single, g, valid, lig, grp)
+                                       : jm_swallowed<2, GL>(single, g, valid, lig, grp);
+    if (valid && lig == 0)
+        single.site_bin[g - single.site_begin] = dead ? 1 : 0;
 }
 
 // Moves the live sites of each bin to the front of its range and stores their
@@ -657,8 +671,14 @@ hipError_t launch_jm_prune(const JobDev& single, const JobDev* jobs_dev, int njo
 {
     if (total_sites <= 0 || total_bins <= 0)
         return hipSuccess;
-    k_jm_mark<<<grid_for(total_sites, kBlock / WAVE), kBlock, 0, s>>>(single, jobs_dev, njobs, site_prefix_dev,
-                                                                     total_sites);
+    if (jobs_dev) {
+        k_jm_mark<WAVE><<<grid_for(total_sites, kBlock / WAVE), kBlock, 0, s>>>(single, jobs_dev, njobs,
+                                                                           site_prefix_dev, total_sites);
+    } else {
+        constexpr int kSites = WAVE / kJmLanes;  // sites per wavefront
+        k_jm_mark<kJmLanes><<<grid_for(total_sites, kBlock / WAVE * kSites), kBlock, 0, s>>>(
+            single, nullptr, 1, nullptr, total_sites);
+    }
     k_jm_compact<<<grid_for(total_bins, kBlock), kBlock, 0, s>>>(single, jobs_dev, njobs, total_bins);
     return hipGetLastError();
 }
