@@ -99,8 +99,9 @@ struct vt_ctx {
     int force_margin = 0;      // Laguerre gather margin forced by the autotuner (0: none)
     bool skip_tune = false;    // plan without the tuning table (the autotuner's default rounds)
     std::vector<TuneEntry> tune;
-    // The plain path keeps two slots of zeroed scratch (bin counts, bounds,
-    // counters) at the start of the arena: a call uses one and its count
+    // The plain and general paths keep two slots of zeroed scratch (bin
+    // counts, bounds, counters) at the start of the arena, laid out for the
+    // path that used them last (slot_owner): a call uses one and its count
     // kernel clears the other for the next call.  slot_clean[k]: bytes of
     // slot k known to be zero (0 after any other use of the arena).  Calls
     // captured into a graph use a third slot, which they clear themselves.
