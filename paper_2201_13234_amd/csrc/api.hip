@@ -1297,12 +1297,12 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     Carver c;
     const size_t o_pb = c.take<unsigned long long>(2 * (int64_t)njobs);
     const size_t o_st = c.take<int32_t>(njobs, 8);
-    const size_t o_cnt = c.take<int32_t>(total_bins, 4);
+    const size_t o_cnt = c.take<int32_t>(vt::count_words(total_bins));  // padded for the one-workgroup scan
     const size_t o_ovfc = c.take<int32_t>(ng, 4);
     const int64_t pcap = vt::scan_flags_needed(total_bins);
     const size_t o_part = c.take<unsigned long long>(pcap, 8);  // scan flags, cleared with the counts
     const size_t zero_end = c.off;
-    const size_t o_start = c.take<int32_t>(total_bins + 1);
+    const size_t o_start = c.take<int32_t>(vt::count_words(total_bins) + 1);
     const size_t o_sbin = c.take<int32_t>(total_sites);
     const size_t o_srank = c.take<int32_t>(total_sites);
     const size_t o_sites = c.take<double4>(total_sites);
@@ -1346,8 +1346,11 @@ vt_status vt_tessellate_batch(vt_ctx* ctx, const vt_job* jobs, int32_t njobs, in
     JobDev dummy;
     std::memset(&dummy, 0, sizeof dummy);
     VT_HIP(vt::launch_bin_count(dummy, djobs, njobs, dprefix, total_sites, s));
-    VT_HIP(vt::launch_scan((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins,
-                           (unsigned long long*)(base + o_part), pcap, s));
+    if (total_bins <= vt::kSmallScanMax)
+        VT_HIP(vt::launch_scan_small((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins, s));
+    else
+        VT_HIP(vt::launch_scan((int32_t*)(base + o_cnt), (int32_t*)(base + o_start), total_bins,
+                               (unsigned long long*)(base + o_part), pcap, s));
     VT_HIP(vt::launch_bin_scatter(dummy, djobs, njobs, dprefix, total_sites, s));
     VT_HIP(vt::launch_jm_prune(dummy, djobs, njobs, dprefix, total_sites, total_bins, s));
     return launch_groups(djobs, groups, (int32_t*)(base + o_ovfc),
